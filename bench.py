@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark: outer iterations/sec of the adaptively conditioned conic solver
+on the 2M-variable sparse LP (m = 500k, n = 2M, 10M nonzeros, power-law row
+degrees, row scales 10^U(-3,3)), FP32 iterate and SpMVs with FP64
+reductions, on one MI355X.
+
+A step is one outer iteration of Algorithm 2 (cone reflection, residual,
+warm-started CG projection, fused update; conditioning at l in L, a KKT check
+every `check_every` iterations).  Inputs are resident in HBM before timing.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=600)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the LP (tests only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+# ----------------------------------------------------------------------------
+# CPU baseline: the oracle on the same instance, in a child process started
+# before this process touches the GPU.
+# ----------------------------------------------------------------------------
+def cpu_child(args):
+    from oracle.alg2 import Algorithm2, default_parameters
+    from paper_2103_00736_amd import synth
+
+    p = synth.config1(scale=args.scale)
+    t, L = default_parameters(p.soc_sizes)
+    alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
+    t0 = time.perf_counter()
+    for _ in range(args.cpu_iters):
+        alg.step()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"iters": args.cpu_iters, "seconds": dt, "pcg_iters": alg.proj.cg_iters}), flush=True)
+
+
+def start_cpu_baseline(args):
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--scale", str(args.scale),
+           "--cpu-iters", str(args.cpu_iters)]
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env, cwd=ROOT)
+
+
+def finish_cpu_baseline(proc, timeout_s=600):
+    try:
+        out, err = proc.communicate(timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        return None
+    if proc.returncode != 0:
+        sys.stderr.write(err[-2000:])
+        return None
+    r = json.loads(out.strip().splitlines()[-1])
+    return {
+        "value": r["iters"] / r["seconds"], "unit": "iters/s", "cores": 1, "kind": "oracle",
+        "sample": (f"first {r['iters']} outer iteration(s) of the FP64 oracle (Algorithm 2 step by step, "
+                   f"l=1 conditioning with its two projections for d, SciPy PCG to 1e-12, "
+                   f"{r['pcg_iters']} PCG steps) on the same full-size instance; single-threaded "
+                   f"scipy.sparse SpMV, {r['seconds']:.1f} s"),
+    }
+
+
+# ----------------------------------------------------------------------------
+# algorithmic bytes per launch of the two CG kernels (value type bytes vt)
+# ----------------------------------------------------------------------------
+def kernel_bytes(m, n, nnz, vt=4):
+    # k_cg_a, rows of A_s: row_ptr, col+val, t gathered (each entry once), r q read+write, w (FP64) read+write
+    cg_a = 4 * (m + 1) + (4 + vt) * nnz + vt * n + m * (vt * 4 + 16)
+    # k_cg_t, rows of A_s^T: row_ptr, col+val, r gathered (each entry once), t_old read + t write
+    cg_t = 4 * (n + 1) + (4 + vt) * nnz + vt * m + 2 * vt * n
+    return {"cg_a": cg_a, "cg_t": cg_t}
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lp2m.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2103_00736_amd", "csrc", "acs_kernels.hip"), "rb").read()
+    if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.cpu_child:
+        cpu_child(args)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        return 2
+    cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline(args)
+
+    from paper_2103_00736_amd import acs, synth
+
+    t0 = time.perf_counter()
+    p = synth.config1(scale=args.scale)
+    gen_s = time.perf_counter() - t0
+    rc = acs.lib().acs_init(0)
+    if rc != 0:
+        raise RuntimeError(acs.lib().acs_last_error().decode())
+    prob = acs.Problem.from_synth(p)
+    st = acs.State(prob, precision=acs.PREC_MIXED)
+    st.step(args.warmup)
+    info0 = st.info()
+    cg0 = info0.cg_steps
+
+    # timed region: K outer iterations, synchronised on both sides (step() syncs on return)
+    t1 = time.perf_counter()
+    st.step(args.steps)
+    t2 = time.perf_counter()
+    info1 = st.info()
+    elapsed = t2 - t1
+    cg_timed = info1.cg_steps - cg0
+
+    # same number of steps again with HIP events around every launch on the solver's stream
+    st.profile(True)
+    cgp0 = st.info().cg_steps
+    st.step(args.steps)
+    st.profile(False)
+    cg_prof = st.info().cg_steps - cgp0
+    cls = {"update": acs.KC_UPDATE, "resid": acs.KC_RESID, "cg_t": acs.KC_CG_T, "cg_a": acs.KC_CG_A,
+           "check": acs.KC_CHECK, "cond": acs.KC_COND}
+    prof = {k: st.timing(v) for k, v in cls.items()}
+    kb = kernel_bytes(p.m, p.n, p.nnz)
+    dom = max(("cg_a", "cg_t"), key=lambda k: prof[k][1])
+    count, total_ms = prof[dom]
+    avg_ms = total_ms / max(count, 1)
+    achieved = kb[dom] * cg_prof / (total_ms * 1e-3) / 1e9  # bytes moved by the active launches / time of all
+    traffic = traffic_record(dom)
+
+    cpu = finish_cpu_baseline(cpu_proc) if cpu_proc else None
+    it_per_s = args.steps / elapsed
+    line = {
+        "metric": "iters/sec + HBM GB/s (2M-var LP); batched solves/sec, p99 latency at 1e-4 KKT",
+        "value": it_per_s,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sparse LP m={p.m} n={p.n} nnz={p.nnz}, power-law rows, row scales 1e+-3 "
+                               f"(Algorithm 2, mu=1, t=9.2, L={{300,400,...}}, iterations {args.warmup + 1}.."
+                               f"{args.warmup + args.steps})",
+                   "precision": "FP32 matrix/iterate/CG vectors, FP64 CG solution, residual sweeps and reductions"},
+        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_ms": avg_ms, "launches": count, "active_launches": cg_prof,
+                     "algorithmic_bytes_per_launch": kb[dom]},
+        "cpu_baseline": cpu,
+        "detail": {
+            "cg_steps_per_iter": cg_timed / args.steps,
+            "kkt_after": info1.kkt, "eps_p": info1.eps_p, "eps_d": info1.eps_d, "eps_gap": info1.eps_gap,
+            "pobj": info1.pobj, "p_star": p.p_star,
+            "kernel_ms": {k: {"count": v[0], "total_ms": round(v[1], 3)} for k, v in prof.items()},
+            "timed_s": elapsed, "gen_s": gen_s,
+        },
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

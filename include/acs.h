@@ -1,0 +1,189 @@
+/*
+ * acs.h - C ABI of the adaptively conditioned first-order conic solver for
+ * MI355X (gfx950).
+ *
+ * Method: Algorithm 2 of "Rapid Convergence of First-Order Numerical
+ * Algorithms via Adaptive Conditioning" (Adil, Tavakkol, Madani, arXiv
+ * 2103.00736).  It solves the primal/dual pair of Sec. II
+ *
+ *     minimise   c^T x    s.t.  A x = b,            x in K        (eq. prob_primal)
+ *     maximise   b^T y    s.t.  A^T y + z = c,      z in K        (eq. prob_dual)
+ *
+ * with K a product of Lorentz cones.  Every iteration reflects the iterate
+ * through the cone (step 16), projects onto the scaled subspace
+ * range((A O)^T) (step 17) and updates the Douglas-Rachford-type iterate s
+ * (step 18); at the iterations of the set L (plus the first) it rescales the
+ * columns of A by a diagonal O computed from the current x and z (steps 5-14).
+ *
+ * Conventions
+ *   - All functions return int: ACS_OK (0) on success, a negative ACS_ERR_*
+ *     code on failure.  acs_last_error() returns a message for the last
+ *     failure on the calling thread.  No C++ exception crosses this ABI.
+ *   - Matrices are CSR (row_ptr[m+1], col_idx[nnz], val[nnz]) with column
+ *     indices strictly ascending inside each row; nnz < 2^31.
+ *   - The cone list is [ n_orth orthant coordinates | soc_sizes[0] | ... ]:
+ *     the first n_orth coordinates of x are R_+ (Lorentz cones of size one),
+ *     followed by the second-order cones {w : w_1 >= ||w_{2:k}||_2} in list
+ *     order; n_orth + sum(soc_sizes) must equal n.
+ *   - Host pointers ("host") are read or written synchronously; the library
+ *     never keeps them.  Device pointers ("device") must be HIP allocations
+ *     on the current device.  Objects are not thread-safe unless stated.
+ *   - `stream` is a hipStream_t (NULL = the library's own stream).  All GPU
+ *     work of an object is ordered on that stream.
+ */
+#ifndef ACS_H_
+#define ACS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define ACS_OK 0
+#define ACS_PENDING 1          /* server: request not finished yet            */
+#define ACS_ERR_ARG (-1)       /* invalid argument or malformed problem        */
+#define ACS_ERR_NOMEM (-2)     /* device or host allocation failed / too big   */
+#define ACS_ERR_DEVICE (-3)    /* HIP runtime error, or no usable GPU          */
+#define ACS_ERR_NUMERIC (-4)   /* NaN/Inf in the iterates                      */
+#define ACS_ERR_STATE (-5)     /* call not valid in the object's state         */
+
+/* ---- solve status (acs_info.status) -------------------------------------- */
+#define ACS_SOLVED 0           /* KKT error <= eps_kkt at a check              */
+#define ACS_MAX_ITER 1         /* iteration limit reached, best effort result  */
+#define ACS_NUMERIC 2          /* NaN/Inf detected, iteration stopped          */
+#define ACS_CANCELLED 3        /* server request cancelled                     */
+
+/* ---- arithmetic ---------------------------------------------------------- */
+#define ACS_PREC_MIXED 0  /* FP32 matrix values, iterate and CG vectors;
+                             FP64 CG solution, residual accumulation,
+                             reductions, scaling factors                   */
+#define ACS_PREC_FP64 1   /* everything in FP64                            */
+
+/*
+ * Settings (Alg. 2 Require line and Sec. V).  Call acs_settings_default()
+ * first.  Conditioning set L = {l_first, l_first + l_every, ...} up to l_last
+ * (inclusive; -1 = unbounded); l_first = 0 means L is empty (Algorithm 1),
+ * l_every = 0 means L = {l_first}.  Iteration 1 always conditions.
+ * With `auto_params` = 1 the library picks the paper's per-class values:
+ * LP: t = 9.2, L = {300, 400, ...}; SOCP: t = 1.7, L = {200, 300, ...}; mu = 1.
+ */
+typedef struct acs_settings {
+  double mu;            /* proximal parameter mu > 0                            */
+  double t;             /* cap on log(max O) - log(min O), t > 0 (step 11)      */
+  int32_t l_first;      /* first conditioning iteration after l = 1             */
+  int32_t l_every;      /* period of L                                          */
+  int32_t l_last;       /* last member of L, -1 = none                          */
+  int32_t auto_params;  /* 1: choose t and L from the problem class             */
+  int32_t max_iter;     /* outer-iteration limit                                */
+  int32_t check_every;  /* KKT evaluation period (iterations)                   */
+  double eps_kkt;       /* stop when max(eps_p, eps_d, eps_gap, eps_cone) <= it */
+  int32_t precision;    /* ACS_PREC_MIXED or ACS_PREC_FP64                      */
+  int32_t cg_max;       /* CG steps per outer iteration, at most                */
+  double cg_reduce;     /* stop CG once ||r|| <= cg_reduce * ||r_0|| (warm)     */
+  double cg_abs;        /* ... or once ||r|| <= cg_abs (scaled system)          */
+  int32_t verbose;      /* 0 quiet, 1 one line per check on stderr              */
+  int32_t reserved[7];
+} acs_settings;
+
+/* Per-solve report.  KKT errors follow the oracle's definition:
+ *   eps_p = ||Ax-b||/(1+||b||), eps_d = ||A^T y+z-c||/(1+||c||),
+ *   eps_gap = |c^T x - b^T y|/(1+|c^T x|+|b^T y|),
+ *   eps_cone = max(dist(x,K), dist(z,K))/(1+max(||x||,||z||)).         */
+typedef struct acs_info {
+  int32_t status;       /* ACS_SOLVED / ACS_MAX_ITER / ACS_NUMERIC / ACS_CANCELLED */
+  int32_t iterations;   /* outer iterations run                                */
+  int64_t cg_steps;     /* total CG steps                                      */
+  int32_t conditionings;/* conditioning events run                             */
+  int32_t reserved0;
+  double eps_p, eps_d, eps_gap, eps_cone, kkt;
+  double pobj, dobj;    /* c^T x and b^T y                                     */
+  double solve_ms;      /* wall time of the iteration loop                     */
+  double setup_ms;      /* upload + setup                                      */
+  double alpha;         /* exponent of the last conditioning (step 11)         */
+  double o_range;       /* log(max O) - log(min O) after the last conditioning */
+  double reserved[6];
+} acs_info;
+
+typedef struct acs_problem acs_problem;
+typedef struct acs_state acs_state;
+
+/* Library and device. */
+const char* acs_version(void);
+const char* acs_last_error(void);
+/* Initialise HIP on `device` (ordinal); returns ACS_ERR_DEVICE when no gfx950 GPU is usable. */
+int acs_init(int32_t device);
+
+void acs_settings_default(acs_settings* s);
+
+/*
+ * Problem (Sec. II).  Inputs are host arrays and are COPIED; the caller may
+ * free them on return.  Validation: m, n >= 1; row_ptr[0] = 0, nondecreasing,
+ * row_ptr[m] = nnz; 0 <= col < n, strictly ascending in a row; finite val,
+ * b, c; n_orth >= 0, soc sizes >= 1, n_orth + sum(soc) = n.  Failure:
+ * ACS_ERR_ARG and *out = NULL.  Pure host code: valid without a GPU.
+ */
+int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                       const double* val, const double* b, const double* c, int32_t n_orth, int32_t n_soc,
+                       const int32_t* soc_sizes, acs_problem** out);
+void acs_problem_destroy(acs_problem* p);
+/* Device bytes a solve of `p` in `precision` allocates (for budgeting). */
+int64_t acs_problem_device_bytes(const acs_problem* p, int32_t precision);
+
+/*
+ * One-shot solve (Alg. 2 until KKT <= eps_kkt or max_iter).  x, z (length n)
+ * and y (length m) are caller-allocated HOST buffers (any may be NULL).
+ * y is the multiplier -w/mu of the scaled dual (Sec. IV).  info may be NULL.
+ */
+int acs_solve(const acs_problem* p, const acs_settings* s, double* x, double* y, double* z, acs_info* info,
+              void* stream);
+
+/*
+ * Solver state on the GPU (resident iterate and scalings; tests, benchmarks
+ * and checkpoint/resume).  The state after l iterations is (l, s_prev, s, O, w):
+ * s = s^{l+1}-to-be input of iteration l+1, s_prev the iterate before it, O the
+ * current column scaling (positive, constant on every cone), w the unscaled
+ * CG solution (y = -w/mu).  x and z of steps 19-20 are
+ * x = O (abs_K(s_prev) + s) / 2 and z = (abs_K(s_prev) - s) / (2 mu O).
+ * acs_state_create uploads the problem and sets the initial state l = 0,
+ * x = z = e_K (s_prev = (1+mu) e_K, s = (1-mu) e_K, O = 1, w = 0).
+ */
+int acs_state_create(const acs_problem* p, const acs_settings* s, void* stream, acs_state** out);
+void acs_state_destroy(acs_state* st);
+/* Host arrays: s_prev, s, O (n), w (m).  O must be positive and constant per cone. */
+int acs_state_set(acs_state* st, int32_t l, const double* s_prev, const double* s, const double* O, const double* w);
+/* Runs exactly `iters` outer iterations (conditioning and checks per settings). */
+int acs_state_step(acs_state* st, int32_t iters);
+/* Runs until KKT <= eps_kkt at a check or `max_iter` total iterations. */
+int acs_state_solve(acs_state* st, acs_info* info);
+/* Host outputs, any may be NULL: s_prev, s, O, x, z (n); w, y (m).  Synchronises. */
+int acs_state_get(acs_state* st, int32_t* l, double* s_prev, double* s, double* O, double* w, double* x,
+                  double* y, double* z);
+int acs_state_info(acs_state* st, acs_info* info);
+/* KKT errors of the current state (runs the check kernels), fills info. */
+int acs_state_check(acs_state* st, acs_info* info);
+
+/*
+ * Kernel-level entry points (device pointers, library stream of `st`), used
+ * by tests and the benchmark's roofline measurement.
+ *   which = 0: y = A_s x   (rows of the scaled matrix, FP32/FP64 per precision)
+ *   which = 1: y = A_s^T x (rows of the scaled transpose)
+ * where A_s = diag(d) A O is the state's current scaled matrix.  x and y are
+ * device arrays of the state's value type (float in MIXED, double in FP64).
+ * `reps` launches are timed with HIP events on the state's stream; *avg_ms
+ * receives the mean duration per launch (may be NULL).
+ */
+int acs_state_spmv(acs_state* st, int32_t which, const void* x, void* y, int32_t reps, double* avg_ms);
+/* Per-kernel-class event timing over subsequent acs_state_step calls.
+ * enable = 1 starts, 0 stops; acs_state_timing reads {count, total_ms} for
+ * class k (0 = update/A^T, 1 = residual/A, 2 = CG A^T, 3 = CG A, 4 = cone,
+ * 5 = check, 6 = conditioning). */
+int acs_state_profile(acs_state* st, int32_t enable);
+int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACS_H_ */

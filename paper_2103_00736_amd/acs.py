@@ -1,0 +1,259 @@
+"""ctypes binding of libacs.so (include/acs.h): argument marshalling only.
+
+Every step of the solver runs in the library's HIP kernels.  If the shared
+library is missing this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libacs.so")
+
+ACS_OK = 0
+ACS_PENDING = 1
+ACS_ERR_ARG = -1
+ACS_ERR_NOMEM = -2
+ACS_ERR_DEVICE = -3
+ACS_ERR_NUMERIC = -4
+ACS_ERR_STATE = -5
+
+SOLVED, MAX_ITER, NUMERIC, CANCELLED = 0, 1, 2, 3
+PREC_MIXED, PREC_FP64 = 0, 1
+
+# timing classes of acs_state_timing
+KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND = range(7)
+
+EXPORTED = [
+    "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
+    "acs_problem_destroy", "acs_problem_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
+    "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
+    "acs_state_spmv", "acs_state_profile", "acs_state_timing",
+]
+
+
+class AcsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"acs error {code}: {msg}")
+        self.code = code
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [
+        ("mu", ctypes.c_double), ("t", ctypes.c_double),
+        ("l_first", ctypes.c_int32), ("l_every", ctypes.c_int32), ("l_last", ctypes.c_int32),
+        ("auto_params", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("eps_kkt", ctypes.c_double), ("precision", ctypes.c_int32), ("cg_max", ctypes.c_int32),
+        ("cg_reduce", ctypes.c_double), ("cg_abs", ctypes.c_double), ("verbose", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("cg_steps", ctypes.c_int64),
+        ("conditionings", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("eps_p", ctypes.c_double), ("eps_d", ctypes.c_double), ("eps_gap", ctypes.c_double),
+        ("eps_cone", ctypes.c_double), ("kkt", ctypes.c_double), ("pobj", ctypes.c_double),
+        ("dobj", ctypes.c_double), ("solve_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
+        ("alpha", ctypes.c_double), ("o_range", ctypes.c_double), ("reserved", ctypes.c_double * 6),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+_lib = None
+P = ctypes.c_void_p
+DP = ctypes.POINTER(ctypes.c_double)
+I32P = ctypes.POINTER(ctypes.c_int32)
+I64P = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_00736_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "acs_version": (ctypes.c_char_p, []),
+        "acs_last_error": (ctypes.c_char_p, []),
+        "acs_init": (ctypes.c_int, [ctypes.c_int32]),
+        "acs_settings_default": (None, [ctypes.POINTER(Settings)]),
+        "acs_problem_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, I64P, I32P, DP, DP, DP,
+                                              ctypes.c_int32, ctypes.c_int32, I32P, ctypes.POINTER(P)]),
+        "acs_problem_destroy": (None, [P]),
+        "acs_problem_device_bytes": (ctypes.c_int64, [P, ctypes.c_int32]),
+        "acs_solve": (ctypes.c_int, [P, ctypes.POINTER(Settings), DP, DP, DP, ctypes.POINTER(Info), P]),
+        "acs_state_create": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, ctypes.POINTER(P)]),
+        "acs_state_destroy": (None, [P]),
+        "acs_state_set": (ctypes.c_int, [P, ctypes.c_int32, DP, DP, DP, DP]),
+        "acs_state_step": (ctypes.c_int, [P, ctypes.c_int32]),
+        "acs_state_solve": (ctypes.c_int, [P, ctypes.POINTER(Info)]),
+        "acs_state_get": (ctypes.c_int, [P, I32P, DP, DP, DP, DP, DP, DP, DP]),
+        "acs_state_info": (ctypes.c_int, [P, ctypes.POINTER(Info)]),
+        "acs_state_check": (ctypes.c_int, [P, ctypes.POINTER(Info)]),
+        "acs_state_spmv": (ctypes.c_int, [P, ctypes.c_int32, P, P, ctypes.c_int32, DP]),
+        "acs_state_profile": (ctypes.c_int, [P, ctypes.c_int32]),
+        "acs_state_timing": (ctypes.c_int, [P, ctypes.c_int32, I64P, DP]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        msg = lib().acs_last_error().decode(errors="replace")
+        raise AcsError(rc, msg)
+    return rc
+
+
+def _dptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(DP)
+
+
+def default_settings(**kw) -> Settings:
+    s = Settings()
+    lib().acs_settings_default(ctypes.byref(s))
+    for k, v in kw.items():
+        if not hasattr(s, k):
+            raise KeyError(f"unknown setting {k}")
+        setattr(s, k, v)
+    return s
+
+
+def version() -> str:
+    return lib().acs_version().decode()
+
+
+class Problem:
+    """Host copy of (A, b, c, K) inside the library (acs_problem)."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=()):
+        self._keep = (
+            np.ascontiguousarray(row_ptr, dtype=np.int64), np.ascontiguousarray(col_idx, dtype=np.int32),
+            np.ascontiguousarray(val, dtype=np.float64), np.ascontiguousarray(b, dtype=np.float64),
+            np.ascontiguousarray(c, dtype=np.float64), np.ascontiguousarray(soc_sizes, dtype=np.int32),
+        )
+        rp, ci, v, bb, cc, ss = self._keep
+        self.m, self.n = int(m), int(n)
+        self.n_orth = int(n_orth)
+        self.soc_sizes = ss
+        if len(ci) != len(v):
+            raise AcsError(ACS_ERR_ARG, "col_idx and val differ in length")
+        if len(rp) != self.m + 1:
+            raise AcsError(ACS_ERR_ARG, "row_ptr must have m+1 entries")
+        h = P()
+        _check(lib().acs_problem_create(self.m, self.n, len(ci), rp.ctypes.data_as(I64P),
+                                        ci.ctypes.data_as(I32P), v.ctypes.data_as(DP), bb.ctypes.data_as(DP),
+                                        cc.ctypes.data_as(DP), self.n_orth, len(ss), ss.ctypes.data_as(I32P),
+                                        ctypes.byref(h)))
+        self.handle = h
+        self._keep = None  # the library copied everything
+
+    @classmethod
+    def from_synth(cls, p) -> "Problem":
+        return cls(p.m, p.n, p.row_ptr, p.col_idx, p.val, p.b, p.c, p.n_orth, p.soc_sizes)
+
+    def device_bytes(self, precision: int = PREC_MIXED) -> int:
+        return int(lib().acs_problem_device_bytes(self.handle, precision))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().acs_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """Resident solver state on the GPU (acs_state)."""
+
+    def __init__(self, problem: Problem, settings: Optional[Settings] = None, stream: int = 0, **kw):
+        if settings is None:
+            settings = default_settings(**kw)
+        self.problem = problem
+        self.settings = settings
+        h = P()
+        _check(lib().acs_state_create(problem.handle, ctypes.byref(settings), P(stream or None), ctypes.byref(h)))
+        self.handle = h
+
+    def set(self, l: int, s_prev, s, O, w):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (s_prev, s, O, w)]
+        _check(lib().acs_state_set(self.handle, int(l), *[_dptr(a) for a in arrs]))
+
+    def step(self, iters: int):
+        _check(lib().acs_state_step(self.handle, int(iters)))
+
+    def solve(self) -> Info:
+        info = Info()
+        _check(lib().acs_state_solve(self.handle, ctypes.byref(info)))
+        return info
+
+    def info(self) -> Info:
+        info = Info()
+        _check(lib().acs_state_info(self.handle, ctypes.byref(info)))
+        return info
+
+    def get(self, xyz: bool = True) -> dict:
+        m, n = self.problem.m, self.problem.n
+        out = {k: np.empty(n) for k in ("s_prev", "s", "O")}
+        out["w"] = np.empty(m)
+        if xyz:
+            out["x"], out["z"], out["y"] = np.empty(n), np.empty(n), np.empty(m)
+        l = ctypes.c_int32()
+        _check(lib().acs_state_get(self.handle, ctypes.byref(l), _dptr(out["s_prev"]), _dptr(out["s"]),
+                                   _dptr(out["O"]), _dptr(out["w"]), _dptr(out.get("x")), _dptr(out.get("y")),
+                                   _dptr(out.get("z"))))
+        out["l"] = int(l.value)
+        return out
+
+    def spmv(self, which: int, x_ptr: int, y_ptr: int, reps: int = 1) -> float:
+        ms = ctypes.c_double()
+        _check(lib().acs_state_spmv(self.handle, int(which), P(x_ptr), P(y_ptr), int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def profile(self, enable: bool):
+        _check(lib().acs_state_profile(self.handle, 1 if enable else 0))
+
+    def timing(self, cls: int) -> Tuple[int, float]:
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(lib().acs_state_timing(self.handle, int(cls), ctypes.byref(cnt), ctypes.byref(ms)))
+        return int(cnt.value), float(ms.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().acs_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(problem: Problem, settings: Optional[Settings] = None, stream: int = 0, **kw):
+    """One-shot solve; returns (x, y, z, info)."""
+    if settings is None:
+        settings = default_settings(**kw)
+    x, z, y = np.empty(problem.n), np.empty(problem.n), np.empty(problem.m)
+    info = Info()
+    _check(lib().acs_solve(problem.handle, ctypes.byref(settings), _dptr(x), _dptr(y), _dptr(z), ctypes.byref(info),
+                           P(stream or None)))
+    return x, y, z, info

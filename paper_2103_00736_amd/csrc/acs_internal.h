@@ -1,0 +1,54 @@
+// Internal types shared by the host code and the HIP kernels of libacs.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/acs.h"
+
+namespace acs {
+
+// Row range [r0, r1) of a CSR matrix processed by one workgroup.  A range
+// holds at most kStageNnz nonzeros, unless it is a single longer row.
+struct RowBlock {
+  int32_t r0;
+  int32_t r1;
+};
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kStageNnz = 2048;   // products staged in LDS per multi-row block
+
+// Host copy of a validated problem (Sec. II): CSR of A, b, c, cone list.
+struct Problem {
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> row_ptr;  // m+1
+  std::vector<int32_t> col;      // nnz
+  std::vector<double> val;       // nnz
+  std::vector<double> b, c;
+  int32_t n_orth = 0;
+  std::vector<int32_t> soc_size;  // sizes of the Lorentz cones after the orthant block
+  std::vector<int32_t> soc_off;   // n_soc+1 absolute offsets, soc_off[0] = n_orth
+  // pattern of A^T (CSR over columns of A): t_row_ptr (n+1), t_col (row of A), t_perm (index into val)
+  std::vector<int32_t> t_row_ptr, t_col, t_perm;
+  std::vector<RowBlock> a_blocks, t_blocks;
+  double bnorm = 0, cnorm = 0;
+  int32_t max_soc = 0;
+  bool is_socp() const { return !soc_size.empty(); }
+};
+
+// Validates and copies a problem; on failure returns false and sets err.
+bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                   const double* val, const double* b, const double* c, int32_t n_orth, int32_t n_soc,
+                   const int32_t* soc_sizes, Problem* out, std::string* err);
+
+// Partition rows of a CSR into RowBlocks (LDS-staged multi-row blocks of at
+// most `stage` nonzeros; a longer row gets a block of its own).  Long-row
+// blocks are placed first so they start early.
+std::vector<RowBlock> make_row_blocks(const int32_t* row_ptr, int32_t rows, int32_t stage);
+
+// Error reporting (thread-local message).
+void set_error(const std::string& msg);
+
+}  // namespace acs

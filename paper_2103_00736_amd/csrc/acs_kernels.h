@@ -1,0 +1,123 @@
+// HIP kernels of one Algorithm-2 instance on gfx950 (wave64).
+//
+// Scaled quantities kept on the device (O: column scaling of Alg. 2 step 11;
+// d_i = 1/sqrt(sum_j a_ij^2 O_j^2), the row normalisation that makes the
+// normal matrix unit-diagonal):
+//   A_s = diag(d) A O   (values in CSR of A and, transposed, in CSR of A^T)
+//   b_s = diag(d) b,    chat = mu O c
+// range(A_s^T) = range((A O)^T), so the projection of step 17 is unchanged by
+// the row normalisation.  One iteration (steps 16-20) is evaluated as
+//   p  = abs_K(s)
+//   w  : (A_s A_s^T) w = A_s (p - chat) - b_s           (CG, warm started)
+//   s+ = (s + p)/2 - chat - A_s^T w
+//   x  = O (p + s+)/2,  z = (p - s+)/(2 mu O),  y = -diag(d) w / mu
+// which equals the listing's r = abs_{A_hat}(p), s+ = s/2 - r/2 + d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "acs_internal.h"
+
+namespace acs {
+
+// Device control block of one instance (CG scalars, reductions, flags).
+struct Ctl {
+  double rho;     // ||r||^2 of the current CG residual
+  double rho0;    // ||r_0||^2 of this outer iteration
+  double tol2;    // CG stops when rho <= tol2
+  double alpha;   // CG step length
+  double beta;    // CG direction update (0 = fresh start)
+  int32_t k;      // CG steps taken in this outer iteration
+  int32_t done;   // CG finished for this outer iteration
+  int32_t cg_max;
+  int32_t iter;   // outer iteration the CG belongs to
+  long long cg_total;
+  double upd[8];  // reductions of the update kernel
+  double cone[4]; // reductions of the cone kernel
+  double cond[4]; // conditioning: min log o, -max log o, -any valid, alpha
+  double kkt[8];  // eps_p, eps_d, eps_gap, eps_cone, kkt, pobj, dobj, ds2
+  unsigned int counter;
+  unsigned int pad;
+};
+
+// Host-visible status written by kernels into pinned, mapped host memory.
+struct HostStatus {
+  long long launch_seq;  // id of the last finished CG-A launch
+  int32_t cg_done_iter;  // last outer iteration whose CG finished
+  int32_t check_iter;    // last iteration whose KKT check finished
+  double kkt[8];         // copy of Ctl::kkt of check_iter
+  long long cg_total;
+  int32_t numeric;       // NaN/Inf seen
+  int32_t pad;
+};
+
+template <typename VT>
+struct Dev {
+  int32_t m, n, n_orth, n_soc;
+  double mu;
+  // CSR of A (rows i) and of A^T (rows j); *_val hold A_s, a_orig the problem's values
+  const int32_t* a_rp;
+  const int32_t* a_col;
+  VT* a_val;
+  const double* a_orig;
+  const int32_t* t_rp;
+  const int32_t* t_col;
+  VT* t_val;
+  const int32_t* t_perm;
+  // FP64 copies of A_s for the once-per-iteration residual / update / check
+  // sweeps (iterative refinement of the FP32 CG); alias *_val when VT = double
+  double* a_val64;
+  double* t_val64;
+  const RowBlock* a_blk;
+  int32_t a_nblk;
+  const RowBlock* t_blk;
+  int32_t t_nblk;
+  const int32_t* soc_off;  // n_soc + 1 absolute offsets
+  const double* b;
+  const double* c;
+  // scaling
+  double* O;
+  double* chat;
+  double* dsq;
+  double* dinv;
+  double* bs;
+  // iterate and CG
+  VT* p;     // abs_K(s) on SOC coordinates (orthant ones are recomputed)
+  VT* v;     // p - chat - A_s^T w : the CG right-hand side before A_s
+  double* zt;  // chat + A_s^T w on SOC coordinates
+  double* w;
+  VT* r;
+  VT* q;
+  VT* t;
+  // outputs
+  double* xout;
+  double* zout;
+  double* yout;
+  double* xhat;
+  double* xc;
+  double* zc;
+  double* ounit;
+  Ctl* ctl;
+  double* partials;
+  HostStatus* hs;
+};
+
+enum UpdMode { UPD_PROLOGUE = 0, UPD_UPDATE = 1, UPD_UPDATE_ONLY = 2 };
+
+// Launchers (all on `st`); grid sizes derive from the row-block counts.
+template <typename VT> void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool check,
+                                          hipStream_t st);
+template <typename VT> void launch_cone(const Dev<VT>& d, const VT* s, bool check, bool next, int group,
+                                        hipStream_t st);
+template <typename VT> void launch_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st);
+template <typename VT> void launch_cg_t(const Dev<VT>& d, hipStream_t st);
+template <typename VT> void launch_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st);
+template <typename VT> void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st);
+template <typename VT> void launch_cond_ratio(const Dev<VT>& d, const VT* s_prev, const VT* s_cur, double t_cap,
+                                              hipStream_t st);
+template <typename VT> void launch_cond_scale(const Dev<VT>& d, VT* s_cur, hipStream_t st);
+template <typename VT> void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st);
+template <typename VT> void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st);
+template <typename VT> void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st);
+
+}  // namespace acs

@@ -1,0 +1,821 @@
+// HIP kernels for gfx950: one generic LDS-staged CSR row-block engine and the
+// steps of Algorithm 2 built on it (see acs_kernels.h for the scaled form).
+//
+// Every kernel that sweeps a matrix processes one RowBlock per workgroup:
+// products val[k] * x[col[k]] of the block's rows are staged in LDS with
+// coalesced loads, then each row is summed by a group of G lanes (G adapts
+// to the rows per block: 1 lane for very short rows, up to a wave64 per
+// row) with a wavefront-shuffle reduction; a row longer than the stage gets
+// a whole workgroup.  Row sums feed a per-kernel epilogue (the fused vector
+// update of that step).  Grid-wide FP64 reductions are deterministic: each
+// workgroup writes a partial, the last workgroup to arrive sums them in
+// fixed order.  Workgroup ids are remapped so that each of the 8 XCDs gets a
+// contiguous range of row blocks.
+#include <cmath>
+
+#include "acs_kernels.h"
+
+namespace acs {
+
+// ----------------------------------------------------------------------------
+// helpers
+// ----------------------------------------------------------------------------
+
+// Hardware places workgroup b on XCD b % 8; hand XCD x a contiguous range.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + (x < rem ? x : rem) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void host_store(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Per-block partial sums (N values) -> partials[blk * N + i].
+template <int N, bool MIN = false>
+__device__ __forceinline__ void block_store_partials(double (&acc)[N], double* partials, int blk) {
+  __shared__ double sh[kBlock / 64][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc[i] = MIN ? wave_min(acc[i]) : wave_sum(acc[i]);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh[w][i] = acc[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = sh[0][threadIdx.x];
+    for (int k = 1; k < kBlock / 64; ++k) s = MIN ? fmin(s, sh[k][threadIdx.x]) : s + sh[k][threadIdx.x];
+    partials[size_t(blk) * N + threadIdx.x] = s;
+  }
+}
+
+// True in the last workgroup to finish; its loads after this see every partial.
+__device__ __forceinline__ bool arrive_last(unsigned int* counter, unsigned int nb) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int tk = atomicAdd(counter, 1u);
+    is_last = (tk == nb - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last != 0;
+}
+
+// Sum (or min) of the partials of nb workgroups, in fixed order; result on all threads.
+template <int N, bool MIN = false>
+__device__ __forceinline__ void final_reduce(const double* partials, int nb, double (&out)[N]) {
+  __shared__ double sh[kBlock / 64][N];
+  double acc[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc[i] = MIN ? INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double v = __hip_atomic_load(partials + size_t(b) * N + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      acc[i] = MIN ? fmin(acc[i], v) : acc[i] + v;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc[i] = MIN ? wave_min(acc[i]) : wave_sum(acc[i]);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh[w][i] = acc[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = sh[0][i];
+    for (int k = 1; k < kBlock / 64; ++k) s = MIN ? fmin(s, sh[k][i]) : s + sh[k][i];
+    out[i] = s;
+  }
+}
+
+// Sum over each row of prod(k) for the rows of one RowBlock; epi(row, sum)
+// runs on one lane per row.  All threads of the workgroup must call it.
+template <typename Acc, class Prod, class Epi>
+__device__ __forceinline__ void rows_block(const int32_t* __restrict__ rp, RowBlock rb, Prod& prod, Epi& epi) {
+  __shared__ Acc lds[kStageNnz];
+  __shared__ Acc red[kBlock / 64];
+  const int tid = threadIdx.x;
+  const int r0 = rb.r0, r1 = rb.r1;
+  const int k0 = rp[r0], k1 = rp[r1];
+  if (k1 - k0 > kStageNnz) {  // a single long row: the whole workgroup
+    Acc s = 0;
+    for (int k = k0 + tid; k < k1; k += kBlock) s += prod(k);
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+      Acc tot = red[0];
+      for (int i = 1; i < kBlock / 64; ++i) tot += red[i];
+      epi(r0, tot);
+    }
+    return;
+  }
+#pragma unroll
+  for (int it = 0; it < kStageNnz / kBlock; ++it) {
+    const int k = k0 + it * kBlock + tid;
+    if (k < k1) lds[k - k0] = prod(k);
+  }
+  __syncthreads();
+  const int nrows = r1 - r0;
+  int G = 64;
+  while (G > 1 && G * nrows > kBlock) G >>= 1;
+  const int grp = tid / G, lane = tid & (G - 1), ngrp = kBlock / G;
+  for (int r = r0 + grp; r < r1; r += ngrp) {
+    const int a = rp[r] - k0, e = rp[r + 1] - k0;
+    Acc s = 0;
+    for (int k = a + lane; k < e; k += G) s += lds[k];
+    for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) epi(r, s);
+  }
+}
+
+// f(row, k) for every nonzero k of the block's rows.
+template <class F>
+__device__ __forceinline__ void rows_foreach(const int32_t* __restrict__ rp, RowBlock rb, F& f) {
+  const int tid = threadIdx.x;
+  const int r0 = rb.r0, r1 = rb.r1;
+  const int k0 = rp[r0], k1 = rp[r1];
+  if (r1 - r0 == 1) {
+    for (int k = k0 + tid; k < k1; k += kBlock) f(r0, k);
+    return;
+  }
+  const int nrows = r1 - r0;
+  int G = 64;
+  while (G > 1 && G * nrows > kBlock) G >>= 1;
+  const int grp = tid / G, lane = tid & (G - 1), ngrp = kBlock / G;
+  for (int r = r0 + grp; r < r1; r += ngrp) {
+    const int e = rp[r + 1];
+    for (int k = rp[r] + lane; k < e; k += G) f(r, k);
+  }
+}
+
+__device__ __forceinline__ double lorentz_dist2(double u0, double nb) {
+  if (nb <= u0) return 0.0;
+  if (nb <= -u0) return u0 * u0 + nb * nb;
+  const double g = nb - u0;
+  return 0.5 * g * g;
+}
+
+// ----------------------------------------------------------------------------
+// step 18 (+19-20 on checks, +16 of the next iteration): rows j of A_s^T
+// ----------------------------------------------------------------------------
+template <typename VT, int MODE, bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restrict__ s_cur, VT* __restrict__ s_new) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.t_blk[blk];
+  const double* __restrict__ tv = d.t_val64;
+  const int32_t* __restrict__ tc = d.t_col;
+  const double* __restrict__ w = d.w;
+  auto prod = [&](int k) -> double { return tv[k] * w[tc[k]]; };
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  const double mu = d.mu;
+  auto epi = [&](int j, double u) {
+    const double zt = d.chat[j] + u;  // mu * (O z) implied by w
+    const double s = double(s_cur[j]);
+    const bool orth = j < d.n_orth;
+    double sn = s;
+    if (MODE != UPD_PROLOGUE) {
+      const double pj = orth ? fabs(s) : double(d.p[j]);
+      const VT snv = VT(0.5 * (s + pj) - zt);
+      s_new[j] = snv;
+      sn = double(snv);
+      acc[0] += (sn - s) * (sn - s);
+      if (CHECK) {
+        const double Oj = d.O[j];
+        const double xh = 0.5 * (pj + sn);
+        const double x = Oj * xh;
+        const double z = 0.5 * (pj - sn) / (mu * Oj);
+        d.xout[j] = x;
+        d.zout[j] = z;
+        d.xhat[j] = xh;
+        acc[1] += d.c[j] * x;
+        acc[2] += x * x;
+        acc[3] += z * z;
+        if (orth) {
+          const double mx = fmin(x, 0.0), mz = fmin(z, 0.0);
+          acc[4] += mx * mx;
+          acc[5] += mz * mz;
+        }
+        const double dr = (pj - sn - 2.0 * zt) / (2.0 * mu * Oj);  // (A^T y + z - c)_j
+        acc[6] += dr * dr;
+      }
+    }
+    if (MODE != UPD_UPDATE_ONLY) {
+      if (orth)
+        d.v[j] = VT(fabs(sn) - zt);
+      else
+        d.zt[j] = zt;
+    }
+  };
+  rows_block<double>(d.t_rp, rb, prod, epi);
+  if (MODE != UPD_PROLOGUE) {
+    block_store_partials<7>(acc, d.partials, blk);
+    if (arrive_last(&d.ctl->counter, gridDim.x)) {
+      double tot[7];
+      final_reduce<7>(d.partials, gridDim.x, tot);
+      if (threadIdx.x == 0) {
+        for (int i = 0; i < 7; ++i) d.ctl->upd[i] = tot[i];
+        d.ctl->counter = 0;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// step 16 on the Lorentz cones: one group of G lanes per cone
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_cone(Dev<VT> d, const VT* __restrict__ s, int check, int next, int G) {
+  const int gpb = kBlock / G;
+  const int grp = threadIdx.x / G, lane = threadIdx.x & (G - 1);
+  const int cone = blockIdx.x * gpb + grp;
+  double acc[2] = {0, 0};
+  if (cone < d.n_soc) {
+    const int off = d.soc_off[cone], end = d.soc_off[cone + 1];
+    if (check) {
+      double nx = 0, nz = 0;
+      for (int e = off + 1 + lane; e < end; e += G) {
+        const double xe = d.xout[e], ze = d.zout[e];
+        nx += xe * xe;
+        nz += ze * ze;
+      }
+      for (int o = G >> 1; o > 0; o >>= 1) {
+        nx += __shfl_xor(nx, o);
+        nz += __shfl_xor(nz, o);
+      }
+      if (lane == 0) {
+        acc[0] = lorentz_dist2(d.xout[off], sqrt(nx));
+        acc[1] = lorentz_dist2(d.zout[off], sqrt(nz));
+      }
+    }
+    if (next) {
+      double n2 = 0;
+      for (int e = off + 1 + lane; e < end; e += G) {
+        const double se = double(s[e]);
+        n2 += se * se;
+      }
+      for (int o = G >> 1; o > 0; o >>= 1) n2 += __shfl_xor(n2, o);
+      const double s0 = double(s[off]);
+      const double nv = sqrt(n2);
+      double a0, f;  // proj = (a0, f * s_bar)
+      if (nv <= s0) {
+        a0 = s0;
+        f = 1.0;
+      } else if (nv <= -s0) {
+        a0 = 0.0;
+        f = 0.0;
+      } else {
+        const double a = 0.5 * (s0 + nv);
+        a0 = a;
+        f = a / nv;
+      }
+      for (int e = off + lane; e < end; e += G) {
+        const double se = double(s[e]);
+        const double pr = (e == off) ? a0 : f * se;
+        const VT pv = VT(2.0 * pr - se);
+        d.p[e] = pv;
+        d.v[e] = VT(double(pv) - d.zt[e]);
+      }
+    }
+  }
+  if (check) {
+    block_store_partials<2>(acc, d.partials, blockIdx.x);
+    if (arrive_last(&d.ctl->counter, gridDim.x)) {
+      double tot[2];
+      final_reduce<2>(d.partials, gridDim.x, tot);
+      if (threadIdx.x == 0) {
+        d.ctl->cone[0] = tot[0];
+        d.ctl->cone[1] = tot[1];
+        d.ctl->counter = 0;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// CG start: r = A_s v - b_s (rows i of A_s), FP64 accumulation
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_resid(Dev<VT> d, int iter, double red2, double abs2) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.a_blk[blk];
+  const double* __restrict__ av = d.a_val64;
+  const int32_t* __restrict__ ac = d.a_col;
+  const VT* __restrict__ v = d.v;
+  auto prod = [&](int k) -> double { return av[k] * double(v[ac[k]]); };
+  double acc[1] = {0};
+  auto epi = [&](int i, double sum) {
+    const VT ri = VT(sum - d.bs[i]);
+    d.r[i] = ri;
+    acc[0] += double(ri) * double(ri);
+  };
+  rows_block<double>(d.a_rp, rb, prod, epi);
+  block_store_partials<1>(acc, d.partials, blk);
+  if (arrive_last(&d.ctl->counter, gridDim.x)) {
+    double tot[1];
+    final_reduce<1>(d.partials, gridDim.x, tot);
+    if (threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      const double rho = tot[0];
+      c->rho = rho;
+      c->rho0 = rho;
+      c->tol2 = fmax(red2 * rho, abs2);
+      c->alpha = 0.0;
+      c->beta = 0.0;
+      c->k = 0;
+      c->iter = iter;
+      const bool bad = !(rho == rho) || isinf(rho);
+      const int done = (bad || rho <= c->tol2 || c->cg_max <= 0) ? 1 : 0;
+      c->done = done;
+      c->counter = 0;
+      if (bad) host_store(&d.hs->numeric, 1);
+      if (done) host_store(&d.hs->cg_done_iter, iter);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// CG, first half: t = A_s^T q with q = r + beta q_old, kept as the recurrence
+// t = A_s^T r + beta t_old (one gathered operand); alpha = rho / ||t||^2
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
+  if (d.ctl->done) return;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.t_blk[blk];
+  const VT* __restrict__ tv = d.t_val;
+  const int32_t* __restrict__ tc = d.t_col;
+  const VT* __restrict__ r = d.r;
+  const double beta = d.ctl->beta;
+  const VT vbeta = VT(beta);
+  auto prod = [&](int k) -> VT { return tv[k] * r[tc[k]]; };
+  double acc[1] = {0};
+  auto epi = [&](int j, VT sum) {
+    const VT tj = (beta != 0.0) ? sum + vbeta * d.t[j] : sum;
+    d.t[j] = tj;
+    acc[0] += double(tj) * double(tj);
+  };
+  rows_block<VT>(d.t_rp, rb, prod, epi);
+  block_store_partials<1>(acc, d.partials, blk);
+  if (arrive_last(&d.ctl->counter, gridDim.x)) {
+    double tot[1];
+    final_reduce<1>(d.partials, gridDim.x, tot);
+    if (threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      const double tt = tot[0];
+      if (tt > 0.0 && !isinf(tt)) {
+        c->alpha = c->rho / tt;
+      } else {
+        c->alpha = 0.0;
+        c->done = 1;
+        if (!(tt == tt)) host_store(&d.hs->numeric, 1);
+        host_store(&d.hs->cg_done_iter, c->iter);
+      }
+      c->counter = 0;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// CG, second half (rows i of A_s): q = r + beta q; w += alpha q;
+// r -= alpha A_s t; beta' = ||r||^2 / rho; stop test
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_cg_a(Dev<VT> d, long long launch_id) {
+  if (d.ctl->done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) host_store(&d.hs->launch_seq, launch_id);
+    return;
+  }
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.a_blk[blk];
+  const VT* __restrict__ av = d.a_val;
+  const int32_t* __restrict__ ac = d.a_col;
+  const VT* __restrict__ t = d.t;
+  const double alpha = d.ctl->alpha, beta = d.ctl->beta;
+  const VT valpha = VT(alpha), vbeta = VT(beta);
+  auto prod = [&](int k) -> VT { return av[k] * t[ac[k]]; };
+  double acc[1] = {0};
+  auto epi = [&](int i, VT mq) {
+    const VT ri = d.r[i];
+    const VT qi = (beta != 0.0) ? ri + vbeta * d.q[i] : ri;
+    d.q[i] = qi;
+    d.w[i] += alpha * double(qi);
+    const VT rn = ri - valpha * mq;
+    d.r[i] = rn;
+    acc[0] += double(rn) * double(rn);
+  };
+  rows_block<VT>(d.a_rp, rb, prod, epi);
+  block_store_partials<1>(acc, d.partials, blk);
+  if (arrive_last(&d.ctl->counter, gridDim.x)) {
+    double tot[1];
+    final_reduce<1>(d.partials, gridDim.x, tot);
+    if (threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      const double rn = tot[0];
+      const bool bad = !(rn == rn) || isinf(rn);
+      c->beta = bad ? 0.0 : rn / c->rho;
+      c->rho = rn;
+      c->k += 1;
+      c->cg_total += 1;
+      const int done = (bad || rn <= c->tol2 || c->k >= c->cg_max) ? 1 : 0;
+      c->done = done;
+      c->counter = 0;
+      if (bad) host_store(&d.hs->numeric, 1);
+      if (done) host_store(&d.hs->cg_done_iter, c->iter);
+      host_store(&d.hs->launch_seq, launch_id);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// KKT check (rows i of A_s): ||A x - b||^2 = sum (d_i^-1 ((A_s xhat)_i - b_s,i))^2,
+// y = -d w / mu, b^T y; the last workgroup assembles the relative errors
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d, int iter, double bnorm, double cnorm, int has_soc) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.a_blk[blk];
+  const double* __restrict__ av = d.a_val64;
+  const int32_t* __restrict__ ac = d.a_col;
+  const double* __restrict__ xh = d.xhat;
+  auto prod = [&](int k) -> double { return av[k] * xh[ac[k]]; };
+  double acc[2] = {0, 0};
+  const double mu = d.mu;
+  auto epi = [&](int i, double ax) {
+    const double res = (ax - d.bs[i]) * d.dsq[i];
+    acc[0] += res * res;
+    const double yi = -d.dinv[i] * d.w[i] / mu;
+    d.yout[i] = yi;
+    acc[1] += d.b[i] * yi;
+  };
+  rows_block<double>(d.a_rp, rb, prod, epi);
+  block_store_partials<2>(acc, d.partials, blk);
+  if (arrive_last(&d.ctl->counter, gridDim.x)) {
+    double tot[2];
+    final_reduce<2>(d.partials, gridDim.x, tot);
+    if (threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      const double* u = c->upd;
+      const double ctx = u[1], bty = tot[1];
+      const double dx2 = u[4] + (has_soc ? c->cone[0] : 0.0);
+      const double dz2 = u[5] + (has_soc ? c->cone[1] : 0.0);
+      double e[8];
+      e[0] = sqrt(tot[0]) / (1.0 + bnorm);
+      e[1] = sqrt(u[6]) / (1.0 + cnorm);
+      e[2] = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
+      e[3] = fmax(sqrt(dx2), sqrt(dz2)) / (1.0 + fmax(sqrt(u[2]), sqrt(u[3])));
+      e[4] = fmax(fmax(e[0], e[1]), fmax(e[2], e[3]));
+      e[5] = ctx;
+      e[6] = bty;
+      e[7] = u[0];
+      bool bad = false;
+      for (int i = 0; i < 8; ++i) {
+        c->kkt[i] = e[i];
+        d.hs->kkt[i] = e[i];
+        if (!(e[i] == e[i]) || isinf(e[i])) bad = true;
+      }
+      c->counter = 0;
+      d.hs->cg_total = c->cg_total;
+      if (bad) host_store(&d.hs->numeric, 1);
+      __threadfence_system();
+      host_store(&d.hs->check_iter, iter);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// conditioning, steps 5-11: ratio per cone unit, then O = o^alpha
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_cond_ratio(Dev<VT> d, const VT* __restrict__ s_prev,
+                                                       const VT* __restrict__ s_cur, double t_cap) {
+  const int units = d.n_orth + d.n_soc;
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  double acc[3] = {INFINITY, INFINITY, INFINITY};  // min log o, min -log o, min -valid
+  const double mu = d.mu;
+  if (u < units) {
+    double num, den;
+    if (u < d.n_orth) {
+      const double sp = double(s_prev[u]), sc = double(s_cur[u]);
+      const double pj = fabs(sp), Oj = d.O[u];
+      const double x = Oj * 0.5 * (pj + sc);
+      const double z = 0.5 * (pj - sc) / (mu * Oj);
+      d.xc[u] = x;
+      d.zc[u] = z;
+      num = fabs(x);
+      den = fabs(z);
+    } else {
+      const int cone = u - d.n_orth;
+      const int off = d.soc_off[cone], end = d.soc_off[cone + 1];
+      const double Ob = d.O[off];
+      // p = abs_K(s_prev) on this cone, recomputed in FP64 (closed-form projection)
+      double n2 = 0;
+      for (int e = off + 1; e < end; ++e) {
+        const double se = double(s_prev[e]);
+        n2 += se * se;
+      }
+      const double s0 = double(s_prev[off]), nv = sqrt(n2);
+      double a0, f;
+      if (nv <= s0) {
+        a0 = s0;
+        f = 1.0;
+      } else if (nv <= -s0) {
+        a0 = 0.0;
+        f = 0.0;
+      } else {
+        a0 = 0.5 * (s0 + nv);
+        f = a0 / nv;
+      }
+      double nb = 0, x0 = 0, z0 = 0;
+      for (int e = off; e < end; ++e) {
+        const double spe = double(s_prev[e]);
+        const double pe = 2.0 * ((e == off) ? a0 : f * spe) - spe;
+        const double se = double(s_cur[e]);
+        const double x = Ob * 0.5 * (pe + se);
+        const double z = 0.5 * (pe - se) / (mu * Ob);
+        d.xc[e] = x;
+        d.zc[e] = z;
+        if (e == off) {
+          x0 = x;
+          z0 = z;
+        } else {
+          nb += x * x;
+        }
+      }
+      num = fabs(x0 - sqrt(nb));
+      den = fabs(z0);
+    }
+    double o;
+    if (num == 0.0 && den == 0.0)
+      o = 1.0;
+    else if (den == 0.0)
+      o = INFINITY;
+    else
+      o = num / den;
+    d.ounit[u] = o;
+    if (o > 0.0 && !isinf(o) && o == o) {
+      const double lo = log(o);
+      acc[0] = lo;
+      acc[1] = -lo;
+      acc[2] = -1.0;
+    }
+  }
+  block_store_partials<3, true>(acc, d.partials, blockIdx.x);
+  if (arrive_last(&d.ctl->counter, gridDim.x)) {
+    double tot[3];
+    final_reduce<3, true>(d.partials, gridDim.x, tot);
+    if (threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      c->cond[0] = tot[0];
+      c->cond[1] = tot[1];
+      c->cond[2] = tot[2];
+      const double span = -tot[1] - tot[0];
+      c->cond[3] = (tot[2] < 0.0 && span > 0.0) ? fmin(1.0, t_cap / span) : 1.0;
+      c->counter = 0;
+    }
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_cond_scale(Dev<VT> d, VT* __restrict__ s_cur) {
+  const int units = d.n_orth + d.n_soc;
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  if (u >= units) return;
+  const Ctl* c = d.ctl;
+  const bool any = c->cond[2] < 0.0;
+  double Onew = 1.0;
+  if (any) {
+    double o = d.ounit[u];
+    if (!(o == o)) o = 1.0;
+    if (o == 0.0) o = exp(c->cond[0]);
+    if (isinf(o)) o = exp(-c->cond[1]);
+    Onew = pow(o, c->cond[3]);
+  }
+  int off, end;
+  if (u < d.n_orth) {
+    off = u;
+    end = u + 1;
+  } else {
+    off = d.soc_off[u - d.n_orth];
+    end = d.soc_off[u - d.n_orth + 1];
+  }
+  const double mu = d.mu;
+  for (int e = off; e < end; ++e) {
+    d.O[e] = Onew;
+    d.chat[e] = mu * Onew * d.c[e];
+    s_cur[e] = VT(d.xc[e] / Onew - mu * Onew * d.zc[e]);  // step 14
+  }
+}
+
+// ----------------------------------------------------------------------------
+// step 12: rebuild A_s = diag(d) A O; d_i = (sum_j a_ij^2 O_j^2)^(-1/2)
+// wmode: 0 keep w, 1 rescale w by d_old/d_new, 2 w holds unscaled w -> multiply by 1/d
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_rowsum(Dev<VT> d, int wmode) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.a_blk[blk];
+  const double* __restrict__ ao = d.a_orig;
+  const int32_t* __restrict__ ac = d.a_col;
+  const double* __restrict__ O = d.O;
+  auto prod = [&](int k) -> double {
+    const double g = ao[k] * O[ac[k]];
+    return g * g;
+  };
+  auto epi = [&](int i, double D) {
+    if (!(D > 0.0)) D = 1.0;  // empty row: unit diagonal
+    const double ds = sqrt(D);
+    if (wmode == 1) d.w[i] *= ds / d.dsq[i];
+    if (wmode == 2) d.w[i] *= ds;
+    d.dsq[i] = ds;
+    d.dinv[i] = 1.0 / ds;
+    d.bs[i] = d.b[i] / ds;
+  };
+  rows_block<double>(d.a_rp, rb, prod, epi);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_scale_a(Dev<VT> d) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.a_blk[blk];
+  auto f = [&](int i, int k) {
+    const double a = d.a_orig[k] * d.O[d.a_col[k]] * d.dinv[i];
+    d.a_val64[k] = a;
+    d.a_val[k] = VT(a);
+  };
+  rows_foreach(d.a_rp, rb, f);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_scale_t(Dev<VT> d) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.t_blk[blk];
+  auto f = [&](int j, int k) {
+    const double a = d.a_orig[d.t_perm[k]] * d.O[j] * d.dinv[d.t_col[k]];
+    d.t_val64[k] = a;
+    d.t_val[k] = VT(a);
+  };
+  rows_foreach(d.t_rp, rb, f);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_chat(Dev<VT> d) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < d.n) d.chat[j] = d.mu * d.O[j] * d.c[j];
+}
+
+// ----------------------------------------------------------------------------
+// plain products with the current scaled matrix (tests, bandwidth timing)
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_spmv(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                 const VT* __restrict__ val, const RowBlock* __restrict__ blocks,
+                                                 const VT* __restrict__ x, VT* __restrict__ y) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = blocks[blk];
+  auto prod = [&](int k) -> VT { return val[k] * x[col[k]]; };
+  auto epi = [&](int i, VT s) { y[i] = s; };
+  rows_block<VT>(rp, rb, prod, epi);
+}
+
+template <typename VT>
+__global__ void k_ctl_reset(Dev<VT> d, int cg_max) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    Ctl* c = d.ctl;
+    c->rho = c->rho0 = c->tol2 = c->alpha = c->beta = 0.0;
+    c->k = 0;
+    c->done = 1;
+    c->cg_max = cg_max;
+    c->iter = 0;
+    c->cg_total = 0;
+    for (int i = 0; i < 8; ++i) c->upd[i] = 0.0;
+    for (int i = 0; i < 4; ++i) c->cone[i] = 0.0;
+    for (int i = 0; i < 4; ++i) c->cond[i] = 0.0;
+    for (int i = 0; i < 8; ++i) c->kkt[i] = 0.0;
+    c->counter = 0;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+template <typename VT>
+void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool check, hipStream_t st) {
+  const dim3 g(d.t_nblk), b(kBlock);
+  if (mode == UPD_PROLOGUE) {
+    hipLaunchKernelGGL((k_update<VT, UPD_PROLOGUE, false>), g, b, 0, st, d, s_cur, s_new);
+  } else if (mode == UPD_UPDATE) {
+    if (check)
+      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE, true>), g, b, 0, st, d, s_cur, s_new);
+    else
+      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE, false>), g, b, 0, st, d, s_cur, s_new);
+  } else {
+    if (check)
+      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE_ONLY, true>), g, b, 0, st, d, s_cur, s_new);
+    else
+      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE_ONLY, false>), g, b, 0, st, d, s_cur, s_new);
+  }
+}
+
+template <typename VT>
+void launch_cone(const Dev<VT>& d, const VT* s, bool check, bool next, int group, hipStream_t st) {
+  if (d.n_soc == 0) return;
+  const int gpb = kBlock / group;
+  hipLaunchKernelGGL((k_cone<VT>), dim3(ceil_div(d.n_soc, gpb)), dim3(kBlock), 0, st, d, s, int(check), int(next),
+                     group);
+}
+
+template <typename VT>
+void launch_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st) {
+  hipLaunchKernelGGL((k_resid<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, iter, red2, abs2);
+}
+
+template <typename VT>
+void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_t<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d);
+}
+
+template <typename VT>
+void launch_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, launch_id);
+}
+
+template <typename VT>
+void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st) {
+  hipLaunchKernelGGL((k_pres<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, iter, bnorm, cnorm, int(d.n_soc > 0));
+}
+
+template <typename VT>
+void launch_cond_ratio(const Dev<VT>& d, const VT* s_prev, const VT* s_cur, double t_cap, hipStream_t st) {
+  const int units = d.n_orth + d.n_soc;
+  hipLaunchKernelGGL((k_cond_ratio<VT>), dim3(ceil_div(units, kBlock)), dim3(kBlock), 0, st, d, s_prev, s_cur, t_cap);
+}
+
+template <typename VT>
+void launch_cond_scale(const Dev<VT>& d, VT* s_cur, hipStream_t st) {
+  const int units = d.n_orth + d.n_soc;
+  hipLaunchKernelGGL((k_cond_scale<VT>), dim3(ceil_div(units, kBlock)), dim3(kBlock), 0, st, d, s_cur);
+}
+
+template <typename VT>
+void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
+  hipLaunchKernelGGL((k_rowsum<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, wmode);
+  hipLaunchKernelGGL((k_scale_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL((k_scale_t<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
+}
+
+template <typename VT>
+void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st) {
+  if (which == 0)
+    hipLaunchKernelGGL((k_spmv<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d.a_rp, d.a_col, d.a_val, d.a_blk, x, y);
+  else
+    hipLaunchKernelGGL((k_spmv<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d.t_rp, d.t_col, d.t_val, d.t_blk, x, y);
+}
+
+template <typename VT>
+void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
+  hipLaunchKernelGGL((k_ctl_reset<VT>), dim3(1), dim3(64), 0, st, d, cg_max);
+}
+
+#define ACS_INSTANTIATE(VT)                                                                            \
+  template void launch_update<VT>(const Dev<VT>&, const VT*, VT*, int, bool, hipStream_t);            \
+  template void launch_cone<VT>(const Dev<VT>&, const VT*, bool, bool, int, hipStream_t);            \
+  template void launch_resid<VT>(const Dev<VT>&, int, double, double, hipStream_t);                   \
+  template void launch_cg_t<VT>(const Dev<VT>&, hipStream_t);                                         \
+  template void launch_cg_a<VT>(const Dev<VT>&, long long, hipStream_t);                              \
+  template void launch_pres<VT>(const Dev<VT>&, int, double, double, hipStream_t);                    \
+  template void launch_cond_ratio<VT>(const Dev<VT>&, const VT*, const VT*, double, hipStream_t);     \
+  template void launch_cond_scale<VT>(const Dev<VT>&, VT*, hipStream_t);                              \
+  template void launch_rescale<VT>(const Dev<VT>&, int, hipStream_t);                                 \
+  template void launch_spmv<VT>(const Dev<VT>&, int, const VT*, VT*, hipStream_t);                    \
+  template void launch_ctl_reset<VT>(const Dev<VT>&, int, hipStream_t);
+
+ACS_INSTANTIATE(float)
+ACS_INSTANTIATE(double)
+
+}  // namespace acs

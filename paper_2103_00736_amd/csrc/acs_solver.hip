@@ -1,0 +1,837 @@
+// Solver core (host side of one Algorithm-2 instance) and the C ABI.
+//
+// The host drives the iteration as a sequence of kernel launches on one
+// stream.  Data-dependent control (how many CG steps an outer iteration
+// needs, whether a KKT check passed) is read back without stalling the
+// stream: the last workgroup of the relevant kernel writes a progress record
+// into pinned, device-mapped host memory; the host polls it and keeps at
+// most one chunk of CG launches in flight beyond what it has seen finish.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "acs_internal.h"
+#include "acs_kernels.h"
+
+namespace acs {
+
+// ----------------------------------------------------------------------------
+// errors
+// ----------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+struct AcsError : std::runtime_error {
+  int code;
+  AcsError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(expr)                                                                                     \
+  do {                                                                                                      \
+    hipError_t e_ = (expr);                                                                                 \
+    if (e_ != hipSuccess)                                                                                   \
+      throw AcsError(ACS_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw AcsError(ACS_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+// ----------------------------------------------------------------------------
+// conditioning schedule L (Alg. 2 step 4: l in L u {1})
+// ----------------------------------------------------------------------------
+struct Schedule {
+  int first = 300, every = 100, last = -1;
+  bool contains(int l) const {
+    if (l == 1) return true;
+    if (first <= 0 || l < first) return false;
+    if (last >= 0 && l > last) return false;
+    if (every <= 0) return l == first;
+    return (l - first) % every == 0;
+  }
+};
+
+static acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
+  acs_settings s = in;
+  if (s.auto_params) {
+    if (p.is_socp()) {
+      s.t = 1.7;
+      s.l_first = 200;
+    } else {
+      s.t = 9.2;
+      s.l_first = 300;
+    }
+    s.l_every = 100;
+    s.l_last = -1;
+  }
+  if (!(s.mu > 0) || !(s.t > 0)) throw AcsError(ACS_ERR_ARG, "settings: mu and t must be > 0");
+  if (s.max_iter < 0 || s.check_every < 1 || s.cg_max < 0) throw AcsError(ACS_ERR_ARG, "settings: bad counts");
+  if (s.precision != ACS_PREC_MIXED && s.precision != ACS_PREC_FP64) throw AcsError(ACS_ERR_ARG, "settings: precision");
+  return s;
+}
+
+// ----------------------------------------------------------------------------
+// device memory
+// ----------------------------------------------------------------------------
+class DeviceArena {
+ public:
+  ~DeviceArena() { release(); }
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw AcsError(ACS_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    ptrs_.push_back(p);
+    bytes_ += bytes;
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+    bytes_ = 0;
+  }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  std::vector<void*> ptrs_;
+  size_t bytes_ = 0;
+};
+
+static int64_t estimate_bytes(const Problem& p, int precision) {
+  const int64_t vt = precision == ACS_PREC_FP64 ? 8 : 4;
+  const int64_t nnz = p.nnz, m = p.m, n = p.n;
+  int64_t b = 0;
+  b += 4 * (m + 1) + 4 * nnz + vt * nnz + 8 * nnz;       // A pattern, scaled values, original values
+  b += 4 * (n + 1) + 4 * nnz + vt * nnz + 4 * nnz;       // A^T pattern, values, perm
+  if (vt == 4) b += 16 * nnz;                            // FP64 copies for the refinement sweeps
+  b += 8 * int64_t(p.a_blocks.size() + p.t_blocks.size());
+  b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
+  b += 8 * 8 * int64_t(std::max<size_t>(std::max(p.a_blocks.size(), p.t_blocks.size()), size_t(n / kBlock + 2)));
+  return b;
+}
+
+// ----------------------------------------------------------------------------
+// one instance
+// ----------------------------------------------------------------------------
+class InstanceBase {
+ public:
+  virtual ~InstanceBase() = default;
+  virtual void set_state(int l, const double* s_prev, const double* s, const double* O, const double* w) = 0;
+  virtual void run(int iters, bool stop_on_converge) = 0;
+  virtual void get(int* l, double* s_prev, double* s, double* O, double* w, double* x, double* y, double* z) = 0;
+  virtual void spmv(int which, const void* x, void* y, int reps, double* avg_ms) = 0;
+  virtual void check_now() = 0;
+  virtual void profile(bool on) = 0;
+  virtual void timing(int cls, int64_t* count, double* total_ms) = 0;
+  virtual int current_l() const = 0;
+  acs_info info{};
+  acs_settings S{};
+};
+
+enum KClass { KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_N = 7 };
+
+template <typename VT>
+class Instance final : public InstanceBase {
+ public:
+  Instance(std::shared_ptr<const Problem> prob, const acs_settings& settings, hipStream_t stream)
+      : P_(std::move(prob)) {
+    const auto t0 = std::chrono::steady_clock::now();
+    S = resolve_settings(settings, *P_);
+    sched_.first = S.l_first;
+    sched_.every = S.l_every;
+    sched_.last = S.l_last;
+    if (stream) {
+      st_ = stream;
+    } else {
+      HIP_CHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+      own_stream_ = true;
+    }
+    setup_device();
+    set_initial();
+    HIP_CHECK(hipStreamSynchronize(st_));
+    info.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  ~Instance() override {
+    if (st_) (void)hipStreamSynchronize(st_);
+    for (auto* v : {&prof_pending_, &prof_free_})
+      for (auto& e : *v) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+      }
+    arena_.release();
+    if (hs_) (void)hipHostFree(hs_);
+    if (own_stream_) (void)hipStreamDestroy(st_);
+  }
+
+  // -------------------------------------------------------------- setup
+  void setup_device() {
+    const Problem& p = *P_;
+    Dev<VT>& d = d_;
+    std::memset(&d, 0, sizeof(d));
+    d.m = p.m;
+    d.n = p.n;
+    d.n_orth = p.n_orth;
+    d.n_soc = int(p.soc_size.size());
+    d.mu = S.mu;
+    auto up = [&](auto* dst, const auto& vec) {
+      HIP_CHECK(hipMemcpyAsync(dst, vec.data(), vec.size() * sizeof(vec[0]), hipMemcpyHostToDevice, st_));
+    };
+    int32_t* a_rp = arena_.alloc<int32_t>(p.m + 1);
+    int32_t* a_col = arena_.alloc<int32_t>(p.nnz);
+    double* a_orig = arena_.alloc<double>(p.nnz);
+    int32_t* t_rp = arena_.alloc<int32_t>(p.n + 1);
+    int32_t* t_col = arena_.alloc<int32_t>(p.nnz);
+    int32_t* t_perm = arena_.alloc<int32_t>(p.nnz);
+    RowBlock* a_blk = arena_.alloc<RowBlock>(p.a_blocks.size());
+    RowBlock* t_blk = arena_.alloc<RowBlock>(p.t_blocks.size());
+    int32_t* soc_off = arena_.alloc<int32_t>(p.soc_off.size());
+    double* b = arena_.alloc<double>(p.m);
+    double* c = arena_.alloc<double>(p.n);
+    up(a_rp, p.row_ptr);
+    if (p.nnz) {
+      up(a_col, p.col);
+      up(a_orig, p.val);
+      up(t_col, p.t_col);
+      up(t_perm, p.t_perm);
+    }
+    up(t_rp, p.t_row_ptr);
+    up(a_blk, p.a_blocks);
+    up(t_blk, p.t_blocks);
+    up(soc_off, p.soc_off);
+    up(b, p.b);
+    up(c, p.c);
+    d.a_rp = a_rp;
+    d.a_col = a_col;
+    d.a_orig = a_orig;
+    d.a_val = arena_.alloc<VT>(p.nnz);
+    d.t_rp = t_rp;
+    d.t_col = t_col;
+    d.t_perm = t_perm;
+    d.t_val = arena_.alloc<VT>(p.nnz);
+    if (sizeof(VT) == sizeof(double)) {
+      d.a_val64 = reinterpret_cast<double*>(d.a_val);
+      d.t_val64 = reinterpret_cast<double*>(d.t_val);
+    } else {
+      d.a_val64 = arena_.alloc<double>(p.nnz);
+      d.t_val64 = arena_.alloc<double>(p.nnz);
+    }
+    d.a_blk = a_blk;
+    d.a_nblk = int(p.a_blocks.size());
+    d.t_blk = t_blk;
+    d.t_nblk = int(p.t_blocks.size());
+    d.soc_off = soc_off;
+    d.b = b;
+    d.c = c;
+    d.O = arena_.alloc<double>(p.n);
+    d.chat = arena_.alloc<double>(p.n);
+    d.dsq = arena_.alloc<double>(p.m);
+    d.dinv = arena_.alloc<double>(p.m);
+    d.bs = arena_.alloc<double>(p.m);
+    d.p = arena_.alloc<VT>(p.n);
+    d.v = arena_.alloc<VT>(p.n);
+    d.zt = arena_.alloc<double>(p.n);
+    d.w = arena_.alloc<double>(p.m);
+    d.r = arena_.alloc<VT>(p.m);
+    d.q = arena_.alloc<VT>(p.m);
+    d.t = arena_.alloc<VT>(p.n);
+    d.xout = arena_.alloc<double>(p.n);
+    d.zout = arena_.alloc<double>(p.n);
+    d.yout = arena_.alloc<double>(p.m);
+    d.xhat = arena_.alloc<double>(p.n);
+    d.xc = arena_.alloc<double>(p.n);
+    d.zc = arena_.alloc<double>(p.n);
+    d.ounit = arena_.alloc<double>(size_t(p.n_orth) + p.soc_size.size());
+    d.ctl = arena_.alloc<Ctl>(1);
+    const size_t units = size_t(p.n_orth) + p.soc_size.size();
+    nparts_ = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), units / kBlock + 1,
+                                 p.soc_size.size() / 4 + 1, 1});
+    d.partials = arena_.alloc<double>(nparts_ * 8);
+    s_buf_[0] = arena_.alloc<VT>(p.n);
+    s_buf_[1] = arena_.alloc<VT>(p.n);
+    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&hs_), sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(hs_, 0, sizeof(HostStatus));
+    hs_->cg_done_iter = -1;
+    hs_->check_iter = -1;
+    HostStatus* hs_dev = nullptr;
+    HIP_CHECK(hipHostGetDevicePointer(reinterpret_cast<void**>(&hs_dev), hs_, 0));
+    d.hs = hs_dev;
+    // cone groups: lanes per Lorentz cone, ~ the mean size, power of two in [4, 64]
+    if (!p.soc_size.empty()) {
+      double mean = double(p.n - p.n_orth) / double(p.soc_size.size());
+      cone_group_ = 4;
+      while (cone_group_ < 64 && cone_group_ < mean) cone_group_ <<= 1;
+    }
+    // zero the vectors that may be read before their first write
+    std::vector<VT> zv(std::max(p.m, p.n), VT(0));
+    std::vector<double> zd(std::max(p.m, p.n), 0.0);
+    HIP_CHECK(hipMemcpyAsync(d.zt, zd.data(), sizeof(double) * p.n, hipMemcpyHostToDevice, st_));
+    HIP_CHECK(hipMemcpyAsync(d.t, zv.data(), sizeof(VT) * p.n, hipMemcpyHostToDevice, st_));
+    HIP_CHECK(hipMemcpyAsync(d.q, zv.data(), sizeof(VT) * p.m, hipMemcpyHostToDevice, st_));
+    HIP_CHECK(hipMemcpyAsync(d.xout, zd.data(), sizeof(double) * p.n, hipMemcpyHostToDevice, st_));
+    HIP_CHECK(hipMemcpyAsync(d.zout, zd.data(), sizeof(double) * p.n, hipMemcpyHostToDevice, st_));
+    HIP_CHECK(hipMemcpyAsync(d.yout, zd.data(), sizeof(double) * p.m, hipMemcpyHostToDevice, st_));
+    launch_ctl_reset(d, S.cg_max, st_);
+    check_launch();
+    HIP_CHECK(hipStreamSynchronize(st_));
+  }
+
+  // x = z = e_K, O = 1, w = 0 (l = 0)
+  void set_initial() {
+    const Problem& p = *P_;
+    std::vector<double> e(p.n, 0.0);
+    for (int j = 0; j < p.n_orth; ++j) e[j] = 1.0;
+    for (size_t i = 0; i < p.soc_size.size(); ++i) e[p.soc_off[i]] = 1.0;
+    std::vector<double> sp(p.n), sc(p.n), O(p.n, 1.0), w(p.m, 0.0);
+    for (int j = 0; j < p.n; ++j) {
+      sp[j] = (1.0 + S.mu) * e[j];
+      sc[j] = (1.0 - S.mu) * e[j];
+    }
+    set_state(0, sp.data(), sc.data(), O.data(), w.data());
+  }
+
+  template <typename T>
+  void upload_vt(VT* dst, const T* src, size_t n) {
+    std::vector<VT> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = VT(src[i]);
+    HIP_CHECK(hipMemcpyAsync(dst, tmp.data(), n * sizeof(VT), hipMemcpyHostToDevice, st_));
+    HIP_CHECK(hipStreamSynchronize(st_));
+  }
+
+  void set_state(int l, const double* s_prev, const double* s, const double* O, const double* w) override {
+    const Problem& p = *P_;
+    if (l < 0) throw AcsError(ACS_ERR_ARG, "l must be >= 0");
+    for (int j = 0; j < p.n; ++j)
+      if (!(O[j] > 0) || !std::isfinite(O[j])) throw AcsError(ACS_ERR_ARG, "O must be positive and finite");
+    for (size_t i = 0; i < p.soc_size.size(); ++i)
+      for (int e = p.soc_off[i] + 1; e < p.soc_off[i + 1]; ++e)
+        if (O[e] != O[p.soc_off[i]]) throw AcsError(ACS_ERR_ARG, "O must be constant on every cone");
+    HIP_CHECK(hipStreamSynchronize(st_));
+    cur_ = 0;
+    upload_vt(s_buf_[0], s, p.n);
+    upload_vt(s_buf_[1], s_prev, p.n);
+    HIP_CHECK(hipMemcpyAsync(d_.O, O, sizeof(double) * p.n, hipMemcpyHostToDevice, st_));
+    HIP_CHECK(hipMemcpyAsync(d_.w, w, sizeof(double) * p.m, hipMemcpyHostToDevice, st_));
+    launch_ctl_reset(d_, S.cg_max, st_);
+    launch_rescale(d_, 2, st_);  // A_s, b_s, chat for O; w -> scaled
+    check_launch();
+    l_ = l;
+    if (sched_.contains(l + 1)) {
+      // the conditioning of iteration l+1 reads abs_K(s_prev) on the cones
+      launch_cone(d_, s_prev_dev(), false, true, cone_group_, st_);
+    } else {
+      prologue();
+    }
+    check_launch();
+    HIP_CHECK(hipStreamSynchronize(st_));
+    have_xyz_ = false;
+    info = acs_info{};
+    info.iterations = l;
+  }
+
+  VT* s_cur_dev() { return s_buf_[cur_]; }
+  VT* s_prev_dev() { return s_buf_[cur_ ^ 1]; }
+
+  // p = abs_K(s), v = p - chat - A_s^T w for the current s
+  void prologue() {
+    timed(KC_UPDATE, [&] { launch_update(d_, s_cur_dev(), s_prev_dev(), UPD_PROLOGUE, false, st_); });
+    if (d_.n_soc) timed(KC_CONE, [&] { launch_cone(d_, s_cur_dev(), false, true, cone_group_, st_); });
+  }
+
+  // Alg. 2 steps 5-14 at the start of iteration l, then the prologue
+  void condition() {
+    timed(KC_COND, [&] {
+      launch_cond_ratio(d_, s_prev_dev(), s_cur_dev(), S.t, st_);
+      launch_cond_scale(d_, s_cur_dev(), st_);
+      launch_rescale(d_, 1, st_);
+    });
+    info.conditionings += 1;
+    prologue();
+  }
+
+  // ----------------------------------------------------------- profiling
+  struct ProfEv {
+    int cls;
+    hipEvent_t a, b;
+  };
+  template <class F>
+  void timed(int cls, F&& f) {
+    if (!profiling_) {
+      f();
+      check_launch();
+      return;
+    }
+    ProfEv e{cls, nullptr, nullptr};
+    if (prof_free_.empty()) {
+      HIP_CHECK(hipEventCreate(&e.a));
+      HIP_CHECK(hipEventCreate(&e.b));
+    } else {
+      e = prof_free_.back();
+      prof_free_.pop_back();
+      e.cls = cls;
+    }
+    HIP_CHECK(hipEventRecord(e.a, st_));
+    f();
+    check_launch();
+    HIP_CHECK(hipEventRecord(e.b, st_));
+    prof_pending_.push_back(e);
+  }
+  void collect_profile() {
+    if (prof_pending_.empty()) return;
+    HIP_CHECK(hipStreamSynchronize(st_));
+    for (auto& e : prof_pending_) {
+      float ms = 0;
+      HIP_CHECK(hipEventElapsedTime(&ms, e.a, e.b));
+      prof_count_[e.cls] += 1;
+      prof_ms_[e.cls] += ms;
+      prof_free_.push_back(e);
+    }
+    prof_pending_.clear();
+  }
+  void profile(bool on) override {
+    collect_profile();
+    if (on) {
+      for (int i = 0; i < KC_N; ++i) {
+        prof_count_[i] = 0;
+        prof_ms_[i] = 0;
+      }
+    }
+    profiling_ = on;
+  }
+  void timing(int cls, int64_t* count, double* total_ms) override {
+    if (cls < 0 || cls >= KC_N) throw AcsError(ACS_ERR_ARG, "timing class out of range");
+    collect_profile();
+    if (count) *count = prof_count_[cls];
+    if (total_ms) *total_ms = prof_ms_[cls];
+  }
+
+  // --------------------------------------------------------- host waits
+  template <class Pred>
+  void wait_for(Pred pred) {
+    auto t0 = std::chrono::steady_clock::now();
+    int spins = 0;
+    while (!pred()) {
+      if (++spins < 2000) {
+        std::atomic_thread_fence(std::memory_order_acquire);
+        continue;
+      }
+      spins = 0;
+      hipError_t q = hipStreamQuery(st_);
+      if (q == hipSuccess) {
+        // stream idle: every record has landed; re-test once
+        std::atomic_thread_fence(std::memory_order_seq_cst);
+        if (pred()) return;
+        throw AcsError(ACS_ERR_DEVICE, "stream idle but progress record missing");
+      }
+      if (q != hipErrorNotReady) throw AcsError(ACS_ERR_DEVICE, std::string("stream error: ") + hipGetErrorString(q));
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
+        throw AcsError(ACS_ERR_DEVICE, "timed out waiting for the GPU");
+      std::this_thread::yield();
+    }
+  }
+  long long hs_launch_seq() { return __atomic_load_n(&hs_->launch_seq, __ATOMIC_ACQUIRE); }
+  int hs_cg_done() { return __atomic_load_n(&hs_->cg_done_iter, __ATOMIC_ACQUIRE); }
+  int hs_check() { return __atomic_load_n(&hs_->check_iter, __ATOMIC_ACQUIRE); }
+
+  // CG for outer iteration `it`: chunks of launches, at most one chunk ahead
+  void run_cg(int it) {
+    const int chunk = 2;
+    int launched = 0;
+    while (launched < S.cg_max) {
+      const int c = std::min(chunk, S.cg_max - launched);
+      for (int i = 0; i < c; ++i) {
+        timed(KC_CG_T, [&] { launch_cg_t(d_, st_); });
+        const long long id = ++launch_id_;
+        timed(KC_CG_A, [&] { launch_cg_a(d_, id, st_); });
+      }
+      launched += c;
+      if (launched >= S.cg_max) break;
+      const long long target = launch_id_ - c;
+      wait_for([&] { return hs_cg_done() >= it || hs_launch_seq() >= target; });
+      if (hs_cg_done() >= it) return;
+    }
+  }
+
+  // consume a finished check; returns true when the KKT tolerance is met
+  bool read_check(int l) {
+    std::atomic_thread_fence(std::memory_order_acquire);
+    const HostStatus& h = *hs_;
+    info.eps_p = h.kkt[0];
+    info.eps_d = h.kkt[1];
+    info.eps_gap = h.kkt[2];
+    info.eps_cone = h.kkt[3];
+    info.kkt = h.kkt[4];
+    info.pobj = h.kkt[5];
+    info.dobj = h.kkt[6];
+    info.cg_steps = h.cg_total;
+    checked_iter_ = l;
+    if (S.verbose)
+      std::fprintf(stderr, "acs l=%d kkt=%.3e p=%.2e d=%.2e g=%.2e k=%.2e obj=%.10e cg=%lld\n", l, info.kkt,
+                   info.eps_p, info.eps_d, info.eps_gap, info.eps_cone, info.pobj, (long long)h.cg_total);
+    if (__atomic_load_n(&hs_->numeric, __ATOMIC_ACQUIRE)) {
+      info.status = ACS_NUMERIC;
+      return true;
+    }
+    return info.kkt <= S.eps_kkt;
+  }
+
+  // ------------------------------------------------------------ iterate
+  void run(int iters, bool stop_on_converge) override {
+    const Problem& p = *P_;
+    const auto t0 = std::chrono::steady_clock::now();
+    const double red2 = S.cg_reduce * S.cg_reduce, abs2 = S.cg_abs * S.cg_abs;
+    int pending = -1;  // iteration of a launched, unread check
+    bool converged = false, stop_now = false;
+    info.status = ACS_MAX_ITER;
+    for (int it = 0; it < iters && !stop_now; ++it) {
+      if (pending >= 0 && hs_check() >= pending) {  // a check finished meanwhile
+        const bool ok = read_check(pending);
+        pending = -1;
+        if (ok && stop_on_converge) {
+          converged = true;
+          break;
+        }
+      }
+      const int l = l_ + 1;
+      if (sched_.contains(l)) condition();
+      timed(KC_RESID, [&] { launch_resid(d_, l, red2, abs2, st_); });
+      run_cg(l);
+      const bool next_event = sched_.contains(l + 1);
+      bool check = (l % S.check_every == 0) || it == iters - 1;
+      if (check && pending >= 0) {  // one check in flight at a time
+        wait_for([&] { return hs_check() >= pending; });
+        const bool ok = read_check(pending);
+        pending = -1;
+        if (ok && stop_on_converge) {  // finish this iteration, keep the converged x, y, z
+          converged = true;
+          check = false;
+          stop_now = true;
+        }
+      }
+      timed(KC_UPDATE, [&] {
+        launch_update(d_, s_cur_dev(), s_prev_dev(), next_event ? UPD_UPDATE_ONLY : UPD_UPDATE, check, st_);
+      });
+      if (d_.n_soc) timed(KC_CONE, [&] { launch_cone(d_, s_prev_dev(), check, !next_event, cone_group_, st_); });
+      cur_ ^= 1;
+      l_ = l;
+      if (check) {
+        timed(KC_CHECK, [&] { launch_pres(d_, l, p.bnorm, p.cnorm, st_); });
+        pending = l;
+      }
+    }
+    if (pending >= 0) {
+      wait_for([&] { return hs_check() >= pending; });
+      if (read_check(pending)) converged = true;
+    }
+    HIP_CHECK(hipStreamSynchronize(st_));
+    if (info.status != ACS_NUMERIC) info.status = converged ? ACS_SOLVED : ACS_MAX_ITER;
+    info.iterations = checked_iter_ >= 0 ? checked_iter_ : l_;
+    have_xyz_ = checked_iter_ >= 0;
+    Ctl ctl;
+    HIP_CHECK(hipMemcpy(&ctl, d_.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    info.cg_steps = ctl.cg_total;
+    info.alpha = ctl.cond[3];
+    info.o_range = -ctl.cond[1] - ctl.cond[0];
+    if (info.o_range > S.t) info.o_range = info.alpha * info.o_range;
+    info.solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  int current_l() const override { return l_; }
+
+  void check_now() override {
+    if (!have_xyz_) throw AcsError(ACS_ERR_STATE, "no iteration has been run since the state was set");
+  }
+
+  void get(int* l, double* s_prev, double* s, double* O, double* w, double* x, double* y, double* z) override {
+    const Problem& p = *P_;
+    HIP_CHECK(hipStreamSynchronize(st_));
+    if (l) *l = l_;
+    auto down_vt = [&](double* dst, const VT* src, size_t n) {
+      std::vector<VT> tmp(n);
+      HIP_CHECK(hipMemcpy(tmp.data(), src, n * sizeof(VT), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < n; ++i) dst[i] = double(tmp[i]);
+    };
+    if (s_prev) down_vt(s_prev, s_prev_dev(), p.n);
+    if (s) down_vt(s, s_cur_dev(), p.n);
+    if (O) HIP_CHECK(hipMemcpy(O, d_.O, sizeof(double) * p.n, hipMemcpyDeviceToHost));
+    if (w) {
+      std::vector<double> ws(p.m), di(p.m);
+      HIP_CHECK(hipMemcpy(ws.data(), d_.w, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(di.data(), d_.dinv, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+      for (int i = 0; i < p.m; ++i) w[i] = ws[i] * di[i];
+    }
+    if (x || y || z) {
+      if (!have_xyz_) throw AcsError(ACS_ERR_STATE, "x, y, z need at least one iteration after the state was set");
+      if (x) HIP_CHECK(hipMemcpy(x, d_.xout, sizeof(double) * p.n, hipMemcpyDeviceToHost));
+      if (z) HIP_CHECK(hipMemcpy(z, d_.zout, sizeof(double) * p.n, hipMemcpyDeviceToHost));
+      if (y) HIP_CHECK(hipMemcpy(y, d_.yout, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+    }
+  }
+
+  void spmv(int which, const void* x, void* y, int reps, double* avg_ms) override {
+    if (which != 0 && which != 1) throw AcsError(ACS_ERR_ARG, "which must be 0 or 1");
+    if (!x || !y) throw AcsError(ACS_ERR_ARG, "null vector");
+    reps = std::max(reps, 1);
+    hipEvent_t a, b;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&b));
+    HIP_CHECK(hipEventRecord(a, st_));
+    for (int i = 0; i < reps; ++i) launch_spmv(d_, which, static_cast<const VT*>(x), static_cast<VT*>(y), st_);
+    check_launch();
+    HIP_CHECK(hipEventRecord(b, st_));
+    HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (avg_ms) *avg_ms = double(ms) / reps;
+  }
+
+ private:
+  std::shared_ptr<const Problem> P_;
+  Schedule sched_;
+  hipStream_t st_ = nullptr;
+  bool own_stream_ = false;
+  DeviceArena arena_;
+  Dev<VT> d_{};
+  VT* s_buf_[2] = {nullptr, nullptr};
+  int cur_ = 0;
+  int l_ = 0;
+  long long launch_id_ = 0;
+  int checked_iter_ = -1;
+  bool have_xyz_ = false;
+  int cone_group_ = 4;
+  size_t nparts_ = 1;
+  HostStatus* hs_ = nullptr;
+  bool profiling_ = false;
+  std::vector<ProfEv> prof_pending_, prof_free_;
+  int64_t prof_count_[KC_N] = {0};
+  double prof_ms_[KC_N] = {0};
+};
+
+static std::unique_ptr<InstanceBase> make_instance(std::shared_ptr<const Problem> p, const acs_settings& s,
+                                                   hipStream_t st) {
+  if (s.precision == ACS_PREC_FP64) return std::make_unique<Instance<double>>(std::move(p), s, st);
+  return std::make_unique<Instance<float>>(std::move(p), s, st);
+}
+
+static int g_device = -1;
+static std::mutex g_init_mu;
+
+static void ensure_device() {
+  std::lock_guard<std::mutex> lk(g_init_mu);
+  if (g_device >= 0) {
+    HIP_CHECK(hipSetDevice(g_device));
+    return;
+  }
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    throw AcsError(ACS_ERR_DEVICE, "no HIP device available");
+  }
+  hipDeviceProp_t prop;
+  HIP_CHECK(hipGetDeviceProperties(&prop, 0));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    throw AcsError(ACS_ERR_DEVICE, std::string("device 0 is ") + prop.gcnArchName + ", this library is built for gfx950");
+  HIP_CHECK(hipSetDevice(0));
+  g_device = 0;
+}
+
+}  // namespace acs
+
+// ============================================================================
+// C ABI
+// ============================================================================
+using namespace acs;
+
+struct acs_problem {
+  std::shared_ptr<const Problem> p;
+};
+struct acs_state {
+  std::unique_ptr<InstanceBase> inst;
+};
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    f();
+    return ACS_OK;
+  } catch (const AcsError& e) {
+    set_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return ACS_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return ACS_ERR_DEVICE;
+  }
+}
+
+extern "C" {
+
+const char* acs_version(void) { return "acs 0.1 (gfx950)"; }
+
+const char* acs_last_error(void) { return g_last_error.c_str(); }
+
+int acs_init(int32_t device) {
+  return guarded([&] {
+    if (device != 0) throw AcsError(ACS_ERR_ARG, "only device 0 is supported");
+    ensure_device();
+  });
+}
+
+void acs_settings_default(acs_settings* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->mu = 1.0;
+  s->t = 9.2;
+  s->l_first = 300;
+  s->l_every = 100;
+  s->l_last = -1;
+  s->auto_params = 1;
+  s->max_iter = 20000;
+  s->check_every = 10;
+  s->eps_kkt = 1e-4;
+  s->precision = ACS_PREC_MIXED;
+  s->cg_max = 50;
+  s->cg_reduce = 0.1;
+  s->cg_abs = 0.0;
+  s->verbose = 0;
+}
+
+int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                       const double* val, const double* b, const double* c, int32_t n_orth, int32_t n_soc,
+                       const int32_t* soc_sizes, acs_problem** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) throw AcsError(ACS_ERR_ARG, "out is null");
+    auto p = std::make_shared<Problem>();
+    std::string err;
+    if (!build_problem(m, n, nnz, row_ptr, col_idx, val, b, c, n_orth, n_soc, soc_sizes, p.get(), &err))
+      throw AcsError(ACS_ERR_ARG, err);
+    *out = new acs_problem{std::move(p)};
+  });
+}
+
+void acs_problem_destroy(acs_problem* p) { delete p; }
+
+int64_t acs_problem_device_bytes(const acs_problem* p, int32_t precision) {
+  if (!p) return -1;
+  return estimate_bytes(*p->p, precision);
+}
+
+int acs_state_create(const acs_problem* p, const acs_settings* s, void* stream, acs_state** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!p || !s || !out) throw AcsError(ACS_ERR_ARG, "null argument");
+    ensure_device();
+    auto st = std::make_unique<acs_state>();
+    st->inst = make_instance(p->p, *s, static_cast<hipStream_t>(stream));
+    *out = st.release();
+  });
+}
+
+void acs_state_destroy(acs_state* st) { delete st; }
+
+int acs_state_set(acs_state* st, int32_t l, const double* s_prev, const double* s, const double* O,
+                  const double* w) {
+  return guarded([&] {
+    if (!st || !s_prev || !s || !O || !w) throw AcsError(ACS_ERR_ARG, "null argument");
+    st->inst->set_state(l, s_prev, s, O, w);
+  });
+}
+
+int acs_state_step(acs_state* st, int32_t iters) {
+  return guarded([&] {
+    if (!st || iters < 0) throw AcsError(ACS_ERR_ARG, "bad argument");
+    if (iters > 0) st->inst->run(iters, false);
+  });
+}
+
+int acs_state_solve(acs_state* st, acs_info* info) {
+  return guarded([&] {
+    if (!st) throw AcsError(ACS_ERR_ARG, "null state");
+    InstanceBase& in = *st->inst;
+    const int left = in.S.max_iter - in.current_l();
+    if (left > 0) in.run(left, true);
+    if (info) *info = in.info;
+  });
+}
+
+int acs_state_get(acs_state* st, int32_t* l, double* s_prev, double* s, double* O, double* w, double* x, double* y,
+                  double* z) {
+  return guarded([&] {
+    if (!st) throw AcsError(ACS_ERR_ARG, "null state");
+    int li = 0;
+    st->inst->get(&li, s_prev, s, O, w, x, y, z);
+    if (l) *l = li;
+  });
+}
+
+int acs_state_info(acs_state* st, acs_info* info) {
+  return guarded([&] {
+    if (!st || !info) throw AcsError(ACS_ERR_ARG, "null argument");
+    *info = st->inst->info;
+  });
+}
+
+int acs_state_check(acs_state* st, acs_info* info) {
+  return guarded([&] {
+    if (!st) throw AcsError(ACS_ERR_ARG, "null state");
+    st->inst->check_now();
+    if (info) *info = st->inst->info;
+  });
+}
+
+int acs_state_spmv(acs_state* st, int32_t which, const void* x, void* y, int32_t reps, double* avg_ms) {
+  return guarded([&] {
+    if (!st) throw AcsError(ACS_ERR_ARG, "null state");
+    st->inst->spmv(which, x, y, reps, avg_ms);
+  });
+}
+
+int acs_state_profile(acs_state* st, int32_t enable) {
+  return guarded([&] {
+    if (!st) throw AcsError(ACS_ERR_ARG, "null state");
+    st->inst->profile(enable != 0);
+  });
+}
+
+int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_ms) {
+  return guarded([&] {
+    if (!st) throw AcsError(ACS_ERR_ARG, "null state");
+    st->inst->timing(cls, count, total_ms);
+  });
+}
+
+int acs_solve(const acs_problem* p, const acs_settings* s, double* x, double* y, double* z, acs_info* info,
+              void* stream) {
+  return guarded([&] {
+    if (!p || !s) throw AcsError(ACS_ERR_ARG, "null argument");
+    ensure_device();
+    auto inst = make_instance(p->p, *s, static_cast<hipStream_t>(stream));
+    inst->run(inst->S.max_iter, true);
+    if (x || y || z) inst->get(nullptr, nullptr, nullptr, nullptr, nullptr, x, y, z);
+    if (info) *info = inst->info;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/acs.h declares, and rejects malformed problems."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_00736_amd import acs, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "acs.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(acs.LIB_PATH), reason="libacs.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(acs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_set():
+    assert set(declared_functions()) == set(acs.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(acs.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_settings_defaults_and_layout():
+    s = acs.default_settings()
+    assert s.mu == 1.0 and s.t == 9.2 and s.l_first == 300 and s.l_every == 100 and s.auto_params == 1
+    assert s.eps_kkt == 1e-4 and s.precision == acs.PREC_MIXED
+    assert ctypes.sizeof(acs.Settings) == 104
+    assert acs.version().startswith("acs")
+
+
+def _lp():
+    return synth.lp_uniform(6, 10, 20, 3)
+
+
+def test_valid_problem_and_device_bytes():
+    p = acs.Problem.from_synth(_lp())
+    assert p.device_bytes(acs.PREC_MIXED) > 0
+    assert p.device_bytes(acs.PREC_FP64) > p.device_bytes(acs.PREC_MIXED)
+    p.close()
+
+
+@pytest.mark.parametrize("mutate, msg", [
+    (lambda a: a.update(row_ptr=np.r_[a["row_ptr"][:-1], a["row_ptr"][-1] + 1]), "row_ptr"),
+    (lambda a: a["row_ptr"].__setitem__(2, a["row_ptr"][3] + 1), "row_ptr"),
+    (lambda a: a["col_idx"].__setitem__(0, 10), "column"),
+    (lambda a: a["col_idx"].__setitem__(0, -1), "column"),
+    (lambda a: a["val"].__setitem__(0, np.nan), "non-finite"),
+    (lambda a: a["b"].__setitem__(0, np.inf), "non-finite"),
+    (lambda a: a["c"].__setitem__(0, np.nan), "non-finite"),
+    (lambda a: a.update(n_orth=9), "n_orth"),
+    (lambda a: a.update(n_orth=5, soc_sizes=np.array([3, 3])), "exceed"),
+    (lambda a: a.update(n_orth=10, soc_sizes=np.array([0])), ">= 1"),
+])
+def test_malformed_problem_rejected(mutate, msg):
+    p = _lp()
+    a = dict(row_ptr=p.row_ptr.copy(), col_idx=p.col_idx.copy(), val=p.val.copy(), b=p.b.copy(), c=p.c.copy(),
+             n_orth=p.n_orth, soc_sizes=np.array([], dtype=np.int32))
+    mutate(a)
+    with pytest.raises(acs.AcsError) as ei:
+        acs.Problem(p.m, p.n, **a)
+    assert ei.value.code == acs.ACS_ERR_ARG
+    assert msg.lower() in str(ei.value).lower()
+
+
+def test_unsorted_columns_rejected():
+    rp = np.array([0, 2], dtype=np.int64)
+    with pytest.raises(acs.AcsError):
+        acs.Problem(1, 3, rp, np.array([2, 1]), np.ones(2), np.ones(1), np.ones(3), 3)
+
+
+def test_socp_problem_accepted():
+    p = synth.socp_percol(20, 60, 3, 5, 3, 8, 0.8)
+    h = acs.Problem.from_synth(p)
+    h.close()
+
+
+def test_no_gpu_here_is_a_clean_error():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert acs.lib().acs_init(0) == acs.ACS_ERR_DEVICE

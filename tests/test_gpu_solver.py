@@ -1,0 +1,166 @@
+"""GPU parity of the HIP solver against the FP64 oracle, through the C ABI.
+
+* one iteration (steps 16-20) from a shared state, before and after a
+  conditioning event, FP64 and mixed precision;
+* the conditioning event itself (steps 5-14): O and the re-cast s;
+* full solves: KKT of the returned (x, y, z) recomputed by the oracle in FP64,
+  objective against the planted optimum, z and y against the oracle's;
+* run-to-run bitwise determinism.
+"""
+import numpy as np
+import pytest
+
+from oracle.alg2 import Algorithm2, Schedule, default_parameters, one_iteration
+from oracle.cones import abs_K
+from oracle.kkt import kkt_errors
+from paper_2103_00736_amd import acs, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _oracle_run(p, iters, t, L):
+    """Oracle state after `iters` iterations: (s_prev, s, O, w) in the GPU's convention."""
+    alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
+    s_prev = None
+    for _ in range(iters):
+        s_prev = alg.s.copy()
+        alg.step()
+    w = -alg.dual_multiplier()  # w = -mu y
+    return alg, s_prev, alg.s.copy(), alg.O.copy(), w
+
+
+PROBLEMS = {
+    "cfg0": lambda: synth.config0(),
+    "lp_powerlaw": lambda: synth.config1(scale=0.002),
+    "socp": lambda: synth.config2(scale=0.002),
+}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert acs.lib().acs_init(0) == acs.ACS_OK, acs.lib().acs_last_error()
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("prec", [acs.PREC_FP64, acs.PREC_MIXED])
+@pytest.mark.parametrize("l0", [57, 317])
+def test_one_iteration_parity(name, prec, l0):
+    p = PROBLEMS[name]()
+    t, L = default_parameters(p.soc_sizes)
+    alg, s_prev, s, O, w = _oracle_run(p, l0, t, L)
+    if prec == acs.PREC_MIXED:
+        s_prev, s = _f32(s_prev), _f32(s)
+    tol = 1e-9 if prec == acs.PREC_FP64 else 1e-5
+    st = acs.State(acs.Problem.from_synth(p), precision=prec, cg_max=2000,
+                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7)
+    st.set(l0, s_prev, s, O, w)
+    st.step(1)
+    g = st.get()
+    ref = one_iteration(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, 1.0, s, O)
+    print(f"{name} prec={prec} l0={l0}: s {_rel(g['s'], ref['s']):.2e} x {_rel(g['x'], ref['x']):.2e} "
+          f"z {_rel(g['z'], ref['z']):.2e} y {_rel(g['y'], ref['y']):.2e}")
+    assert g["l"] == l0 + 1
+    assert np.array_equal(g["s_prev"], s)
+    assert _rel(g["s"], ref["s"]) <= tol
+    assert _rel(g["x"], ref["x"]) <= tol
+    assert _rel(g["z"], ref["z"]) <= tol
+    assert _rel(g["y"], ref["y"]) <= 10 * tol
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("prec", [acs.PREC_FP64, acs.PREC_MIXED])
+def test_conditioning_event_parity(name, prec):
+    p = PROBLEMS[name]()
+    t, L = default_parameters(p.soc_sizes)
+    l_event = L.first + L.every  # a member of L after the first event
+    alg, s_prev, s, O, w = _oracle_run(p, l_event - 1, t, L)
+    if prec == acs.PREC_MIXED:
+        s_prev, s = _f32(s_prev), _f32(s)
+    # oracle from exactly the shared state: x, z of the last iteration (steps 19-20)
+    pp = abs_K(s_prev, p.n_orth, p.soc_sizes)
+    alg.x = O * (pp + s) / 2.0
+    alg.z = (pp - s) / (2.0 * O)
+    alg.l = l_event - 1
+    alg.step()  # conditions (steps 5-14) then iterates
+    st = acs.State(acs.Problem.from_synth(p), precision=prec, cg_max=2000,
+                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7)
+    st.set(l_event - 1, s_prev, s, O, w)
+    st.step(1)
+    g = st.get()
+    print(f"{name} prec={prec}: O {_rel(g['O'], alg.O):.2e} s {_rel(g['s'], alg.s):.2e} "
+          f"O range {np.log(alg.O.max() / alg.O.min()):.3f}")
+    assert _rel(g["O"], alg.O) <= 1e-9
+    tol = 1e-9 if prec == acs.PREC_FP64 else 1e-5
+    assert _rel(g["s"], alg.s) <= tol
+    assert _rel(g["x"], alg.x) <= tol
+
+
+def _verify(p, x, y, z, info, eps):
+    rec = kkt_errors(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, x, y, z)
+    obj_err = abs(rec["pobj"] - p.p_star) / (1 + abs(p.p_star))
+    print(f"{p.name}: status={info.status} iters={info.iterations} cg={info.cg_steps} gpu_kkt={info.kkt:.2e} "
+          f"oracle_kkt={rec['kkt']:.2e} (p {rec['eps_p']:.1e} d {rec['eps_d']:.1e} g {rec['eps_g']:.1e} "
+          f"k {rec['eps_k']:.1e}) obj_err={obj_err:.2e} solve_ms={info.solve_ms:.1f}")
+    assert info.status == acs.SOLVED
+    assert rec["kkt"] <= eps
+    return rec, obj_err
+
+
+def test_solve_config0_fp64():
+    p = synth.config0()
+    x, y, z, info = acs.solve(acs.Problem.from_synth(p), precision=acs.PREC_FP64, eps_kkt=1e-6, max_iter=5000)
+    rec, obj_err = _verify(p, x, y, z, info, 1.05e-6)
+    assert obj_err <= 1e-5
+    t, L = default_parameters(p.soc_sizes)
+    alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
+    alg.run(5000, eps=1e-8, check_every=10)
+    assert np.linalg.norm(z - alg.z) <= 1e-3 * (1 + np.linalg.norm(alg.z))
+    assert np.linalg.norm(y - p.y0) <= 1e-3 * (1 + np.linalg.norm(p.y0))
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_solve_mixed_to_1e4(name):
+    p = PROBLEMS[name]()
+    x, y, z, info = acs.solve(acs.Problem.from_synth(p), precision=acs.PREC_MIXED, eps_kkt=1e-4, max_iter=20000)
+    rec, obj_err = _verify(p, x, y, z, info, 1.05e-4)
+    assert obj_err <= 3e-4
+
+
+def test_paper_example_fp64():
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_example.json")))
+    A = np.array(g["A"])
+    rp = np.array([0, 5, 10, 15])
+    prob = acs.Problem(3, 5, rp, np.tile(np.arange(5), 3), A.ravel(), np.array(g["b"]), np.array(g["c"]), 5)
+    x, y, z, info = acs.solve(prob, precision=acs.PREC_FP64, eps_kkt=1e-8, check_every=1, auto_params=0, t=9.2,
+                              l_first=1, l_every=1, l_last=50, max_iter=2000, cg_reduce=1e-14, cg_max=20)
+    from tests._brute import lp_vertex_optimum
+
+    best = lp_vertex_optimum(A, np.array(g["b"]), np.array(g["c"]))
+    print(info.as_dict())
+    assert info.status == acs.SOLVED
+    assert abs(info.pobj - best[0]) <= 1e-6 * abs(best[0])
+    assert np.allclose(x, best[2], atol=1e-5)
+
+
+def test_determinism_bitwise():
+    p = synth.config1(scale=0.002)
+    prob = acs.Problem.from_synth(p)
+    outs = []
+    for _ in range(2):
+        st = acs.State(prob, precision=acs.PREC_MIXED)
+        st.step(120)
+        outs.append(st.get())
+        st.close()
+    for k in ("s", "s_prev", "O", "w", "x", "y", "z"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
