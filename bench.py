@@ -144,7 +144,7 @@ def main():
     st.profile(False)
     cg_prof = st.info().cg_steps - cgp0
     cls = {"update": acs.KC_UPDATE, "resid": acs.KC_RESID, "cg_t": acs.KC_CG_T, "cg_a": acs.KC_CG_A,
-           "check": acs.KC_CHECK, "cond": acs.KC_COND}
+           "check": acs.KC_CHECK, "cond": acs.KC_COND, "fin": acs.KC_FIN}
     prof = {k: st.timing(v) for k, v in cls.items()}
     kb = kernel_bytes(p.m, p.n, p.nnz)
     dom = max(("cg_a", "cg_t"), key=lambda k: prof[k][1])

@@ -183,6 +183,40 @@ int acs_state_spmv(acs_state* st, int32_t which, const void* x, void* y, int32_t
 int acs_state_profile(acs_state* st, int32_t enable);
 int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_ms);
 
+/*
+ * Batched solving of many independent (small) problems in one persistent
+ * kernel launch (captured in a HIP graph): each workgroup takes the next
+ * instance from a device work queue, largest first, and runs Algorithm 2 for
+ * it with workgroup-level sweeps and reductions until its KKT error meets
+ * eps_kkt or the iteration budget runs out.  The same iteration as the
+ * one-instance path (fused steps 16-20, conditioning steps 5-14, same
+ * precision split); per-instance t and L follow the class when auto_params=1.
+ * Device memory: one arena for all instances (acs_problem_device_bytes
+ * summed, roughly); ACS_ERR_NOMEM if it does not fit.
+ */
+typedef struct acs_batch acs_batch;
+int acs_batch_create(int32_t count, const acs_problem* const* probs, const acs_settings* s, void* stream,
+                     acs_batch** out);
+void acs_batch_destroy(acs_batch* b);
+/* Timed choice of lanes-per-row (rows of A and of A^T) for each size class on
+ * `sample` instances of the class, `iters` iterations per trial; results are
+ * read from / merged into the text file cache_path (may be NULL).  Resets all
+ * instances to their initial state. */
+int acs_batch_autotune(acs_batch* b, int32_t sample, int32_t iters, const char* cache_path);
+/* Advance every unfinished instance by up to iter_budget iterations in one
+ * launch (use_graph = 1: replay of the captured graph; 0: eager launch);
+ * *ms (may be NULL) gets the launch's GPU time.  Resumable: the state stays
+ * resident between calls. */
+int acs_batch_run(acs_batch* b, int32_t iter_budget, int32_t use_graph, double* ms);
+/* Host outputs of instance i (any may be NULL); x, z length n_i, y length m_i. */
+int acs_batch_result(acs_batch* b, int32_t i, double* x, double* y, double* z, acs_info* info);
+/* Lanes per row chosen for instance i. */
+int acs_batch_lanes(acs_batch* b, int32_t i, int32_t* g_a, int32_t* g_t);
+/* One-shot: create, run to completion (max_iter), copy results, destroy.
+ * x[i], y[i], z[i] are per-instance host buffers (the arrays may be NULL). */
+int acs_batch_solve(int32_t count, const acs_problem* const* probs, const acs_settings* s, double* const* x,
+                    double* const* y, double* const* z, acs_info* infos, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,13 +26,14 @@ SOLVED, MAX_ITER, NUMERIC, CANCELLED = 0, 1, 2, 3
 PREC_MIXED, PREC_FP64 = 0, 1
 
 # timing classes of acs_state_timing
-KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND = range(7)
+KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN = range(8)
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
     "acs_problem_destroy", "acs_problem_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
     "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
-    "acs_state_spmv", "acs_state_profile", "acs_state_timing",
+    "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_batch_create", "acs_batch_destroy",
+    "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_lanes", "acs_batch_solve",
 ]
 
 
@@ -102,6 +103,16 @@ def lib() -> ctypes.CDLL:
         "acs_state_spmv": (ctypes.c_int, [P, ctypes.c_int32, P, P, ctypes.c_int32, DP]),
         "acs_state_profile": (ctypes.c_int, [P, ctypes.c_int32]),
         "acs_state_timing": (ctypes.c_int, [P, ctypes.c_int32, I64P, DP]),
+        "acs_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(Settings), P,
+                                            ctypes.POINTER(P)]),
+        "acs_batch_destroy": (None, [P]),
+        "acs_batch_autotune": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p]),
+        "acs_batch_run": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, DP]),
+        "acs_batch_result": (ctypes.c_int, [P, ctypes.c_int32, DP, DP, DP, ctypes.POINTER(Info)]),
+        "acs_batch_lanes": (ctypes.c_int, [P, ctypes.c_int32, I32P, I32P]),
+        "acs_batch_solve": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(Settings),
+                                           ctypes.POINTER(DP), ctypes.POINTER(DP), ctypes.POINTER(DP),
+                                           ctypes.POINTER(Info), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -257,3 +268,52 @@ def solve(problem: Problem, settings: Optional[Settings] = None, stream: int = 0
     _check(lib().acs_solve(problem.handle, ctypes.byref(settings), _dptr(x), _dptr(y), _dptr(z), ctypes.byref(info),
                            P(stream or None)))
     return x, y, z, info
+
+
+class Batch:
+    """Many independent problems solved by one persistent kernel (acs_batch)."""
+
+    def __init__(self, problems, settings: Optional[Settings] = None, stream: int = 0, **kw):
+        if settings is None:
+            settings = default_settings(**kw)
+        self.problems = list(problems)
+        self.settings = settings
+        arr = (P * len(self.problems))(*[p.handle for p in self.problems])
+        h = P()
+        _check(lib().acs_batch_create(len(self.problems), arr, ctypes.byref(settings), P(stream or None),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def autotune(self, sample: int = 8, iters: int = 20, cache_path: Optional[str] = None):
+        _check(lib().acs_batch_autotune(self.handle, int(sample), int(iters),
+                                        cache_path.encode() if cache_path else None))
+
+    def run(self, budget: int, use_graph: bool = True) -> float:
+        ms = ctypes.c_double()
+        _check(lib().acs_batch_run(self.handle, int(budget), 1 if use_graph else 0, ctypes.byref(ms)))
+        return ms.value
+
+    def result(self, i: int, xyz: bool = True):
+        p = self.problems[i]
+        info = Info()
+        x = np.empty(p.n) if xyz else None
+        z = np.empty(p.n) if xyz else None
+        y = np.empty(p.m) if xyz else None
+        _check(lib().acs_batch_result(self.handle, int(i), _dptr(x), _dptr(y), _dptr(z), ctypes.byref(info)))
+        return x, y, z, info
+
+    def lanes(self, i: int):
+        a, t = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().acs_batch_lanes(self.handle, int(i), ctypes.byref(a), ctypes.byref(t)))
+        return a.value, t.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().acs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,6 +2,9 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -51,4 +54,38 @@ std::vector<RowBlock> make_row_blocks(const int32_t* row_ptr, int32_t rows, int3
 // Error reporting (thread-local message).
 void set_error(const std::string& msg);
 
+// Error carried inside the library; converted to a return code at the ABI.
+struct AcsError : std::runtime_error {
+  int code;
+  AcsError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// Settings with the per-class defaults resolved and validated.
+acs_settings resolve_settings(const acs_settings& in, const Problem& p);
+
+// Select device 0 (gfx950) once per process.
+void ensure_device();
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    return ACS_OK;
+  } catch (const AcsError& e) {
+    set_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return ACS_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return ACS_ERR_DEVICE;
+  }
+}
+
 }  // namespace acs
+
+// Library-side body of the opaque problem handle.
+struct acs_problem {
+  std::shared_ptr<const acs::Problem> p;
+};

@@ -36,8 +36,6 @@ struct Ctl {
   double cone[4]; // reductions of the cone kernel
   double cond[4]; // conditioning: min log o, -max log o, -any valid, alpha
   double kkt[8];  // eps_p, eps_d, eps_gap, eps_cone, kkt, pobj, dobj, ds2
-  unsigned int counter;
-  unsigned int pad;
 };
 
 // Host-visible status written by kernels into pinned, mapped host memory.
@@ -109,9 +107,14 @@ template <typename VT> void launch_update(const Dev<VT>& d, const VT* s_cur, VT*
                                           hipStream_t st);
 template <typename VT> void launch_cone(const Dev<VT>& d, const VT* s, bool check, bool next, int group,
                                         hipStream_t st);
-template <typename VT> void launch_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st);
+// residual sweep and its finalizer (rho_0, threshold, zero-step exit)
+template <typename VT> void launch_resid(const Dev<VT>& d, hipStream_t st);
+template <typename VT> void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st);
+// the two CG sweeps and their finalizers (alpha; beta, stop test, host progress record)
 template <typename VT> void launch_cg_t(const Dev<VT>& d, hipStream_t st);
-template <typename VT> void launch_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st);
+template <typename VT> void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st);
+template <typename VT> void launch_cg_a(const Dev<VT>& d, hipStream_t st);
+template <typename VT> void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st);
 template <typename VT> void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st);
 template <typename VT> void launch_cond_ratio(const Dev<VT>& d, const VT* s_prev, const VT* s_cur, double t_cap,
                                               hipStream_t st);

@@ -66,23 +66,11 @@ __device__ __forceinline__ void block_store_partials(double (&acc)[N], double* p
   }
 }
 
-// True in the last workgroup to finish; its loads after this see every partial.
-__device__ __forceinline__ bool arrive_last(unsigned int* counter, unsigned int nb) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int tk = atomicAdd(counter, 1u);
-    is_last = (tk == nb - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
-// Sum (or min) of the partials of nb workgroups, in fixed order; result on all threads.
+// Sum (or min) of the partials of nb workgroups in fixed order, by one
+// workgroup of a later kernel (the kernel boundary makes them visible);
+// result on every thread.
 template <int N, bool MIN = false>
-__device__ __forceinline__ void final_reduce(const double* partials, int nb, double (&out)[N]) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, int nb, double (&out)[N]) {
   __shared__ double sh[kBlock / 64][N];
   double acc[N];
 #pragma unroll
@@ -90,7 +78,7 @@ __device__ __forceinline__ void final_reduce(const double* partials, int nb, dou
   for (int b = threadIdx.x; b < nb; b += kBlock) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const double v = __hip_atomic_load(partials + size_t(b) * N + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double v = partials[size_t(b) * N + i];
       acc[i] = MIN ? fmin(acc[i], v) : acc[i] + v;
     }
   }
@@ -104,9 +92,9 @@ __device__ __forceinline__ void final_reduce(const double* partials, int nb, dou
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    double s = sh[0][i];
-    for (int k = 1; k < kBlock / 64; ++k) s = MIN ? fmin(s, sh[k][i]) : s + sh[k][i];
-    out[i] = s;
+    double v = sh[0][i];
+    for (int k = 1; k < kBlock / 64; ++k) v = MIN ? fmin(v, sh[k][i]) : v + sh[k][i];
+    out[i] = v;
   }
 }
 
@@ -230,17 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restri
     }
   };
   rows_block<double>(d.t_rp, rb, prod, epi);
-  if (MODE != UPD_PROLOGUE) {
-    block_store_partials<7>(acc, d.partials, blk);
-    if (arrive_last(&d.ctl->counter, gridDim.x)) {
-      double tot[7];
-      final_reduce<7>(d.partials, gridDim.x, tot);
-      if (threadIdx.x == 0) {
-        for (int i = 0; i < 7; ++i) d.ctl->upd[i] = tot[i];
-        d.ctl->counter = 0;
-      }
-    }
-  }
+  if (MODE != UPD_PROLOGUE) block_store_partials<7>(acc, d.partials, blk);
 }
 
 // ----------------------------------------------------------------------------
@@ -300,25 +278,14 @@ __global__ __launch_bounds__(kBlock) void k_cone(Dev<VT> d, const VT* __restrict
       }
     }
   }
-  if (check) {
-    block_store_partials<2>(acc, d.partials, blockIdx.x);
-    if (arrive_last(&d.ctl->counter, gridDim.x)) {
-      double tot[2];
-      final_reduce<2>(d.partials, gridDim.x, tot);
-      if (threadIdx.x == 0) {
-        d.ctl->cone[0] = tot[0];
-        d.ctl->cone[1] = tot[1];
-        d.ctl->counter = 0;
-      }
-    }
-  }
+  if (check) block_store_partials<2>(acc, d.partials, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
 // CG start: r = A_s v - b_s (rows i of A_s), FP64 accumulation
 // ----------------------------------------------------------------------------
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_resid(Dev<VT> d, int iter, double red2, double abs2) {
+__global__ __launch_bounds__(kBlock) void k_resid(Dev<VT> d) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const RowBlock rb = d.a_blk[blk];
   const double* __restrict__ av = d.a_val64;
@@ -333,27 +300,6 @@ __global__ __launch_bounds__(kBlock) void k_resid(Dev<VT> d, int iter, double re
   };
   rows_block<double>(d.a_rp, rb, prod, epi);
   block_store_partials<1>(acc, d.partials, blk);
-  if (arrive_last(&d.ctl->counter, gridDim.x)) {
-    double tot[1];
-    final_reduce<1>(d.partials, gridDim.x, tot);
-    if (threadIdx.x == 0) {
-      Ctl* c = d.ctl;
-      const double rho = tot[0];
-      c->rho = rho;
-      c->rho0 = rho;
-      c->tol2 = fmax(red2 * rho, abs2);
-      c->alpha = 0.0;
-      c->beta = 0.0;
-      c->k = 0;
-      c->iter = iter;
-      const bool bad = !(rho == rho) || isinf(rho);
-      const int done = (bad || rho <= c->tol2 || c->cg_max <= 0) ? 1 : 0;
-      c->done = done;
-      c->counter = 0;
-      if (bad) host_store(&d.hs->numeric, 1);
-      if (done) host_store(&d.hs->cg_done_iter, iter);
-    }
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -379,23 +325,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
   };
   rows_block<VT>(d.t_rp, rb, prod, epi);
   block_store_partials<1>(acc, d.partials, blk);
-  if (arrive_last(&d.ctl->counter, gridDim.x)) {
-    double tot[1];
-    final_reduce<1>(d.partials, gridDim.x, tot);
-    if (threadIdx.x == 0) {
-      Ctl* c = d.ctl;
-      const double tt = tot[0];
-      if (tt > 0.0 && !isinf(tt)) {
-        c->alpha = c->rho / tt;
-      } else {
-        c->alpha = 0.0;
-        c->done = 1;
-        if (!(tt == tt)) host_store(&d.hs->numeric, 1);
-        host_store(&d.hs->cg_done_iter, c->iter);
-      }
-      c->counter = 0;
-    }
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -403,11 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
 // r -= alpha A_s t; beta' = ||r||^2 / rho; stop test
 // ----------------------------------------------------------------------------
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_cg_a(Dev<VT> d, long long launch_id) {
-  if (d.ctl->done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) host_store(&d.hs->launch_seq, launch_id);
-    return;
-  }
+__global__ __launch_bounds__(kBlock) void k_cg_a(Dev<VT> d) {
+  if (d.ctl->done) return;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const RowBlock rb = d.a_blk[blk];
   const VT* __restrict__ av = d.a_val;
@@ -428,25 +354,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(Dev<VT> d, long long launch_id)
   };
   rows_block<VT>(d.a_rp, rb, prod, epi);
   block_store_partials<1>(acc, d.partials, blk);
-  if (arrive_last(&d.ctl->counter, gridDim.x)) {
-    double tot[1];
-    final_reduce<1>(d.partials, gridDim.x, tot);
-    if (threadIdx.x == 0) {
-      Ctl* c = d.ctl;
-      const double rn = tot[0];
-      const bool bad = !(rn == rn) || isinf(rn);
-      c->beta = bad ? 0.0 : rn / c->rho;
-      c->rho = rn;
-      c->k += 1;
-      c->cg_total += 1;
-      const int done = (bad || rn <= c->tol2 || c->k >= c->cg_max) ? 1 : 0;
-      c->done = done;
-      c->counter = 0;
-      if (bad) host_store(&d.hs->numeric, 1);
-      if (done) host_store(&d.hs->cg_done_iter, c->iter);
-      host_store(&d.hs->launch_seq, launch_id);
-    }
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -454,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(Dev<VT> d, long long launch_id)
 // y = -d w / mu, b^T y; the last workgroup assembles the relative errors
 // ----------------------------------------------------------------------------
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d, int iter, double bnorm, double cnorm, int has_soc) {
+__global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const RowBlock rb = d.a_blk[blk];
   const double* __restrict__ av = d.a_val64;
@@ -472,37 +379,6 @@ __global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d, int iter, double bno
   };
   rows_block<double>(d.a_rp, rb, prod, epi);
   block_store_partials<2>(acc, d.partials, blk);
-  if (arrive_last(&d.ctl->counter, gridDim.x)) {
-    double tot[2];
-    final_reduce<2>(d.partials, gridDim.x, tot);
-    if (threadIdx.x == 0) {
-      Ctl* c = d.ctl;
-      const double* u = c->upd;
-      const double ctx = u[1], bty = tot[1];
-      const double dx2 = u[4] + (has_soc ? c->cone[0] : 0.0);
-      const double dz2 = u[5] + (has_soc ? c->cone[1] : 0.0);
-      double e[8];
-      e[0] = sqrt(tot[0]) / (1.0 + bnorm);
-      e[1] = sqrt(u[6]) / (1.0 + cnorm);
-      e[2] = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
-      e[3] = fmax(sqrt(dx2), sqrt(dz2)) / (1.0 + fmax(sqrt(u[2]), sqrt(u[3])));
-      e[4] = fmax(fmax(e[0], e[1]), fmax(e[2], e[3]));
-      e[5] = ctx;
-      e[6] = bty;
-      e[7] = u[0];
-      bool bad = false;
-      for (int i = 0; i < 8; ++i) {
-        c->kkt[i] = e[i];
-        d.hs->kkt[i] = e[i];
-        if (!(e[i] == e[i]) || isinf(e[i])) bad = true;
-      }
-      c->counter = 0;
-      d.hs->cg_total = c->cg_total;
-      if (bad) host_store(&d.hs->numeric, 1);
-      __threadfence_system();
-      host_store(&d.hs->check_iter, iter);
-    }
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -510,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d, int iter, double bno
 // ----------------------------------------------------------------------------
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_cond_ratio(Dev<VT> d, const VT* __restrict__ s_prev,
-                                                       const VT* __restrict__ s_cur, double t_cap) {
+                                                       const VT* __restrict__ s_cur) {
   const int units = d.n_orth + d.n_soc;
   const int u = blockIdx.x * kBlock + threadIdx.x;
   double acc[3] = {INFINITY, INFINITY, INFINITY};  // min log o, min -log o, min -valid
@@ -583,19 +459,6 @@ __global__ __launch_bounds__(kBlock) void k_cond_ratio(Dev<VT> d, const VT* __re
     }
   }
   block_store_partials<3, true>(acc, d.partials, blockIdx.x);
-  if (arrive_last(&d.ctl->counter, gridDim.x)) {
-    double tot[3];
-    final_reduce<3, true>(d.partials, gridDim.x, tot);
-    if (threadIdx.x == 0) {
-      Ctl* c = d.ctl;
-      c->cond[0] = tot[0];
-      c->cond[1] = tot[1];
-      c->cond[2] = tot[2];
-      const double span = -tot[1] - tot[0];
-      c->cond[3] = (tot[2] < 0.0 && span > 0.0) ? fmin(1.0, t_cap / span) : 1.0;
-      c->counter = 0;
-    }
-  }
 }
 
 template <typename VT>
@@ -656,28 +519,51 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(Dev<VT> d, int wmode) {
   rows_block<double>(d.a_rp, rb, prod, epi);
 }
 
+// Row index of every staged nonzero of a row block (LDS), so that the
+// per-nonzero rewrite below reads and writes with coalesced accesses.
+__device__ __forceinline__ void stage_rows(const int32_t* __restrict__ rp, RowBlock rb, int k0, int32_t* rowof) {
+  const int tid = threadIdx.x;
+  const int nrows = rb.r1 - rb.r0;
+  int G = 64;
+  while (G > 1 && G * nrows > kBlock) G >>= 1;
+  const int grp = tid / G, lane = tid & (G - 1), ngrp = kBlock / G;
+  for (int r = rb.r0 + grp; r < rb.r1; r += ngrp) {
+    const int e = rp[r + 1] - k0;
+    for (int k = rp[r] - k0 + lane; k < e; k += G) rowof[k] = r;
+  }
+  __syncthreads();
+}
+
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_scale_a(Dev<VT> d) {
+  __shared__ int32_t rowof[kStageNnz];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const RowBlock rb = d.a_blk[blk];
-  auto f = [&](int i, int k) {
+  const int k0 = d.a_rp[rb.r0], k1 = d.a_rp[rb.r1];
+  const bool one = (k1 - k0 > kStageNnz);
+  if (!one) stage_rows(d.a_rp, rb, k0, rowof);
+  for (int k = k0 + threadIdx.x; k < k1; k += kBlock) {
+    const int i = one ? rb.r0 : rowof[k - k0];
     const double a = d.a_orig[k] * d.O[d.a_col[k]] * d.dinv[i];
     d.a_val64[k] = a;
     d.a_val[k] = VT(a);
-  };
-  rows_foreach(d.a_rp, rb, f);
+  }
 }
 
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_scale_t(Dev<VT> d) {
+  __shared__ int32_t rowof[kStageNnz];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const RowBlock rb = d.t_blk[blk];
-  auto f = [&](int j, int k) {
+  const int k0 = d.t_rp[rb.r0], k1 = d.t_rp[rb.r1];
+  const bool one = (k1 - k0 > kStageNnz);
+  if (!one) stage_rows(d.t_rp, rb, k0, rowof);
+  for (int k = k0 + threadIdx.x; k < k1; k += kBlock) {
+    const int j = one ? rb.r0 : rowof[k - k0];
     const double a = d.a_orig[d.t_perm[k]] * d.O[j] * d.dinv[d.t_col[k]];
     d.t_val64[k] = a;
     d.t_val[k] = VT(a);
-  };
-  rows_foreach(d.t_rp, rb, f);
+  }
 }
 
 template <typename VT>
@@ -714,7 +600,143 @@ __global__ void k_ctl_reset(Dev<VT> d, int cg_max) {
     for (int i = 0; i < 4; ++i) c->cone[i] = 0.0;
     for (int i = 0; i < 4; ++i) c->cond[i] = 0.0;
     for (int i = 0; i < 8; ++i) c->kkt[i] = 0.0;
-    c->counter = 0;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// finalizers: one workgroup sums the per-workgroup partials of the kernel
+// just before it and applies the scalar logic
+// ----------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_fin_upd(Dev<VT> d, int nb) {
+  double t[7];
+  sum_partials<7>(d.partials, nb, t);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 7; ++i) d.ctl->upd[i] = t[i];
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_fin_cone(Dev<VT> d, int nb) {
+  double t[2];
+  sum_partials<2>(d.partials, nb, t);
+  if (threadIdx.x == 0) {
+    d.ctl->cone[0] = t[0];
+    d.ctl->cone[1] = t[1];
+  }
+}
+
+// CG start: rho_0, the stop threshold, zero-step exit
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_fin_resid(Dev<VT> d, int nb, int iter, double red2, double abs2) {
+  double t[1];
+  sum_partials<1>(d.partials, nb, t);
+  if (threadIdx.x == 0) {
+    Ctl* c = d.ctl;
+    const double rho = t[0];
+    c->rho = rho;
+    c->rho0 = rho;
+    c->tol2 = fmax(red2 * rho, abs2);
+    c->alpha = 0.0;
+    c->beta = 0.0;
+    c->k = 0;
+    c->iter = iter;
+    const bool bad = !(rho == rho) || isinf(rho);
+    const int done = (bad || rho <= c->tol2 || c->cg_max <= 0) ? 1 : 0;
+    c->done = done;
+    if (bad) host_store(&d.hs->numeric, 1);
+    if (done) host_store(&d.hs->cg_done_iter, iter);
+  }
+}
+
+// alpha = rho / ||t||^2 (||t||^2 = q^T A_s A_s^T q)
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_fin_cg_t(Dev<VT> d, int nb) {
+  if (d.ctl->done) return;
+  double t[1];
+  sum_partials<1>(d.partials, nb, t);
+  if (threadIdx.x == 0) {
+    Ctl* c = d.ctl;
+    const double tt = t[0];
+    if (tt > 0.0 && !isinf(tt)) {
+      c->alpha = c->rho / tt;
+    } else {
+      c->alpha = 0.0;
+      c->done = 1;
+      if (!(tt == tt)) host_store(&d.hs->numeric, 1);
+      host_store(&d.hs->cg_done_iter, c->iter);
+    }
+  }
+}
+
+// beta = ||r_new||^2 / rho, stop test, progress record for the host
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_fin_cg_a(Dev<VT> d, int nb, long long launch_id) {
+  if (!d.ctl->done) {
+    double t[1];
+    sum_partials<1>(d.partials, nb, t);
+    if (threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      const double rn = t[0];
+      const bool bad = !(rn == rn) || isinf(rn);
+      c->beta = bad ? 0.0 : rn / c->rho;
+      c->rho = rn;
+      c->k += 1;
+      c->cg_total += 1;
+      const int done = (bad || rn <= c->tol2 || c->k >= c->cg_max) ? 1 : 0;
+      c->done = done;
+      if (bad) host_store(&d.hs->numeric, 1);
+      if (done) host_store(&d.hs->cg_done_iter, c->iter);
+    }
+  }
+  if (threadIdx.x == 0) host_store(&d.hs->launch_seq, launch_id);
+}
+
+// KKT relative errors of the check iteration
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_fin_pres(Dev<VT> d, int nb, int iter, double bnorm, double cnorm,
+                                                     int has_soc) {
+  double t[2];
+  sum_partials<2>(d.partials, nb, t);
+  if (threadIdx.x == 0) {
+    Ctl* c = d.ctl;
+    const double* u = c->upd;
+    const double ctx = u[1], bty = t[1];
+    const double dx2 = u[4] + (has_soc ? c->cone[0] : 0.0);
+    const double dz2 = u[5] + (has_soc ? c->cone[1] : 0.0);
+    double e[8];
+    e[0] = sqrt(t[0]) / (1.0 + bnorm);
+    e[1] = sqrt(u[6]) / (1.0 + cnorm);
+    e[2] = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
+    e[3] = fmax(sqrt(dx2), sqrt(dz2)) / (1.0 + fmax(sqrt(u[2]), sqrt(u[3])));
+    e[4] = fmax(fmax(e[0], e[1]), fmax(e[2], e[3]));
+    e[5] = ctx;
+    e[6] = bty;
+    e[7] = u[0];
+    bool bad = false;
+    for (int i = 0; i < 8; ++i) {
+      c->kkt[i] = e[i];
+      d.hs->kkt[i] = e[i];
+      if (!(e[i] == e[i]) || isinf(e[i])) bad = true;
+    }
+    d.hs->cg_total = c->cg_total;
+    if (bad) host_store(&d.hs->numeric, 1);
+    __threadfence_system();
+    host_store(&d.hs->check_iter, iter);
+  }
+}
+
+// step 11: alpha from the log range of the valid ratios
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_fin_cond(Dev<VT> d, int nb, double t_cap) {
+  double t[3];
+  sum_partials<3, true>(d.partials, nb, t);
+  if (threadIdx.x == 0) {
+    Ctl* c = d.ctl;
+    c->cond[0] = t[0];
+    c->cond[1] = t[1];
+    c->cond[2] = t[2];
+    const double span = -t[1] - t[0];
+    c->cond[3] = (t[2] < 0.0 && span > 0.0) ? fmin(1.0, t_cap / span) : 1.0;
   }
 }
 
@@ -728,7 +750,9 @@ void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool 
   const dim3 g(d.t_nblk), b(kBlock);
   if (mode == UPD_PROLOGUE) {
     hipLaunchKernelGGL((k_update<VT, UPD_PROLOGUE, false>), g, b, 0, st, d, s_cur, s_new);
-  } else if (mode == UPD_UPDATE) {
+    return;
+  }
+  if (mode == UPD_UPDATE) {
     if (check)
       hipLaunchKernelGGL((k_update<VT, UPD_UPDATE, true>), g, b, 0, st, d, s_cur, s_new);
     else
@@ -739,19 +763,26 @@ void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool 
     else
       hipLaunchKernelGGL((k_update<VT, UPD_UPDATE_ONLY, false>), g, b, 0, st, d, s_cur, s_new);
   }
+  hipLaunchKernelGGL((k_fin_upd<VT>), dim3(1), b, 0, st, d, d.t_nblk);
 }
 
 template <typename VT>
 void launch_cone(const Dev<VT>& d, const VT* s, bool check, bool next, int group, hipStream_t st) {
   if (d.n_soc == 0) return;
   const int gpb = kBlock / group;
-  hipLaunchKernelGGL((k_cone<VT>), dim3(ceil_div(d.n_soc, gpb)), dim3(kBlock), 0, st, d, s, int(check), int(next),
-                     group);
+  const int nb = ceil_div(d.n_soc, gpb);
+  hipLaunchKernelGGL((k_cone<VT>), dim3(nb), dim3(kBlock), 0, st, d, s, int(check), int(next), group);
+  if (check) hipLaunchKernelGGL((k_fin_cone<VT>), dim3(1), dim3(kBlock), 0, st, d, nb);
 }
 
 template <typename VT>
-void launch_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st) {
-  hipLaunchKernelGGL((k_resid<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, iter, red2, abs2);
+void launch_resid(const Dev<VT>& d, hipStream_t st) {
+  hipLaunchKernelGGL((k_resid<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+}
+
+template <typename VT>
+void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st) {
+  hipLaunchKernelGGL((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, iter, red2, abs2);
 }
 
 template <typename VT>
@@ -760,19 +791,33 @@ void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
 }
 
 template <typename VT>
-void launch_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, launch_id);
+void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st) {
+  hipLaunchKernelGGL((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.t_nblk);
+}
+
+template <typename VT>
+void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+}
+
+template <typename VT>
+void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
+  hipLaunchKernelGGL((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, launch_id);
 }
 
 template <typename VT>
 void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st) {
-  hipLaunchKernelGGL((k_pres<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, iter, bnorm, cnorm, int(d.n_soc > 0));
+  hipLaunchKernelGGL((k_pres<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL((k_fin_pres<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, iter, bnorm, cnorm,
+                     int(d.n_soc > 0));
 }
 
 template <typename VT>
 void launch_cond_ratio(const Dev<VT>& d, const VT* s_prev, const VT* s_cur, double t_cap, hipStream_t st) {
   const int units = d.n_orth + d.n_soc;
-  hipLaunchKernelGGL((k_cond_ratio<VT>), dim3(ceil_div(units, kBlock)), dim3(kBlock), 0, st, d, s_prev, s_cur, t_cap);
+  const int nb = ceil_div(units, kBlock);
+  hipLaunchKernelGGL((k_cond_ratio<VT>), dim3(nb), dim3(kBlock), 0, st, d, s_prev, s_cur);
+  hipLaunchKernelGGL((k_fin_cond<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, t_cap);
 }
 
 template <typename VT>
@@ -805,9 +850,12 @@ void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
 #define ACS_INSTANTIATE(VT)                                                                            \
   template void launch_update<VT>(const Dev<VT>&, const VT*, VT*, int, bool, hipStream_t);            \
   template void launch_cone<VT>(const Dev<VT>&, const VT*, bool, bool, int, hipStream_t);            \
-  template void launch_resid<VT>(const Dev<VT>&, int, double, double, hipStream_t);                   \
+  template void launch_resid<VT>(const Dev<VT>&, hipStream_t);                                        \
+  template void launch_fin_resid<VT>(const Dev<VT>&, int, double, double, hipStream_t);               \
   template void launch_cg_t<VT>(const Dev<VT>&, hipStream_t);                                         \
-  template void launch_cg_a<VT>(const Dev<VT>&, long long, hipStream_t);                              \
+  template void launch_fin_cg_t<VT>(const Dev<VT>&, hipStream_t);                                     \
+  template void launch_cg_a<VT>(const Dev<VT>&, hipStream_t);                                         \
+  template void launch_fin_cg_a<VT>(const Dev<VT>&, long long, hipStream_t);                          \
   template void launch_pres<VT>(const Dev<VT>&, int, double, double, hipStream_t);                    \
   template void launch_cond_ratio<VT>(const Dev<VT>&, const VT*, const VT*, double, hipStream_t);     \
   template void launch_cond_scale<VT>(const Dev<VT>&, VT*, hipStream_t);                              \

@@ -32,11 +32,6 @@ namespace acs {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-struct AcsError : std::runtime_error {
-  int code;
-  AcsError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
-
 #define HIP_CHECK(expr)                                                                                     \
   do {                                                                                                      \
     hipError_t e_ = (expr);                                                                                 \
@@ -63,7 +58,7 @@ struct Schedule {
   }
 };
 
-static acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
+acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
   acs_settings s = in;
   if (s.auto_params) {
     if (p.is_socp()) {
@@ -144,7 +139,7 @@ class InstanceBase {
   acs_settings S{};
 };
 
-enum KClass { KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_N = 7 };
+enum KClass { KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_FIN = 7, KC_N = 8 };
 
 template <typename VT>
 class Instance final : public InstanceBase {
@@ -457,8 +452,10 @@ class Instance final : public InstanceBase {
       const int c = std::min(chunk, S.cg_max - launched);
       for (int i = 0; i < c; ++i) {
         timed(KC_CG_T, [&] { launch_cg_t(d_, st_); });
+        timed(KC_FIN, [&] { launch_fin_cg_t(d_, st_); });
+        timed(KC_CG_A, [&] { launch_cg_a(d_, st_); });
         const long long id = ++launch_id_;
-        timed(KC_CG_A, [&] { launch_cg_a(d_, id, st_); });
+        timed(KC_FIN, [&] { launch_fin_cg_a(d_, id, st_); });
       }
       launched += c;
       if (launched >= S.cg_max) break;
@@ -510,7 +507,8 @@ class Instance final : public InstanceBase {
       }
       const int l = l_ + 1;
       if (sched_.contains(l)) condition();
-      timed(KC_RESID, [&] { launch_resid(d_, l, red2, abs2, st_); });
+      timed(KC_RESID, [&] { launch_resid(d_, st_); });
+      timed(KC_FIN, [&] { launch_fin_resid(d_, l, red2, abs2, st_); });
       run_cg(l);
       const bool next_event = sched_.contains(l + 1);
       bool check = (l % S.check_every == 0) || it == iters - 1;
@@ -634,7 +632,7 @@ static std::unique_ptr<InstanceBase> make_instance(std::shared_ptr<const Problem
 static int g_device = -1;
 static std::mutex g_init_mu;
 
-static void ensure_device() {
+void ensure_device() {
   std::lock_guard<std::mutex> lk(g_init_mu);
   if (g_device >= 0) {
     HIP_CHECK(hipSetDevice(g_device));
@@ -661,29 +659,9 @@ static void ensure_device() {
 // ============================================================================
 using namespace acs;
 
-struct acs_problem {
-  std::shared_ptr<const Problem> p;
-};
 struct acs_state {
   std::unique_ptr<InstanceBase> inst;
 };
-
-template <class F>
-static int guarded(F&& f) {
-  try {
-    f();
-    return ACS_OK;
-  } catch (const AcsError& e) {
-    set_error(e.what());
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return ACS_ERR_NOMEM;
-  } catch (const std::exception& e) {
-    set_error(e.what());
-    return ACS_ERR_DEVICE;
-  }
-}
 
 extern "C" {
 

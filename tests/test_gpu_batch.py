@@ -1,0 +1,94 @@
+"""GPU tests of the persistent batched solver (acs_batch_*): every instance's
+KKT error recomputed by the FP64 oracle, objectives against the planted
+optimum and the one-instance solver, resumable runs and HIP-graph replays
+bitwise equal to one eager run, and the lanes-per-row autotuner."""
+import numpy as np
+import pytest
+
+from oracle.kkt import kkt_errors
+from paper_2103_00736_amd import acs, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert acs.lib().acs_init(0) == acs.ACS_OK, acs.lib().acs_last_error()
+
+
+def _mixed_set(k=24):
+    """Uneven small LPs of the batch recipe (smaller m to keep the oracle quick)
+    plus small SOCPs, and degenerate shapes (1-row, empty rows/columns)."""
+    probs = []
+    sizes = np.random.default_rng(5).integers(50, 400, size=k)
+    for i, m in enumerate(sizes):
+        probs.append(synth.config3(i, m=int(m)))
+    for i in range(4):
+        probs.append(synth.socp_percol(60 + 20 * i, 200 + 50 * i, 3, 100 + i, 3, 12, 0.8, name=f"socp{i}"))
+    probs.append(synth.lp_uniform(1, 4, 3, 7, name="one_row"))
+    probs.append(synth.lp_uniform(50, 125, 62, 8, name="sparse_empty"))
+    return probs
+
+
+def test_batch_matches_oracle_and_single_solver():
+    probs = _mixed_set()
+    handles = [acs.Problem.from_synth(p) for p in probs]
+    b = acs.Batch(handles, eps_kkt=1e-4, max_iter=20000)
+    ms = b.run(20000)
+    print(f"batch of {len(probs)}: {ms:.1f} ms")
+    for i, p in enumerate(probs):
+        x, y, z, info = b.result(i)
+        rec = kkt_errors(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, x, y, z)
+        obj_err = abs(rec["pobj"] - p.p_star) / (1 + abs(p.p_star))
+        print(f"  {p.name}: status={info.status} it={info.iterations} gpu_kkt={info.kkt:.2e} "
+              f"oracle_kkt={rec['kkt']:.2e} obj_err={obj_err:.1e}")
+        assert info.status == acs.SOLVED, p.name
+        assert rec["kkt"] <= 1.05e-4, p.name
+        assert abs(info.kkt - rec["kkt"]) <= 1e-6 + 1e-2 * rec["kkt"]
+        assert obj_err <= 5e-4, p.name
+    # alone (one-instance kernels) vs in the batch: same optimum within tolerance
+    for i in (0, 5, len(probs) - 3):
+        p = probs[i]
+        x1, y1, z1, info1 = acs.solve(handles[i], eps_kkt=1e-4)
+        _, _, _, info2 = b.result(i)
+        assert abs(info1.pobj - info2.pobj) <= 5e-4 * (1 + abs(p.p_star))
+
+
+def test_resume_and_graph_replays_are_bitwise_equal():
+    probs = [synth.config3(i, m=int(m)) for i, m in enumerate([300, 120, 80, 200, 60, 150])]
+    handles = [acs.Problem.from_synth(p) for p in probs]
+    ref = acs.Batch(handles, max_iter=3000)
+    ref.run(3000, use_graph=False)
+    chunks = acs.Batch(handles, max_iter=3000)
+    for rep in range(60):  # graph replays with host work and syncs in between
+        chunks.run(50, use_graph=True)
+        _ = chunks.result(rep % len(probs))
+    eager = acs.Batch(handles, max_iter=3000)
+    for _ in range(60):
+        eager.run(50, use_graph=False)
+    for i in range(len(probs)):
+        a, b_, c = ref.result(i), chunks.result(i), eager.result(i)
+        for k in range(3):
+            assert np.array_equal(a[k], b_[k]), (i, k)
+            assert np.array_equal(a[k], c[k]), (i, k)
+        assert a[3].iterations == b_[3].iterations == c[3].iterations
+
+
+def test_autotune_and_cache(tmp_path):
+    probs = [synth.config3(i, m=int(m)) for i, m in enumerate([400, 420, 60, 70, 1000])]
+    handles = [acs.Problem.from_synth(p) for p in probs]
+    cache = str(tmp_path / "tune.txt")
+    b = acs.Batch(handles, max_iter=5000)
+    b.autotune(sample=2, iters=10, cache_path=cache)
+    lanes = [b.lanes(i) for i in range(len(probs))]
+    assert all(g in (1, 2, 4, 8, 16, 32, 64) for pair in lanes for g in pair)
+    text = open(cache).read()
+    assert text.startswith("gfx950")
+    b.run(5000)
+    for i, p in enumerate(probs):
+        x, y, z, info = b.result(i)
+        rec = kkt_errors(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, x, y, z)
+        assert info.status == acs.SOLVED and rec["kkt"] <= 1.05e-4
+    b2 = acs.Batch(handles, max_iter=5000)
+    b2.autotune(sample=2, iters=10, cache_path=cache)  # served from the cache
+    assert [b2.lanes(i) for i in range(len(probs))] == lanes
