@@ -13,11 +13,14 @@ one GPU.
 """
 import argparse
 import hashlib
+import threading
 import json
 import os
 import subprocess
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -34,6 +37,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--workload", choices=["lp2m", "batch", "serve"], default="lp2m",
+                    help="lp2m: iterations/s on the 2M-variable LP (default); batch: 4096 small LPs in one "
+                         "persistent launch; serve: Poisson request stream through the serving loop")
+    ap.add_argument("--count", type=int, default=4096, help="batch: number of instances")
+    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (requests/s)")
     return ap.parse_args()
 
 
@@ -45,6 +54,17 @@ def cpu_child(args):
     from oracle.alg2 import Algorithm2, default_parameters
     from paper_2103_00736_amd import synth
 
+    if args.workload == "batch":  # whole solves of a seeded subset, one at a time
+        idx = np.random.default_rng(1).choice(args.count, size=6, replace=False)
+        t0 = time.perf_counter()
+        for i in idx:
+            q = synth.config3(int(i))
+            t, L = default_parameters(q.soc_sizes)
+            Algorithm2(q.scipy_csr(), q.b, q.c, q.n_orth, q.soc_sizes, mu=1.0, t=t, schedule=L).run(
+                20000, eps=1e-4, check_every=10)
+        dt = time.perf_counter() - t0
+        print(json.dumps({"iters": len(idx), "seconds": dt, "pcg_iters": 0, "what": "solves"}), flush=True)
+        return
     p = synth.config1(scale=args.scale)
     t, L = default_parameters(p.soc_sizes)
     alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
@@ -57,7 +77,7 @@ def cpu_child(args):
 
 def start_cpu_baseline(args):
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--scale", str(args.scale),
-           "--cpu-iters", str(args.cpu_iters)]
+           "--cpu-iters", str(args.cpu_iters), "--workload", args.workload, "--count", str(args.count)]
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env, cwd=ROOT)
 
@@ -72,6 +92,10 @@ def finish_cpu_baseline(proc, timeout_s=600):
         sys.stderr.write(err[-2000:])
         return None
     r = json.loads(out.strip().splitlines()[-1])
+    if r.get("what") == "solves":
+        return {"value": r["iters"] / r["seconds"], "unit": "solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"{r['iters']} seeded instances of the batch recipe solved one at a time to 1e-4 KKT by "
+                          f"the FP64 oracle (dense Cholesky projections), {r['seconds']:.1f} s"}
     return {
         "value": r["iters"] / r["seconds"], "unit": "iters/s", "cores": 1, "kind": "oracle",
         "sample": (f"first {r['iters']} outer iteration(s) of the FP64 oracle (Algorithm 2 step by step, "
@@ -113,7 +137,11 @@ def main():
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
-    cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline(args)
+    cpu_proc = None if (args.no_cpu_baseline or args.workload == "serve") else start_cpu_baseline(args)
+    if args.workload == "batch":
+        return bench_batch(args, cpu_proc)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     from paper_2103_00736_amd import acs, synth
 
@@ -185,6 +213,132 @@ def main():
             "timed_s": elapsed, "gen_s": gen_s,
         },
     }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _base_line(metric, value, unit, config, steps=1, ms=None):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": 0,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": config}
+
+
+def bench_batch(args, cpu_proc):
+    """4096 small LPs (m ~ U{50..2000}, n = 2.5m, 1% density) in one persistent launch."""
+    from paper_2103_00736_amd import acs, synth
+
+    assert acs.lib().acs_init(0) == 0
+    t0 = time.perf_counter()
+    probs = [synth.config3(i) for i in range(args.count)]
+    handles = [acs.Problem.from_synth(p) for p in probs]
+    gen_s = time.perf_counter() - t0
+    _progress(f"generated {len(probs)} instances in {gen_s:.1f} s")
+    b = acs.Batch(handles, eps_kkt=1e-4, max_iter=20000)
+    t1 = time.perf_counter()
+    b.autotune(sample=4, iters=20, cache_path=os.path.join("/tmp", "acs_lanes_gfx950.txt"))
+    tune_s = time.perf_counter() - t1
+    _progress(f"autotuned in {tune_s:.1f} s")
+    ms = b.run(20000)
+    _progress(f"batch launch {ms:.1f} ms")
+    infos = [b.result(i, xyz=False)[3] for i in range(len(probs))]
+    solved = sum(1 for f in infos if f.status == acs.SOLVED)
+    # algorithmic bytes moved by the launch (mixed precision: FP32 CG sweeps, FP64 residual/update sweeps)
+    byts = 0.0
+    for p, f in zip(probs, infos):
+        m, n, nnz = p.m, p.n, p.nnz
+        cg = (4 * (n + 1) + 8 * nnz + 4 * m + 8 * n) + (4 * (m + 1) + 8 * nnz + 4 * n + 32 * m)
+        it = (4 * (m + 1) + 12 * nnz + 4 * n + 12 * m) + (4 * (n + 1) + 12 * nnz + 8 * m + 20 * n)
+        byts += f.cg_steps * cg + f.iterations * it
+    achieved = byts / (ms * 1e-3) / 1e9
+    # the plain one-instance GPU solver on a seeded subset, one at a time
+    sub = np.random.default_rng(2).choice(len(probs), size=24, replace=False)
+    t2 = time.perf_counter()
+    for i in sub:
+        acs.solve(handles[int(i)], eps_kkt=1e-4, max_iter=20000)
+    per = (time.perf_counter() - t2) / len(sub)
+    _progress(f"one-at-a-time sample {per * 1e3:.1f} ms per solve")
+    value = len(probs) / (ms * 1e-3)
+    cpu = finish_cpu_baseline(cpu_proc) if cpu_proc else None
+    line = _base_line("batched solves/sec at 1e-4 KKT", value, "solves/s",
+                      {"workload": f"{len(probs)} planted sparse LPs, m~U{{50..2000}}, n=2.5m, 1% density, "
+                                   f"sum nnz={sum(p.nnz for p in probs)}, one persistent graph-launched kernel",
+                       "precision": "FP32 CG sweeps, FP64 residual/update sweeps and reductions"}, 1, ms)
+    line["roofline"] = {"bound": "hbm", "kernel": "k_batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "avg_launch_ms": ms, "launches": 1}
+    line["cpu_baseline"] = cpu
+    line["detail"] = {"solved": solved, "count": len(probs), "launch_ms": ms,
+                      "one_at_a_time_gpu_solves_per_s": 1.0 / per,
+                      "one_at_a_time_sample": f"{len(sub)} seeded instances solved sequentially by acs_solve",
+                      "speedup_vs_one_at_a_time": value * per, "max_gpu_kkt": max(f.kkt for f in infos),
+                      "mean_iterations": float(np.mean([f.iterations for f in infos])),
+                      "gen_s": gen_s, "autotune_s": tune_s}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_serve(args):
+    """Poisson request stream (70% LP / 30% SOCP, m log-uniform in [1e3, 2e5]) through the serving loop."""
+    from paper_2103_00736_amd import acs, synth
+
+    assert acs.lib().acs_init(0) == 0
+    trace = synth.config4_trace(args.requests, rate_per_s=args.rate)
+    t0 = time.perf_counter()
+    handles = []
+    for k, r in enumerate(trace):
+        handles.append(acs.Problem.from_synth(r.problem()))
+        if k % 25 == 0:
+            _progress(f"generated {k + 1}/{len(trace)} requests")
+    gen_s = time.perf_counter() - t0
+    srv = acs.Server(hbm_budget=160 << 30, max_slots=512, small_nnz=200_000, workers=3, tick_iters=50)
+    tickets = [None] * len(trace)
+    start = time.perf_counter()
+
+    def client():
+        for i, r in enumerate(trace):
+            delay = start + r.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = srv.submit(handles[i], eps_kkt=1e-4, max_iter=20000)
+
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    res = []
+    for i in range(len(trace)):
+        x, y, z, info = srv.wait(tickets[i], -1)
+        res.append(info)
+        if i % 25 == 0:
+            _progress(f"request {i} done, latency {info.latency_ms:.0f} ms")
+    end = time.perf_counter()
+    warm = max(1, len(trace) // 10)
+    lat = np.array([f.latency_ms for f in res[warm:]])
+    solved = sum(1 for f in res if f.status == acs.SOLVED)
+    value = len(res) / (end - start)
+    st = srv.stats()
+    srv.close()
+    sub = list(range(0, len(trace), max(1, len(trace) // 12)))[:12]
+    t2 = time.perf_counter()
+    for i in sub:
+        acs.solve(handles[i], eps_kkt=1e-4, max_iter=20000)
+    per = (time.perf_counter() - t2) / len(sub)
+    line = _base_line("served solves/sec and latency at 1e-4 KKT", value, "solves/s",
+                      {"workload": f"{len(trace)} requests, Poisson {args.rate:g}/s, 70% LP / 30% SOCP, "
+                                   f"m log-uniform [1e3, 2e5], n=3m, 6 nnz/column, SOC sizes U{{3..30}}",
+                       "server": "small_nnz=200k pool (persistent kernel ticks of 50 iterations) + 3 worker streams"},
+                      len(res), 1e3 * (end - start) / len(res))
+    line["roofline"] = None
+    line["cpu_baseline"] = None
+    line["detail"] = {"p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+                      "mean_queue_ms": float(np.mean([f.queue_ms for f in res[warm:]])), "solved": solved,
+                      "offered_rate": args.rate, "makespan_s": end - start,
+                      "one_at_a_time_gpu_solves_per_s": 1.0 / per,
+                      "one_at_a_time_sample": f"{len(sub)} requests of the trace solved sequentially by acs_solve",
+                      "peak_resident": st["peak_running"], "pool_ticks": st["ticks"], "gen_s": gen_s}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -104,7 +104,9 @@ typedef struct acs_info {
   double setup_ms;      /* upload + setup                                      */
   double alpha;         /* exponent of the last conditioning (step 11)         */
   double o_range;       /* log(max O) - log(min O) after the last conditioning */
-  double reserved[6];
+  double queue_ms;      /* server: submit -> admission                         */
+  double latency_ms;    /* server: submit -> result ready                      */
+  double reserved[4];
 } acs_info;
 
 typedef struct acs_problem acs_problem;
@@ -216,6 +218,45 @@ int acs_batch_lanes(acs_batch* b, int32_t i, int32_t* g_a, int32_t* g_t);
  * x[i], y[i], z[i] are per-instance host buffers (the arrays may be NULL). */
 int acs_batch_solve(int32_t count, const acs_problem* const* probs, const acs_settings* s, double* const* x,
                     double* const* y, double* const* z, acs_info* infos, void* stream);
+
+/*
+ * Serving loop (continuous batching), thread-safe.  Requests are admitted in
+ * arrival order while fewer than max_slots are resident and their device
+ * footprint fits hbm_budget bytes; each stays resident (iterates, scalings,
+ * scaled matrix) until it finishes.  Requests with nnz <= small_nnz share a
+ * slot pool advanced by one persistent batch-kernel launch per tick
+ * (tick_iters iterations per tick; new requests join at the next tick);
+ * larger ones run the one-instance kernels on `workers` streams (1..8)
+ * concurrently.  A result does not depend on the other resident requests.
+ * A request whose footprint exceeds the budget fails at submit with
+ * ACS_ERR_NOMEM.
+ */
+typedef struct acs_server acs_server;
+typedef struct acs_server_counters {
+  int64_t queued;        /* waiting for admission                     */
+  int64_t running;       /* resident                                  */
+  int64_t completed;     /* finished (including cancelled)            */
+  int64_t bytes_in_use;  /* device bytes reserved by resident requests */
+  int64_t ticks;         /* pool launches so far                      */
+  int64_t peak_running;
+  int64_t reserved[2];
+} acs_server_counters;
+int acs_server_create(int64_t hbm_budget, int32_t max_slots, int64_t small_nnz, int32_t workers, int32_t tick_iters,
+                      acs_server** out);
+/* Stops the loop; unfinished requests are dropped. */
+void acs_server_destroy(acs_server* srv);
+/* Queue a solve of p (the problem handle may be destroyed afterwards). */
+int acs_server_submit(acs_server* srv, const acs_problem* p, const acs_settings* s, uint64_t* ticket);
+/* ACS_PENDING while unfinished; ACS_OK copies x, z (n), y (m) and info (any
+ * may be NULL) and releases the ticket. */
+int acs_server_poll(acs_server* srv, uint64_t ticket, double* x, double* y, double* z, acs_info* info);
+/* As poll, blocking up to timeout_ms (< 0: no limit). */
+int acs_server_wait(acs_server* srv, uint64_t ticket, int32_t timeout_ms, double* x, double* y, double* z,
+                    acs_info* info);
+/* Queued or pooled requests stop at once; a request on a worker stream is
+ * marked and reported ACS_CANCELLED when it returns. */
+int acs_server_cancel(acs_server* srv, uint64_t ticket);
+int acs_server_stats(acs_server* srv, acs_server_counters* st);
 
 #ifdef __cplusplus
 }

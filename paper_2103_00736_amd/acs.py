@@ -34,6 +34,8 @@ EXPORTED = [
     "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
     "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_batch_create", "acs_batch_destroy",
     "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_lanes", "acs_batch_solve",
+    "acs_server_create", "acs_server_destroy", "acs_server_submit", "acs_server_poll", "acs_server_wait",
+    "acs_server_cancel", "acs_server_stats",
 ]
 
 
@@ -61,11 +63,18 @@ class Info(ctypes.Structure):
         ("eps_p", ctypes.c_double), ("eps_d", ctypes.c_double), ("eps_gap", ctypes.c_double),
         ("eps_cone", ctypes.c_double), ("kkt", ctypes.c_double), ("pobj", ctypes.c_double),
         ("dobj", ctypes.c_double), ("solve_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
-        ("alpha", ctypes.c_double), ("o_range", ctypes.c_double), ("reserved", ctypes.c_double * 6),
+        ("alpha", ctypes.c_double), ("o_range", ctypes.c_double), ("queue_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double), ("reserved", ctypes.c_double * 4),
     ]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("running", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_int64), ("ticks", ctypes.c_int64), ("peak_running", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 2)]
 
 
 _lib = None
@@ -113,6 +122,14 @@ def lib() -> ctypes.CDLL:
         "acs_batch_solve": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(Settings),
                                            ctypes.POINTER(DP), ctypes.POINTER(DP), ctypes.POINTER(DP),
                                            ctypes.POINTER(Info), P]),
+        "acs_server_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.POINTER(P)]),
+        "acs_server_destroy": (None, [P]),
+        "acs_server_submit": (ctypes.c_int, [P, P, ctypes.POINTER(Settings), ctypes.POINTER(ctypes.c_uint64)]),
+        "acs_server_poll": (ctypes.c_int, [P, ctypes.c_uint64, DP, DP, DP, ctypes.POINTER(Info)]),
+        "acs_server_wait": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.c_int32, DP, DP, DP, ctypes.POINTER(Info)]),
+        "acs_server_cancel": (ctypes.c_int, [P, ctypes.c_uint64]),
+        "acs_server_stats": (ctypes.c_int, [P, ctypes.POINTER(ServerStats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -310,6 +327,61 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().acs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (acs_server)."""
+
+    def __init__(self, hbm_budget: int = 64 << 30, max_slots: int = 256, small_nnz: int = 200_000, workers: int = 3,
+                 tick_iters: int = 50):
+        h = P()
+        _check(lib().acs_server_create(int(hbm_budget), int(max_slots), int(small_nnz), int(workers),
+                                       int(tick_iters), ctypes.byref(h)))
+        self.handle = h
+        self._shapes = {}
+
+    def submit(self, problem: Problem, settings: Optional[Settings] = None, **kw) -> int:
+        if settings is None:
+            settings = default_settings(**kw)
+        t = ctypes.c_uint64()
+        _check(lib().acs_server_submit(self.handle, problem.handle, ctypes.byref(settings), ctypes.byref(t)))
+        self._shapes[t.value] = (problem.m, problem.n)
+        return t.value
+
+    def _fetch(self, fn, ticket, *extra):
+        m, n = self._shapes[ticket]
+        x, z, y = np.empty(n), np.empty(n), np.empty(m)
+        info = Info()
+        rc = _check(fn(self.handle, ctypes.c_uint64(ticket), *extra, _dptr(x), _dptr(y), _dptr(z), ctypes.byref(info)))
+        if rc == ACS_PENDING:
+            return None
+        del self._shapes[ticket]
+        return x, y, z, info
+
+    def poll(self, ticket: int):
+        return self._fetch(lib().acs_server_poll, ticket)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        return self._fetch(lib().acs_server_wait, ticket, ctypes.c_int32(timeout_ms))
+
+    def cancel(self, ticket: int):
+        _check(lib().acs_server_cancel(self.handle, ctypes.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().acs_server_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_ if k != "reserved"}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().acs_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -61,6 +61,23 @@ struct BInst {
   double kkt[8];    // eps_p, eps_d, eps_gap, eps_cone, kkt, pobj, dobj, alpha
 };
 
+// Byte offsets of one instance's arrays inside an arena (256-B aligned).
+struct InstLayout {
+  size_t a_rp, a_col, a_orig, t_rp, t_col, t_perm, soc_off, b, c, const_end;
+  size_t a_val, a_val64, t_val, t_val64, O, chat, dsq, dinv, bs, w, s0, s1, p, v, t, r, q, zt, x, y, z, xhat, ounit;
+  size_t end;
+};
+// Lay out one instance starting at byte `base`.
+InstLayout layout_instance(const Problem& p, size_t base);
+// Copy the constant arrays (pattern, values, b, c, cones) into the arena.
+void upload_instance_const(char* d_arena, const InstLayout& o, const Problem& p, hipStream_t st);
+// Descriptor with device pointers, settings and the initial state (x = z = e_K, O = 1, w = 0);
+// uploads the initial vectors.
+void init_instance_state(BInst& I, char* d_arena, const InstLayout& o, const Problem& p, const acs_settings& s,
+                         int g_a, int g_t, hipStream_t st);
+// Lanes per row: next power of two of the mean row length, in [1, 64].
+int default_lanes(double mean_row);
+
 // Launch the persistent kernel over `count` descriptors; `order` lists
 // descriptor indices in the order workgroups take them; every instance runs
 // until solved or until `iter_budget` more iterations (resumable).

@@ -43,6 +43,153 @@ static int size_class(const Problem& p) {
   return ca * 8 + ct;
 }
 
+
+int default_lanes(double mean_row) { return pow2_at_least(mean_row, 1, 64); }
+
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+InstLayout layout_instance(const Problem& p, size_t base) {
+  InstLayout o;
+  size_t off = base;
+  const size_t m = p.m, n = p.n, nnz = p.nnz, units = size_t(p.n_orth) + p.soc_size.size();
+  auto take = [&](size_t bytes) {
+    const size_t r = off;
+    off += al256(std::max<size_t>(bytes, 4));
+    return r;
+  };
+  o.a_rp = take(4 * (m + 1));
+  o.a_col = take(4 * nnz);
+  o.a_orig = take(8 * nnz);
+  o.t_rp = take(4 * (n + 1));
+  o.t_col = take(4 * nnz);
+  o.t_perm = take(4 * nnz);
+  o.soc_off = take(4 * (p.soc_off.size()));
+  o.b = take(8 * m);
+  o.c = take(8 * n);
+  o.const_end = off;
+  o.a_val = take(4 * nnz);
+  o.a_val64 = take(8 * nnz);
+  o.t_val = take(4 * nnz);
+  o.t_val64 = take(8 * nnz);
+  o.O = take(8 * n);
+  o.chat = take(8 * n);
+  o.dsq = take(8 * m);
+  o.dinv = take(8 * m);
+  o.bs = take(8 * m);
+  o.w = take(8 * m);
+  o.s0 = take(4 * n);
+  o.s1 = take(4 * n);
+  o.p = take(4 * n);
+  o.v = take(4 * n);
+  o.t = take(4 * n);
+  o.r = take(4 * m);
+  o.q = take(4 * m);
+  o.zt = take(8 * n);
+  o.x = take(8 * n);
+  o.y = take(8 * m);
+  o.z = take(8 * n);
+  o.xhat = take(8 * n);
+  o.ounit = take(8 * units);
+  o.end = off;
+  return o;
+}
+
+void upload_instance_const(char* d_arena, const InstLayout& o, const Problem& p, hipStream_t st) {
+  const size_t base = o.a_rp, len = o.const_end - o.a_rp;
+  std::vector<char> stage(len, 0);
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(stage.data() + (at - base), src, bytes);
+  };
+  put(o.a_rp, p.row_ptr.data(), 4 * p.row_ptr.size());
+  put(o.a_col, p.col.data(), 4 * p.col.size());
+  put(o.a_orig, p.val.data(), 8 * p.val.size());
+  put(o.t_rp, p.t_row_ptr.data(), 4 * p.t_row_ptr.size());
+  put(o.t_col, p.t_col.data(), 4 * p.t_col.size());
+  put(o.t_perm, p.t_perm.data(), 4 * p.t_perm.size());
+  put(o.soc_off, p.soc_off.data(), 4 * p.soc_off.size());
+  put(o.b, p.b.data(), 8 * p.b.size());
+  put(o.c, p.c.data(), 8 * p.c.size());
+  BHIP(hipMemcpyAsync(d_arena + base, stage.data(), len, hipMemcpyHostToDevice, st));
+  BHIP(hipStreamSynchronize(st));
+}
+
+void init_instance_state(BInst& I, char* B, const InstLayout& o, const Problem& p, const acs_settings& s, int g_a,
+                         int g_t, hipStream_t st) {
+  std::memset(&I, 0, sizeof(I));
+  I.m = p.m;
+  I.n = p.n;
+  I.nnz = int32_t(p.nnz);
+  I.n_orth = p.n_orth;
+  I.n_soc = int32_t(p.soc_size.size());
+  I.g_a = g_a;
+  I.g_t = g_t;
+  I.a_rp = reinterpret_cast<int32_t*>(B + o.a_rp);
+  I.a_col = reinterpret_cast<int32_t*>(B + o.a_col);
+  I.a_orig = reinterpret_cast<double*>(B + o.a_orig);
+  I.a_val = reinterpret_cast<float*>(B + o.a_val);
+  I.a_val64 = reinterpret_cast<double*>(B + o.a_val64);
+  I.t_rp = reinterpret_cast<int32_t*>(B + o.t_rp);
+  I.t_col = reinterpret_cast<int32_t*>(B + o.t_col);
+  I.t_perm = reinterpret_cast<int32_t*>(B + o.t_perm);
+  I.t_val = reinterpret_cast<float*>(B + o.t_val);
+  I.t_val64 = reinterpret_cast<double*>(B + o.t_val64);
+  I.soc_off = reinterpret_cast<int32_t*>(B + o.soc_off);
+  I.b = reinterpret_cast<double*>(B + o.b);
+  I.c = reinterpret_cast<double*>(B + o.c);
+  I.O = reinterpret_cast<double*>(B + o.O);
+  I.chat = reinterpret_cast<double*>(B + o.chat);
+  I.dsq = reinterpret_cast<double*>(B + o.dsq);
+  I.dinv = reinterpret_cast<double*>(B + o.dinv);
+  I.bs = reinterpret_cast<double*>(B + o.bs);
+  I.w = reinterpret_cast<double*>(B + o.w);
+  I.s_buf[0] = reinterpret_cast<float*>(B + o.s0);
+  I.s_buf[1] = reinterpret_cast<float*>(B + o.s1);
+  I.p = reinterpret_cast<float*>(B + o.p);
+  I.v = reinterpret_cast<float*>(B + o.v);
+  I.t = reinterpret_cast<float*>(B + o.t);
+  I.r = reinterpret_cast<float*>(B + o.r);
+  I.q = reinterpret_cast<float*>(B + o.q);
+  I.zt = reinterpret_cast<double*>(B + o.zt);
+  I.x = reinterpret_cast<double*>(B + o.x);
+  I.y = reinterpret_cast<double*>(B + o.y);
+  I.z = reinterpret_cast<double*>(B + o.z);
+  I.xhat = reinterpret_cast<double*>(B + o.xhat);
+  I.ounit = reinterpret_cast<double*>(B + o.ounit);
+  I.bnorm = p.bnorm;
+  I.cnorm = p.cnorm;
+  I.mu = s.mu;
+  I.t_cap = s.t;
+  I.eps = s.eps_kkt;
+  I.cg_red2 = s.cg_reduce * s.cg_reduce;
+  I.cg_abs2 = s.cg_abs * s.cg_abs;
+  I.l_first = s.l_first;
+  I.l_every = s.l_every;
+  I.l_last = s.l_last;
+  I.max_iter = s.max_iter;
+  I.check_every = s.check_every;
+  I.cg_max = s.cg_max;
+  I.l = 0;
+  I.cur = 0;
+  I.status = -1;
+  // s_buf[0] = s = (1-mu) e_K, s_buf[1] = s_prev = (1+mu) e_K, O = 1, w = 0, sqrt(D) = 1
+  std::vector<float> s0(p.n, 0.f), s1(p.n, 0.f);
+  for (int j = 0; j < p.n_orth; ++j) {
+    s0[j] = float(1.0 - s.mu);
+    s1[j] = float(1.0 + s.mu);
+  }
+  for (size_t c = 0; c < p.soc_size.size(); ++c) {
+    s0[p.soc_off[c]] = float(1.0 - s.mu);
+    s1[p.soc_off[c]] = float(1.0 + s.mu);
+  }
+  std::vector<double> ones_n(p.n, 1.0), ones_m(p.m, 1.0), zeros_m(p.m, 0.0);
+  BHIP(hipMemcpyAsync(I.s_buf[0], s0.data(), 4 * p.n, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(I.s_buf[1], s1.data(), 4 * p.n, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(I.O, ones_n.data(), 8 * p.n, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(I.dsq, ones_m.data(), 8 * p.m, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(I.w, zeros_m.data(), 8 * p.m, hipMemcpyHostToDevice, st));
+  BHIP(hipStreamSynchronize(st));
+}
+
 class Batch {
  public:
   Batch(std::vector<std::shared_ptr<const Problem>> probs, const acs_settings& s, hipStream_t stream)
@@ -62,8 +209,8 @@ class Batch {
     g_.resize(count);
     for (int i = 0; i < count; ++i) {
       const Problem& p = *probs_[i];
-      g_[i].first = pow2_at_least(double(p.nnz) / std::max(1, p.m), 1, 64);
-      g_[i].second = pow2_at_least(double(p.nnz) / std::max(1, p.n), 1, 64);
+      g_[i].first = default_lanes(double(p.nnz) / std::max(1, p.m));
+      g_[i].second = default_lanes(double(p.nnz) / std::max(1, p.n));
     }
     order_.resize(count);
     std::iota(order_.begin(), order_.end(), 0);
@@ -231,55 +378,14 @@ class Batch {
     return ms;
   }
 
-  static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
-
-  // Arena layout per instance; constant arrays are staged on the host.
+  // Arena layout of all instances; constant arrays are staged per instance.
   void layout_and_upload() {
     const int count = int(probs_.size());
     offs_.resize(count);
     size_t off = 0;
     for (int i = 0; i < count; ++i) {
-      const Problem& p = *probs_[i];
-      Offs& o = offs_[i];
-      const size_t m = p.m, n = p.n, nnz = p.nnz, units = size_t(p.n_orth) + p.soc_size.size();
-      auto take = [&](size_t bytes) {
-        const size_t r = off;
-        off += al(std::max<size_t>(bytes, 4));
-        return r;
-      };
-      o.a_rp = take(4 * (m + 1));
-      o.a_col = take(4 * nnz);
-      o.a_orig = take(8 * nnz);
-      o.t_rp = take(4 * (n + 1));
-      o.t_col = take(4 * nnz);
-      o.t_perm = take(4 * nnz);
-      o.soc_off = take(4 * (p.soc_off.size()));
-      o.b = take(8 * m);
-      o.c = take(8 * n);
-      o.const_end = off;
-      o.a_val = take(4 * nnz);
-      o.a_val64 = take(8 * nnz);
-      o.t_val = take(4 * nnz);
-      o.t_val64 = take(8 * nnz);
-      o.O = take(8 * n);
-      o.chat = take(8 * n);
-      o.dsq = take(8 * m);
-      o.dinv = take(8 * m);
-      o.bs = take(8 * m);
-      o.w = take(8 * m);
-      o.s0 = take(4 * n);
-      o.s1 = take(4 * n);
-      o.p = take(4 * n);
-      o.v = take(4 * n);
-      o.t = take(4 * n);
-      o.r = take(4 * m);
-      o.q = take(4 * m);
-      o.zt = take(8 * n);
-      o.x = take(8 * n);
-      o.y = take(8 * m);
-      o.z = take(8 * n);
-      o.xhat = take(8 * n);
-      o.ounit = take(8 * units);
+      offs_[i] = layout_instance(*probs_[i], off);
+      off = offs_[i].end;
     }
     bytes_ = off;
     hipError_t e = hipMalloc(&d_arena_, std::max<size_t>(bytes_, 256));
@@ -288,111 +394,14 @@ class Batch {
       throw AcsError(ACS_ERR_NOMEM, "batch arena of " + std::to_string(bytes_) + " bytes does not fit");
     }
     BHIP(hipMemset(d_arena_, 0, bytes_));
-    // constant arrays, one staged copy per instance
-    for (int i = 0; i < count; ++i) {
-      const Problem& p = *probs_[i];
-      const Offs& o = offs_[i];
-      const size_t base = o.a_rp, len = o.const_end - o.a_rp;
-      std::vector<char> stage(len, 0);
-      auto put = [&](size_t at, const void* src, size_t bytes) {
-        if (bytes) std::memcpy(stage.data() + (at - base), src, bytes);
-      };
-      put(o.a_rp, p.row_ptr.data(), 4 * p.row_ptr.size());
-      put(o.a_col, p.col.data(), 4 * p.col.size());
-      put(o.a_orig, p.val.data(), 8 * p.val.size());
-      put(o.t_rp, p.t_row_ptr.data(), 4 * p.t_row_ptr.size());
-      put(o.t_col, p.t_col.data(), 4 * p.t_col.size());
-      put(o.t_perm, p.t_perm.data(), 4 * p.t_perm.size());
-      put(o.soc_off, p.soc_off.data(), 4 * p.soc_off.size());
-      put(o.b, p.b.data(), 8 * p.b.size());
-      put(o.c, p.c.data(), 8 * p.c.size());
-      BHIP(hipMemcpyAsync(d_arena_ + base, stage.data(), len, hipMemcpyHostToDevice, st_));
-      BHIP(hipStreamSynchronize(st_));
-    }
+    for (int i = 0; i < count; ++i) upload_instance_const(d_arena_, offs_[i], *probs_[i], st_);
     host_inst_.resize(count);
     BHIP(hipMalloc(&d_inst_, sizeof(BInst) * std::max(count, 1)));
   }
 
-  // Initial state: x = z = e_K, O = 1, w = 0 (the first conditioning builds A_s).
   void init_instance(int i) {
-    const Problem& p = *probs_[i];
-    const Offs& o = offs_[i];
-    const acs_settings& s = settings_[i];
-    BInst& I = host_inst_[i];
-    std::memset(&I, 0, sizeof(I));
-    char* B = d_arena_;
-    I.m = p.m;
-    I.n = p.n;
-    I.nnz = int32_t(p.nnz);
-    I.n_orth = p.n_orth;
-    I.n_soc = int32_t(p.soc_size.size());
-    I.g_a = g_.empty() ? 1 : g_[i].first;
-    I.g_t = g_.empty() ? 1 : g_[i].second;
-    I.a_rp = reinterpret_cast<int32_t*>(B + o.a_rp);
-    I.a_col = reinterpret_cast<int32_t*>(B + o.a_col);
-    I.a_orig = reinterpret_cast<double*>(B + o.a_orig);
-    I.a_val = reinterpret_cast<float*>(B + o.a_val);
-    I.a_val64 = reinterpret_cast<double*>(B + o.a_val64);
-    I.t_rp = reinterpret_cast<int32_t*>(B + o.t_rp);
-    I.t_col = reinterpret_cast<int32_t*>(B + o.t_col);
-    I.t_perm = reinterpret_cast<int32_t*>(B + o.t_perm);
-    I.t_val = reinterpret_cast<float*>(B + o.t_val);
-    I.t_val64 = reinterpret_cast<double*>(B + o.t_val64);
-    I.soc_off = reinterpret_cast<int32_t*>(B + o.soc_off);
-    I.b = reinterpret_cast<double*>(B + o.b);
-    I.c = reinterpret_cast<double*>(B + o.c);
-    I.O = reinterpret_cast<double*>(B + o.O);
-    I.chat = reinterpret_cast<double*>(B + o.chat);
-    I.dsq = reinterpret_cast<double*>(B + o.dsq);
-    I.dinv = reinterpret_cast<double*>(B + o.dinv);
-    I.bs = reinterpret_cast<double*>(B + o.bs);
-    I.w = reinterpret_cast<double*>(B + o.w);
-    I.s_buf[0] = reinterpret_cast<float*>(B + o.s0);
-    I.s_buf[1] = reinterpret_cast<float*>(B + o.s1);
-    I.p = reinterpret_cast<float*>(B + o.p);
-    I.v = reinterpret_cast<float*>(B + o.v);
-    I.t = reinterpret_cast<float*>(B + o.t);
-    I.r = reinterpret_cast<float*>(B + o.r);
-    I.q = reinterpret_cast<float*>(B + o.q);
-    I.zt = reinterpret_cast<double*>(B + o.zt);
-    I.x = reinterpret_cast<double*>(B + o.x);
-    I.y = reinterpret_cast<double*>(B + o.y);
-    I.z = reinterpret_cast<double*>(B + o.z);
-    I.xhat = reinterpret_cast<double*>(B + o.xhat);
-    I.ounit = reinterpret_cast<double*>(B + o.ounit);
-    I.bnorm = p.bnorm;
-    I.cnorm = p.cnorm;
-    I.mu = s.mu;
-    I.t_cap = s.t;
-    I.eps = s.eps_kkt;
-    I.cg_red2 = s.cg_reduce * s.cg_reduce;
-    I.cg_abs2 = s.cg_abs * s.cg_abs;
-    I.l_first = s.l_first;
-    I.l_every = s.l_every;
-    I.l_last = s.l_last;
-    I.max_iter = s.max_iter;
-    I.check_every = s.check_every;
-    I.cg_max = s.cg_max;
-    I.l = 0;
-    I.cur = 0;
-    I.status = -1;
-    // s_buf[0] = s = (1-mu) e_K, s_buf[1] = s_prev = (1+mu) e_K, O = 1, w = 0, sqrt(D) = 1
-    std::vector<float> s0(p.n, 0.f), s1(p.n, 0.f);
-    for (int j = 0; j < p.n_orth; ++j) {
-      s0[j] = float(1.0 - s.mu);
-      s1[j] = float(1.0 + s.mu);
-    }
-    for (size_t c = 0; c < p.soc_size.size(); ++c) {
-      s0[p.soc_off[c]] = float(1.0 - s.mu);
-      s1[p.soc_off[c]] = float(1.0 + s.mu);
-    }
-    std::vector<double> ones_n(p.n, 1.0), ones_m(p.m, 1.0), zeros_m(p.m, 0.0);
-    BHIP(hipMemcpyAsync(I.s_buf[0], s0.data(), 4 * p.n, hipMemcpyHostToDevice, st_));
-    BHIP(hipMemcpyAsync(I.s_buf[1], s1.data(), 4 * p.n, hipMemcpyHostToDevice, st_));
-    BHIP(hipMemcpyAsync(I.O, ones_n.data(), 8 * p.n, hipMemcpyHostToDevice, st_));
-    BHIP(hipMemcpyAsync(I.dsq, ones_m.data(), 8 * p.m, hipMemcpyHostToDevice, st_));
-    BHIP(hipMemcpyAsync(I.w, zeros_m.data(), 8 * p.m, hipMemcpyHostToDevice, st_));
-    BHIP(hipStreamSynchronize(st_));
+    init_instance_state(host_inst_[i], d_arena_, offs_[i], *probs_[i], settings_[i], g_.empty() ? 1 : g_[i].first,
+                        g_.empty() ? 1 : g_[i].second, st_);
   }
 
   void upload_desc() {
@@ -442,15 +451,9 @@ class Batch {
     graph_budget_ = budget;
   }
 
-  struct Offs {
-    size_t a_rp, a_col, a_orig, t_rp, t_col, t_perm, soc_off, b, c, const_end;
-    size_t a_val, a_val64, t_val, t_val64, O, chat, dsq, dinv, bs, w, s0, s1, p, v, t, r, q, zt, x, y, z, xhat,
-        ounit;
-  };
-
   std::vector<std::shared_ptr<const Problem>> probs_;
   std::vector<acs_settings> settings_;
-  std::vector<Offs> offs_;
+  std::vector<InstLayout> offs_;
   std::vector<BInst> host_inst_;
   std::vector<std::pair<int, int>> g_;
   std::vector<int32_t> order_;

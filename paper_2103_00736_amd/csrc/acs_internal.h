@@ -66,6 +66,14 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p);
 // Select device 0 (gfx950) once per process.
 void ensure_device();
 
+// One-instance solve (the acs_solve path) on a given stream.
+struct SolveOut {
+  std::vector<double> x, y, z;
+  acs_info info;
+};
+SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream);
+int64_t instance_device_bytes(const Problem& p, int precision);
+
 template <class F>
 int guarded(F&& f) {
   try {

@@ -629,6 +629,20 @@ static std::unique_ptr<InstanceBase> make_instance(std::shared_ptr<const Problem
   return std::make_unique<Instance<float>>(std::move(p), s, st);
 }
 
+SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream) {
+  auto inst = make_instance(p, s, static_cast<hipStream_t>(stream));
+  inst->run(inst->S.max_iter, true);
+  SolveOut o;
+  o.x.resize(p->n);
+  o.z.resize(p->n);
+  o.y.resize(p->m);
+  inst->get(nullptr, nullptr, nullptr, nullptr, nullptr, o.x.data(), o.y.data(), o.z.data());
+  o.info = inst->info;
+  return o;
+}
+
+int64_t instance_device_bytes(const Problem& p, int precision) { return estimate_bytes(p, precision); }
+
 static int g_device = -1;
 static std::mutex g_init_mu;
 
