@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--workload", choices=["lp2m", "batch", "serve"], default="lp2m",
+    ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy"], default="lp2m",
                     help="lp2m: iterations/s on the 2M-variable LP (default); batch: 4096 small LPs in one "
                          "persistent launch; serve: Poisson request stream through the serving loop")
     ap.add_argument("--count", type=int, default=4096, help="batch: number of instances")
@@ -108,12 +108,15 @@ def finish_cpu_baseline(proc, timeout_s=600):
 # ----------------------------------------------------------------------------
 # algorithmic bytes per launch of the two CG kernels (value type bytes vt)
 # ----------------------------------------------------------------------------
-def kernel_bytes(m, n, nnz, vt=4):
-    # k_cg_a, rows of A_s: row_ptr, col+val, t gathered (each entry once), r q read+write, w (FP64) read+write
-    cg_a = 4 * (m + 1) + (4 + vt) * nnz + vt * n + m * (vt * 4 + 16)
+def kernel_bytes(m, n, nnz, vt=4, slices=8):
+    # k_cg_a_part, rows of the 8 column slices of A_s: 8 row pointers, col+val, t gathered (each entry
+    # once), 8 partial row-sum vectors written
+    cg_a = slices * 4 * (m + 1) + (4 + vt) * nnz + vt * n + slices * vt * m
     # k_cg_t, rows of A_s^T: row_ptr, col+val, r gathered (each entry once), t_old read + t write
     cg_t = 4 * (n + 1) + (4 + vt) * nnz + vt * m + 2 * vt * n
-    return {"cg_a": cg_a, "cg_t": cg_t}
+    # k_cg_a_comb: 8 partials read, r and q read + written, w (FP64) read + written
+    comb = slices * vt * m + 4 * vt * m + 16 * m
+    return {"cg_a": cg_a, "cg_t": cg_t, "cg_comb": comb}
 
 
 def traffic_record(kernel):
@@ -142,6 +145,8 @@ def main():
         return bench_batch(args, cpu_proc)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "copy":
+        return bench_copy()
 
     from paper_2103_00736_amd import acs, synth
 
@@ -172,7 +177,7 @@ def main():
     st.profile(False)
     cg_prof = st.info().cg_steps - cgp0
     cls = {"update": acs.KC_UPDATE, "resid": acs.KC_RESID, "cg_t": acs.KC_CG_T, "cg_a": acs.KC_CG_A,
-           "check": acs.KC_CHECK, "cond": acs.KC_COND, "fin": acs.KC_FIN}
+           "check": acs.KC_CHECK, "cond": acs.KC_COND, "fin": acs.KC_FIN, "cg_comb": acs.KC_CG_COMB}
     prof = {k: st.timing(v) for k, v in cls.items()}
     kb = kernel_bytes(p.m, p.n, p.nnz)
     dom = max(("cg_a", "cg_t"), key=lambda k: prof[k][1])
@@ -200,7 +205,7 @@ def main():
                                f"(Algorithm 2, mu=1, t=9.2, L={{300,400,...}}, iterations {args.warmup + 1}.."
                                f"{args.warmup + args.steps})",
                    "precision": "FP32 matrix/iterate/CG vectors, FP64 CG solution, residual sweeps and reductions"},
-        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": {"cg_a": "k_cg_a_part", "cg_t": "k_cg_t"}[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "launches": count, "active_launches": cg_prof,
                      "algorithmic_bytes_per_launch": kb[dom]},
@@ -214,6 +219,27 @@ def main():
         },
     }
     print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_copy():
+    """A plain device copy of exactly 1 GiB (torch), the calibration dispatch for HBM byte counters."""
+    import torch
+
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"metric": "copy GB/s (read+write)", "value": 2 * (1 << 30) / ms / 1e6, "unit": "GB/s",
+                      "bytes_each_way": 1 << 30, "ms": ms}), flush=True)
     return 0
 
 

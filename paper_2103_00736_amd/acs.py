@@ -26,7 +26,7 @@ SOLVED, MAX_ITER, NUMERIC, CANCELLED = 0, 1, 2, 3
 PREC_MIXED, PREC_FP64 = 0, 1
 
 # timing classes of acs_state_timing
-KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN = range(8)
+KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG_COMB = range(9)
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",

@@ -21,6 +21,7 @@ struct RowBlock {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kStageNnz = 2048;   // products staged in LDS per multi-row block
+constexpr int kSlices = 8;        // column slices of A, one per XCD
 
 // Host copy of a validated problem (Sec. II): CSR of A, b, c, cone list.
 struct Problem {
@@ -36,6 +37,12 @@ struct Problem {
   // pattern of A^T (CSR over columns of A): t_row_ptr (n+1), t_col (row of A), t_perm (index into val)
   std::vector<int32_t> t_row_ptr, t_col, t_perm;
   std::vector<RowBlock> a_blocks, t_blocks;
+  // A split by column ranges [x*w, (x+1)*w), w = ceil(n/kSlices): the nonzeros
+  // of slice x in row order; s_row_ptr holds kSlices row pointers of m+1
+  // absolute offsets; s_perm maps to the position in A's CSR.
+  std::vector<int32_t> s_row_ptr, s_col, s_perm;
+  std::vector<RowBlock> s_blocks;     // row blocks of every slice, slice after slice
+  std::vector<int32_t> s_blk_off;     // kSlices + 1 offsets into s_blocks
   double bnorm = 0, cnorm = 0;
   int32_t max_soc = 0;
   bool is_socp() const { return !soc_size.empty(); }
@@ -66,12 +73,51 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p);
 // Select device 0 (gfx950) once per process.
 void ensure_device();
 
+// First-fit sub-allocator over one device allocation (256-B granularity).
+// Serving uses it so that no hipMalloc/hipFree (hipFree waits for the whole
+// device) happens while requests run.  Thread-safe.
+class SubAllocator {
+ public:
+  explicit SubAllocator(size_t bytes);
+  ~SubAllocator();
+  void* alloc(size_t bytes);  // nullptr when no free range fits
+  void release(void* p);
+  size_t capacity() const { return size_; }
+
+ private:
+  struct Impl;
+  Impl* impl_;
+  char* base_ = nullptr;
+  size_t size_ = 0;
+};
+
+struct HostStatus;
+// Pinned, device-mapped host records for the kernels' progress reports.
+class StatusPool {
+ public:
+  explicit StatusPool(int count);
+  ~StatusPool();
+  HostStatus* take();  // nullptr when exhausted
+  void give(HostStatus* h);
+
+ private:
+  struct Impl;
+  Impl* impl_;
+};
+
+// Optional resources an instance draws on instead of allocating its own.
+struct InstanceResources {
+  SubAllocator* mem = nullptr;
+  StatusPool* status = nullptr;
+};
+
 // One-instance solve (the acs_solve path) on a given stream.
 struct SolveOut {
   std::vector<double> x, y, z;
   acs_info info;
 };
-SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream);
+SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream,
+                            const InstanceResources& res = InstanceResources());
 int64_t instance_device_bytes(const Problem& p, int precision);
 
 template <class F>

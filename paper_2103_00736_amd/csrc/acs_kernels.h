@@ -52,6 +52,7 @@ struct HostStatus {
 template <typename VT>
 struct Dev {
   int32_t m, n, n_orth, n_soc;
+  int32_t a_rp_nnz;  // nnz
   double mu;
   // CSR of A (rows i) and of A^T (rows j); *_val hold A_s, a_orig the problem's values
   const int32_t* a_rp;
@@ -66,6 +67,15 @@ struct Dev {
   // sweeps (iterative refinement of the FP32 CG); alias *_val when VT = double
   double* a_val64;
   double* t_val64;
+  // column slices of A (one per XCD) for the CG product A_s t
+  const int32_t* s_rp;     // kSlices x (m+1), absolute offsets
+  const int32_t* s_col;
+  VT* s_val;
+  const int32_t* s_perm;
+  const RowBlock* s_blk;   // row blocks of every slice
+  int32_t s_off[kSlices + 1];
+  int32_t s_nblk_max;      // most row blocks of any slice
+  VT* part;                // kSlices x m partial row sums
   const RowBlock* a_blk;
   int32_t a_nblk;
   const RowBlock* t_blk;
@@ -113,7 +123,9 @@ template <typename VT> void launch_fin_resid(const Dev<VT>& d, int iter, double 
 // the two CG sweeps and their finalizers (alpha; beta, stop test, host progress record)
 template <typename VT> void launch_cg_t(const Dev<VT>& d, hipStream_t st);
 template <typename VT> void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st);
+// CG product by column slices (+ alpha in workgroup 0), then combine + CG update
 template <typename VT> void launch_cg_a(const Dev<VT>& d, hipStream_t st);
+template <typename VT> void launch_cg_comb(const Dev<VT>& d, hipStream_t st);
 template <typename VT> void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st);
 template <typename VT> void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st);
 template <typename VT> void launch_cond_ratio(const Dev<VT>& d, const VT* s_prev, const VT* s_cur, double t_cap,

@@ -11,6 +11,7 @@
 // workgroup writes a partial, the last workgroup to arrive sums them in
 // fixed order.  Workgroup ids are remapped so that each of the 8 XCDs gets a
 // contiguous range of row blocks.
+#include <algorithm>
 #include <cmath>
 
 #include "acs_kernels.h"
@@ -328,22 +329,53 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
 }
 
 // ----------------------------------------------------------------------------
-// CG, second half (rows i of A_s): q = r + beta q; w += alpha q;
-// r -= alpha A_s t; beta' = ||r||^2 / rho; stop test
+// CG, second half, by column slices: workgroup b works on slice b % kSlices,
+// i.e. on the XCD it is dispatched to, so its gathers of t touch 1/kSlices of
+// t and stay in that XCD's L2; it writes partial row sums part[x][i].
+// Workgroup 0 first turns the first half's partials into alpha = rho/||t||^2.
 // ----------------------------------------------------------------------------
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_cg_a(Dev<VT> d) {
+__global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
   if (d.ctl->done) return;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const RowBlock rb = d.a_blk[blk];
-  const VT* __restrict__ av = d.a_val;
-  const int32_t* __restrict__ ac = d.a_col;
+  if (blockIdx.x == 0) {
+    double tt[1];
+    sum_partials<1>(d.partials, t_nb, tt);
+    if (threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      if (tt[0] > 0.0 && !isinf(tt[0])) {
+        c->alpha = c->rho / tt[0];
+      } else {
+        c->alpha = 0.0;
+        c->done = 1;
+        if (!(tt[0] == tt[0])) host_store(&d.hs->numeric, 1);
+        host_store(&d.hs->cg_done_iter, c->iter);
+      }
+    }
+  }
+  const int x = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
+  if (lb >= d.s_off[x + 1] - d.s_off[x]) return;
+  const RowBlock rb = d.s_blk[d.s_off[x] + lb];
+  const VT* __restrict__ sv = d.s_val;
+  const int32_t* __restrict__ sc = d.s_col;
   const VT* __restrict__ t = d.t;
+  VT* __restrict__ part = d.part + size_t(x) * d.m;
+  auto prod = [&](int k) -> VT { return sv[k] * t[sc[k]]; };
+  auto epi = [&](int i, VT sum) { part[i] = sum; };
+  rows_block<VT>(d.s_rp + size_t(x) * (d.m + 1), rb, prod, epi);
+}
+
+// Mq_i = sum over slices (fixed order); q = r + beta q; w += alpha q; r -= alpha Mq
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_cg_a_comb(Dev<VT> d) {
+  if (d.ctl->done) return;
   const double alpha = d.ctl->alpha, beta = d.ctl->beta;
   const VT valpha = VT(alpha), vbeta = VT(beta);
-  auto prod = [&](int k) -> VT { return av[k] * t[ac[k]]; };
   double acc[1] = {0};
-  auto epi = [&](int i, VT mq) {
+  const int m = d.m;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+    VT mq = d.part[i];
+#pragma unroll
+    for (int x = 1; x < kSlices; ++x) mq += d.part[size_t(x) * m + i];
     const VT ri = d.r[i];
     const VT qi = (beta != 0.0) ? ri + vbeta * d.q[i] : ri;
     d.q[i] = qi;
@@ -351,9 +383,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(Dev<VT> d) {
     const VT rn = ri - valpha * mq;
     d.r[i] = rn;
     acc[0] += double(rn) * double(rn);
-  };
-  rows_block<VT>(d.a_rp, rb, prod, epi);
-  block_store_partials<1>(acc, d.partials, blk);
+  }
+  block_store_partials<1>(acc, d.partials, blockIdx.x);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_scale_s(Dev<VT> d, int nnz) {
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nnz; k += gridDim.x * kBlock) d.s_val[k] = VT(d.a_val64[d.s_perm[k]]);
 }
 
 // ----------------------------------------------------------------------------
@@ -795,14 +831,21 @@ void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st) {
   hipLaunchKernelGGL((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.t_nblk);
 }
 
+static inline int comb_blocks(int m) { return std::min(ceil_div(m, kBlock), 2048); }
+
 template <typename VT>
 void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL((k_cg_a_part<VT>), dim3(kSlices * d.s_nblk_max), dim3(kBlock), 0, st, d, d.t_nblk);
+}
+
+template <typename VT>
+void launch_cg_comb(const Dev<VT>& d, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_a_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
-  hipLaunchKernelGGL((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, launch_id);
+  hipLaunchKernelGGL((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), launch_id);
 }
 
 template <typename VT>
@@ -831,6 +874,9 @@ void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
   hipLaunchKernelGGL((k_rowsum<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, wmode);
   hipLaunchKernelGGL((k_scale_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL((k_scale_t<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d);
+  const int nnz = d.a_rp_nnz;
+  hipLaunchKernelGGL((k_scale_s<VT>), dim3(std::max(1, std::min(ceil_div(nnz, kBlock), 8192))), dim3(kBlock), 0, st, d,
+                     nnz);
   hipLaunchKernelGGL((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
 }
 
@@ -855,6 +901,7 @@ void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
   template void launch_cg_t<VT>(const Dev<VT>&, hipStream_t);                                         \
   template void launch_fin_cg_t<VT>(const Dev<VT>&, hipStream_t);                                     \
   template void launch_cg_a<VT>(const Dev<VT>&, hipStream_t);                                         \
+  template void launch_cg_comb<VT>(const Dev<VT>&, hipStream_t);                                      \
   template void launch_fin_cg_a<VT>(const Dev<VT>&, long long, hipStream_t);                          \
   template void launch_pres<VT>(const Dev<VT>&, int, double, double, hipStream_t);                    \
   template void launch_cond_ratio<VT>(const Dev<VT>&, const VT*, const VT*, double, hipStream_t);     \

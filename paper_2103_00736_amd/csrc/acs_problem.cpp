@@ -88,6 +88,41 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
       p.t_perm[pos] = k;
     }
   }
+  // column slices of A (one per XCD): gathers of an n-vector stay within 1/kSlices of it
+  {
+    const int64_t w = (int64_t(n) + kSlices - 1) / kSlices;
+    p.s_row_ptr.assign(size_t(kSlices) * (m + 1), 0);
+    for (int32_t i = 0; i < m; ++i)
+      for (int32_t k = p.row_ptr[i]; k < p.row_ptr[i + 1]; ++k) {
+        const int x = int(p.col[k] / w);
+        p.s_row_ptr[size_t(x) * (m + 1) + i + 1]++;
+      }
+    int32_t base = 0;
+    for (int x = 0; x < kSlices; ++x) {
+      int32_t* rp = &p.s_row_ptr[size_t(x) * (m + 1)];
+      rp[0] = base;
+      for (int32_t i = 0; i < m; ++i) rp[i + 1] += rp[i];
+      base = rp[m];
+    }
+    p.s_col.resize(nnz);
+    p.s_perm.resize(nnz);
+    std::vector<int32_t> fill(size_t(kSlices) * m);
+    for (int x = 0; x < kSlices; ++x)
+      for (int32_t i = 0; i < m; ++i) fill[size_t(x) * m + i] = p.s_row_ptr[size_t(x) * (m + 1) + i];
+    for (int32_t i = 0; i < m; ++i)
+      for (int32_t k = p.row_ptr[i]; k < p.row_ptr[i + 1]; ++k) {
+        const int x = int(p.col[k] / w);
+        const int32_t pos = fill[size_t(x) * m + i]++;
+        p.s_col[pos] = p.col[k];
+        p.s_perm[pos] = k;
+      }
+    p.s_blk_off.assign(kSlices + 1, 0);
+    for (int x = 0; x < kSlices; ++x) {
+      std::vector<RowBlock> b = make_row_blocks(&p.s_row_ptr[size_t(x) * (m + 1)], m, kStageNnz);
+      p.s_blocks.insert(p.s_blocks.end(), b.begin(), b.end());
+      p.s_blk_off[x + 1] = int32_t(p.s_blocks.size());
+    }
+  }
   p.a_blocks = make_row_blocks(p.row_ptr.data(), m, kStageNnz);
   p.t_blocks = make_row_blocks(p.t_row_ptr.data(), n, kStageNnz);
   double bb = 0, cc = 0;

@@ -59,6 +59,12 @@ class Server {
   Server(int64_t budget, int max_slots, int64_t small_nnz, int workers, int tick_iters)
       : budget_(budget), max_slots_(max_slots), small_nnz_(small_nnz), tick_iters_(tick_iters) {
     ensure_device();
+    // all request memory comes from one device pool and one pinned record pool,
+    // so serving never calls hipMalloc/hipFree (which waits for the whole device)
+    mem_ = std::make_unique<SubAllocator>(size_t(budget) + size_t(budget) / 8 + (size_t(64) << 20));
+    status_ = std::make_unique<StatusPool>(workers + 4);
+    res_.mem = mem_.get();
+    res_.status = status_.get();
     SHIP(hipStreamCreateWithFlags(&pool_stream_, hipStreamNonBlocking));
     SHIP(hipMalloc(&d_inst_, sizeof(BInst) * max_slots_));
     SHIP(hipMalloc(&d_order_, sizeof(int32_t) * max_slots_));
@@ -87,7 +93,7 @@ class Server {
     for (auto& t : workers_)
       if (t.joinable()) t.join();
     for (auto& sl : pool_)
-      if (sl.arena) (void)hipFree(sl.arena);
+      if (sl.arena) mem_->release(sl.arena);
     (void)hipFree(d_inst_);
     (void)hipFree(d_order_);
     (void)hipFree(d_queue_);
@@ -238,7 +244,9 @@ class Server {
     Slot& sl = pool_[idx];
     try {
       sl.lay = layout_instance(*r->p, 0);
-      SHIP(hipMalloc(&sl.arena, std::max<size_t>(sl.lay.end, 256)));
+      sl.arena = static_cast<char*>(mem_->alloc(std::max<size_t>(sl.lay.end, 256)));
+      if (!sl.arena) throw AcsError(ACS_ERR_NOMEM, "device pool fragmented");
+      SHIP(hipMemsetAsync(sl.arena, 0, sl.lay.end, pool_stream_));
       upload_instance_const(sl.arena, sl.lay, *r->p, pool_stream_);
       const Problem& p = *r->p;
       init_instance_state(sl.host, sl.arena, sl.lay, p, r->s, default_lanes(double(p.nnz) / std::max(1, p.m)),
@@ -248,7 +256,7 @@ class Server {
       sl.active = true;
       ++pool_active_;
     } catch (const AcsError& e) {
-      if (sl.arena) (void)hipFree(sl.arena);
+      if (sl.arena) mem_->release(sl.arena);
       sl.arena = nullptr;
       r->error = e.code;
       r->error_msg = e.what();
@@ -302,7 +310,7 @@ class Server {
       in.dobj = st.kkt[6];
       in.alpha = st.kkt[7];
       in.solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - r->t_admit).count();
-      (void)hipFree(sl.arena);
+      mem_->release(sl.arena);
       sl.arena = nullptr;
       sl.active = false;
       sl.r.reset();
@@ -327,7 +335,7 @@ class Server {
       }
       try {
         if (!r->cancel) {
-          SolveOut out = solve_one_instance(r->p, r->s, static_cast<void*>(streams_[w]));
+          SolveOut out = solve_one_instance(r->p, r->s, static_cast<void*>(streams_[w]), res_);
           r->x = std::move(out.x);
           r->y = std::move(out.y);
           r->z = std::move(out.z);
@@ -346,6 +354,9 @@ class Server {
     }
   }
 
+  std::unique_ptr<SubAllocator> mem_;
+  std::unique_ptr<StatusPool> status_;
+  InstanceResources res_;
   int64_t budget_;
   int max_slots_;
   int64_t small_nnz_;

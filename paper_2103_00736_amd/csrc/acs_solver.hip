@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -80,30 +81,140 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
 // ----------------------------------------------------------------------------
 // device memory
 // ----------------------------------------------------------------------------
+struct SubAllocator::Impl {
+  std::mutex mu;
+  std::map<size_t, size_t> free_by_off;  // offset -> size
+  std::map<size_t, size_t> used;         // offset -> size
+};
+
+SubAllocator::SubAllocator(size_t bytes) : impl_(new Impl) {
+  size_ = (bytes + 255) & ~size_t(255);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&base_), size_);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete impl_;
+    impl_ = nullptr;
+    throw AcsError(ACS_ERR_NOMEM, "device pool of " + std::to_string(size_) + " bytes does not fit");
+  }
+  impl_->free_by_off[0] = size_;
+}
+
+SubAllocator::~SubAllocator() {
+  if (base_) (void)hipFree(base_);
+  delete impl_;
+}
+
+void* SubAllocator::alloc(size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  for (auto it = impl_->free_by_off.begin(); it != impl_->free_by_off.end(); ++it) {
+    if (it->second < bytes) continue;
+    const size_t off = it->first, sz = it->second;
+    impl_->free_by_off.erase(it);
+    if (sz > bytes) impl_->free_by_off[off + bytes] = sz - bytes;
+    impl_->used[off] = bytes;
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void SubAllocator::release(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  const size_t off = size_t(static_cast<char*>(p) - base_);
+  auto u = impl_->used.find(off);
+  if (u == impl_->used.end()) return;
+  size_t start = off, sz = u->second;
+  impl_->used.erase(u);
+  auto next = impl_->free_by_off.lower_bound(start);
+  if (next != impl_->free_by_off.end() && next->first == start + sz) {  // merge with the following range
+    sz += next->second;
+    impl_->free_by_off.erase(next);
+  }
+  auto it = impl_->free_by_off.lower_bound(start);
+  if (it != impl_->free_by_off.begin()) {  // merge with the preceding range
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == start) {
+      start = prev->first;
+      sz += prev->second;
+      impl_->free_by_off.erase(prev);
+    }
+  }
+  impl_->free_by_off[start] = sz;
+}
+
+struct StatusPool::Impl {
+  std::mutex mu;
+  HostStatus* base = nullptr;
+  std::vector<HostStatus*> free_list;
+};
+
+StatusPool::StatusPool(int count) : impl_(new Impl) {
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&impl_->base), sizeof(HostStatus) * std::max(count, 1),
+                               hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete impl_;
+    impl_ = nullptr;
+    throw AcsError(ACS_ERR_NOMEM, "pinned status records");
+  }
+  for (int i = count - 1; i >= 0; --i) impl_->free_list.push_back(impl_->base + i);
+}
+
+StatusPool::~StatusPool() {
+  if (impl_ && impl_->base) (void)hipHostFree(impl_->base);
+  delete impl_;
+}
+
+HostStatus* StatusPool::take() {
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  if (impl_->free_list.empty()) return nullptr;
+  HostStatus* h = impl_->free_list.back();
+  impl_->free_list.pop_back();
+  return h;
+}
+
+void StatusPool::give(HostStatus* h) {
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  impl_->free_list.push_back(h);
+}
+
 class DeviceArena {
  public:
+  explicit DeviceArena(SubAllocator* sa = nullptr) : sa_(sa) {}
   ~DeviceArena() { release(); }
   template <typename T>
   T* alloc(size_t count) {
     void* p = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw AcsError(ACS_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    if (sa_) {
+      p = sa_->alloc(bytes);
+      if (!p) throw AcsError(ACS_ERR_NOMEM, "device pool exhausted (" + std::to_string(bytes) + " bytes)");
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw AcsError(ACS_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      }
     }
     ptrs_.push_back(p);
     bytes_ += bytes;
     return static_cast<T*>(p);
   }
   void release() {
-    for (void* p : ptrs_) (void)hipFree(p);
+    for (void* p : ptrs_) {
+      if (sa_)
+        sa_->release(p);
+      else
+        (void)hipFree(p);
+    }
     ptrs_.clear();
     bytes_ = 0;
   }
   size_t bytes() const { return bytes_; }
 
  private:
+  SubAllocator* sa_;
   std::vector<void*> ptrs_;
   size_t bytes_ = 0;
 };
@@ -115,9 +226,11 @@ static int64_t estimate_bytes(const Problem& p, int precision) {
   b += 4 * (m + 1) + 4 * nnz + vt * nnz + 8 * nnz;       // A pattern, scaled values, original values
   b += 4 * (n + 1) + 4 * nnz + vt * nnz + 4 * nnz;       // A^T pattern, values, perm
   if (vt == 4) b += 16 * nnz;                            // FP64 copies for the refinement sweeps
+  b += (8 + vt) * nnz + 4 * kSlices * (m + 1) + vt * kSlices * m;  // column-sliced copy of A + partials
   b += 8 * int64_t(p.a_blocks.size() + p.t_blocks.size());
   b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
   b += 8 * 8 * int64_t(std::max<size_t>(std::max(p.a_blocks.size(), p.t_blocks.size()), size_t(n / kBlock + 2)));
+  b += 8 * int64_t(p.s_blocks.size()) + 64 * 256;  // sliced row blocks, per-array alignment
   return b;
 }
 
@@ -139,13 +252,14 @@ class InstanceBase {
   acs_settings S{};
 };
 
-enum KClass { KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_FIN = 7, KC_N = 8 };
+enum KClass { KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_FIN = 7, KC_CG_COMB = 8, KC_N = 9 };
 
 template <typename VT>
 class Instance final : public InstanceBase {
  public:
-  Instance(std::shared_ptr<const Problem> prob, const acs_settings& settings, hipStream_t stream)
-      : P_(std::move(prob)) {
+  Instance(std::shared_ptr<const Problem> prob, const acs_settings& settings, hipStream_t stream,
+           const InstanceResources& res = InstanceResources())
+      : P_(std::move(prob)), res_(res), arena_(res.mem) {
     const auto t0 = std::chrono::steady_clock::now();
     S = resolve_settings(settings, *P_);
     sched_.first = S.l_first;
@@ -171,7 +285,12 @@ class Instance final : public InstanceBase {
         (void)hipEventDestroy(e.b);
       }
     arena_.release();
-    if (hs_) (void)hipHostFree(hs_);
+    if (hs_) {
+      if (res_.status)
+        res_.status->give(hs_);
+      else
+        (void)hipHostFree(hs_);
+    }
     if (own_stream_) (void)hipStreamDestroy(st_);
   }
 
@@ -229,6 +348,28 @@ class Instance final : public InstanceBase {
     }
     d.a_blk = a_blk;
     d.a_nblk = int(p.a_blocks.size());
+    d.a_rp_nnz = int32_t(p.nnz);
+    {
+      int32_t* s_rp = arena_.alloc<int32_t>(p.s_row_ptr.size());
+      int32_t* s_col = arena_.alloc<int32_t>(p.nnz);
+      int32_t* s_perm = arena_.alloc<int32_t>(p.nnz);
+      RowBlock* s_blk = arena_.alloc<RowBlock>(p.s_blocks.size());
+      up(s_rp, p.s_row_ptr);
+      if (p.nnz) {
+        up(s_col, p.s_col);
+        up(s_perm, p.s_perm);
+      }
+      up(s_blk, p.s_blocks);
+      d.s_rp = s_rp;
+      d.s_col = s_col;
+      d.s_perm = s_perm;
+      d.s_blk = s_blk;
+      d.s_val = arena_.alloc<VT>(p.nnz);
+      d.s_nblk_max = 1;
+      for (int x = 0; x <= kSlices; ++x) d.s_off[x] = p.s_blk_off[x];
+      for (int x = 0; x < kSlices; ++x) d.s_nblk_max = std::max(d.s_nblk_max, p.s_blk_off[x + 1] - p.s_blk_off[x]);
+      d.part = arena_.alloc<VT>(size_t(kSlices) * p.m);
+    }
     d.t_blk = t_blk;
     d.t_nblk = int(p.t_blocks.size());
     d.soc_off = soc_off;
@@ -256,11 +397,17 @@ class Instance final : public InstanceBase {
     d.ctl = arena_.alloc<Ctl>(1);
     const size_t units = size_t(p.n_orth) + p.soc_size.size();
     nparts_ = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), units / kBlock + 1,
-                                 p.soc_size.size() / 4 + 1, 1});
+                                 p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, 1});
     d.partials = arena_.alloc<double>(nparts_ * 8);
     s_buf_[0] = arena_.alloc<VT>(p.n);
     s_buf_[1] = arena_.alloc<VT>(p.n);
-    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&hs_), sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent));
+    if (res_.status) {
+      hs_ = res_.status->take();
+      if (!hs_) throw AcsError(ACS_ERR_NOMEM, "no free status record");
+    } else {
+      HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&hs_), sizeof(HostStatus),
+                              hipHostMallocMapped | hipHostMallocCoherent));
+    }
     std::memset(hs_, 0, sizeof(HostStatus));
     hs_->cg_done_iter = -1;
     hs_->check_iter = -1;
@@ -452,8 +599,8 @@ class Instance final : public InstanceBase {
       const int c = std::min(chunk, S.cg_max - launched);
       for (int i = 0; i < c; ++i) {
         timed(KC_CG_T, [&] { launch_cg_t(d_, st_); });
-        timed(KC_FIN, [&] { launch_fin_cg_t(d_, st_); });
         timed(KC_CG_A, [&] { launch_cg_a(d_, st_); });
+        timed(KC_CG_COMB, [&] { launch_cg_comb(d_, st_); });
         const long long id = ++launch_id_;
         timed(KC_FIN, [&] { launch_fin_cg_a(d_, id, st_); });
       }
@@ -603,6 +750,7 @@ class Instance final : public InstanceBase {
 
  private:
   std::shared_ptr<const Problem> P_;
+  InstanceResources res_;
   Schedule sched_;
   hipStream_t st_ = nullptr;
   bool own_stream_ = false;
@@ -624,13 +772,15 @@ class Instance final : public InstanceBase {
 };
 
 static std::unique_ptr<InstanceBase> make_instance(std::shared_ptr<const Problem> p, const acs_settings& s,
-                                                   hipStream_t st) {
-  if (s.precision == ACS_PREC_FP64) return std::make_unique<Instance<double>>(std::move(p), s, st);
-  return std::make_unique<Instance<float>>(std::move(p), s, st);
+                                                   hipStream_t st,
+                                                   const InstanceResources& res = InstanceResources()) {
+  if (s.precision == ACS_PREC_FP64) return std::make_unique<Instance<double>>(std::move(p), s, st, res);
+  return std::make_unique<Instance<float>>(std::move(p), s, st, res);
 }
 
-SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream) {
-  auto inst = make_instance(p, s, static_cast<hipStream_t>(stream));
+SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream,
+                            const InstanceResources& res) {
+  auto inst = make_instance(p, s, static_cast<hipStream_t>(stream), res);
   inst->run(inst->S.max_iter, true);
   SolveOut o;
   o.x.resize(p->n);

@@ -1,0 +1,174 @@
+"""GPU checks at the full benchmark sizes and on edge cases.
+
+* The 2M-variable LP and the 1M-variable SOCP solved to 1e-4 KKT in the
+  launch configuration the benchmark times: KKT recomputed in FP64 by the
+  oracle at full size, objective against the planted optimum.
+* The scaled products A_s x and A_s^T x on sampled rows, each row summed one
+  by one in FP64 from the problem's values and the state's O and D.
+* Edge cases of the kernels: Lorentz cones of sizes 1, 2, 3, 64, 65 and 130
+  (lane groups of every width), empty rows and columns, and one row longer
+  than the LDS stage (the whole-workgroup path) in every sweep.
+"""
+import numpy as np
+import pytest
+
+from oracle.alg2 import Algorithm2, default_parameters, one_iteration
+from oracle.kkt import kkt_errors
+from paper_2103_00736_amd import acs, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert acs.lib().acs_init(0) == acs.ACS_OK, acs.lib().acs_last_error()
+
+
+def _solve_and_verify(p, max_iter):
+    x, y, z, info = acs.solve(acs.Problem.from_synth(p), eps_kkt=1e-4, max_iter=max_iter)
+    rec = kkt_errors(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, x, y, z)
+    obj_err = abs(rec["pobj"] - p.p_star) / (1 + abs(p.p_star))
+    print(f"{p.name}: status={info.status} it={info.iterations} cg={info.cg_steps} gpu_kkt={info.kkt:.2e} "
+          f"oracle_kkt={rec['kkt']:.2e} (p {rec['eps_p']:.1e} d {rec['eps_d']:.1e} g {rec['eps_g']:.1e} "
+          f"k {rec['eps_k']:.1e}) obj_err={obj_err:.2e} solve_s={info.solve_ms / 1e3:.2f}")
+    assert info.status == acs.SOLVED
+    assert rec["kkt"] <= 1.05e-4
+    assert abs(info.kkt - rec["kkt"]) <= 1e-6 + 0.02 * rec["kkt"]
+    assert obj_err <= 3e-4
+
+
+def test_full_lp_2m():
+    _solve_and_verify(synth.config1(), 20000)
+
+
+def test_full_socp_1m():
+    _solve_and_verify(synth.config2(), 20000)
+
+
+def test_sampled_rows_of_scaled_products_full_size():
+    import torch
+
+    p = synth.config1()
+    st = acs.State(acs.Problem.from_synth(p))
+    st.step(301)  # past the first conditioning of the LP schedule: O spans e^9.2
+    g = st.get(xyz=False)
+    O = g["O"]
+    A = p.scipy_csr()
+    d = 1.0 / np.sqrt(np.asarray(A.multiply(A).multiply(O[None, :] ** 2).sum(axis=1)).ravel())
+    d[~np.isfinite(d)] = 1.0  # empty rows keep a unit diagonal
+    rng = np.random.default_rng(0)
+    dev = torch.device("cuda:0")
+    xn = rng.standard_normal(p.n).astype(np.float32)
+    xm = rng.standard_normal(p.m).astype(np.float32)
+    y_m = torch.empty(p.m, dtype=torch.float32, device=dev)
+    y_n = torch.empty(p.n, dtype=torch.float32, device=dev)
+    xn_d, xm_d = torch.from_numpy(xn).to(dev), torch.from_numpy(xm).to(dev)
+    st.spmv(0, xn_d.data_ptr(), y_m.data_ptr())
+    st.spmv(1, xm_d.data_ptr(), y_n.data_ptr())
+    torch.cuda.synchronize()
+    ym, yn = y_m.cpu().numpy(), y_n.cpu().numpy()
+    deg = np.diff(p.row_ptr)
+    rows = np.r_[rng.choice(p.m, 400, replace=False), np.argsort(deg)[-5:]]  # include the longest rows
+    for i in rows:
+        k0, k1 = p.row_ptr[i], p.row_ptr[i + 1]
+        cols = p.col_idx[k0:k1]
+        terms = d[i] * p.val[k0:k1] * O[cols] * xn[cols].astype(np.float64)
+        ref = terms.sum()
+        assert abs(ym[i] - ref) <= 1e-5 * (np.abs(terms).sum() + 1e-30), i
+    At = A.T.tocsr()
+    for j in rng.choice(p.n, 400, replace=False):
+        k0, k1 = At.indptr[j], At.indptr[j + 1]
+        rws = At.indices[k0:k1]
+        terms = d[rws] * At.data[k0:k1] * O[j] * xm[rws].astype(np.float64)
+        assert abs(yn[j] - terms.sum()) <= 1e-5 * (np.abs(terms).sum() + 1e-30), j
+
+
+def _edge_problem(seed=3):
+    """Orthant block + Lorentz cones of sizes 1, 2, 3, 64, 65, 130; empty rows
+    and columns; a row longer than the 2048-nonzero LDS stage, another one
+    that long inside a single column slice, and a column that long (a long
+    row of A^T)."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    sizes = [1, 2, 3, 64, 65, 130, 5, 7]
+    n_orth = 40000
+    n = n_orth + sum(sizes)
+    m = 3000
+    rows = []
+    for i in range(m):
+        if i in (5, 77, 150):
+            r = set()
+        elif i == 200:
+            r = set(rng.choice(n, 5000, replace=False).tolist())
+        elif i == 201:
+            r = set(rng.choice(5000, 3000, replace=False).tolist())
+        else:
+            r = set(rng.choice(n, int(rng.integers(5, 40)), replace=False).tolist())
+        rows.append(r)
+    for i in rng.choice([i for i in range(m) if i not in (5, 77, 150)], 2500, replace=False):
+        rows[i].add(7)
+    rows = [np.array(sorted(r), dtype=np.int64) for r in rows]
+    data = np.concatenate([rng.standard_normal(len(r)) for r in rows]).astype(np.float32).astype(np.float64)
+    indptr = np.r_[0, np.cumsum([len(r) for r in rows])]
+    A = sp.csr_matrix((data, np.concatenate(rows), indptr), shape=(m, n))
+    x0 = np.zeros(n)
+    z0 = np.zeros(n)
+    mask = rng.random(n_orth) < 0.5
+    x0[:n_orth][mask] = rng.random(mask.sum())
+    z0[:n_orth][~mask] = rng.random((~mask).sum())
+    off = n_orth
+    for k in sizes:
+        u = rng.standard_normal(k - 1) if k > 1 else np.zeros(0)
+        nu = np.linalg.norm(u)
+        sel = rng.integers(0, 3)
+        if sel == 0:
+            x0[off] = nu + 0.5
+            x0[off + 1:off + k] = u
+        elif sel == 1:
+            z0[off] = nu + 0.5
+            z0[off + 1:off + k] = u
+        else:
+            x0[off], x0[off + 1:off + k] = nu, u
+            z0[off], z0[off + 1:off + k] = nu, -u
+        off += k
+    y0 = rng.standard_normal(m)
+    b = A @ x0
+    c = A.T @ y0 + z0
+    return synth.ConicProblem(m=m, n=n, row_ptr=A.indptr.astype(np.int64), col_idx=A.indices.astype(np.int32),
+                              val=A.data, b=b, c=c, n_orth=n_orth, soc_sizes=np.array(sizes, dtype=np.int32),
+                              x0=x0, y0=y0, z0=z0, name="edge")
+
+
+@pytest.mark.parametrize("prec", [acs.PREC_FP64, acs.PREC_MIXED])
+def test_edge_case_iteration_parity(prec):
+    p = _edge_problem()
+    t, L = default_parameters(p.soc_sizes)
+    alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
+    for _ in range(L.first + 7):
+        s_prev = alg.s.copy()
+        alg.step()
+    s = alg.s.copy()
+    if prec == acs.PREC_MIXED:
+        s_prev = s_prev.astype(np.float32).astype(np.float64)
+        s = s.astype(np.float32).astype(np.float64)
+    st = acs.State(acs.Problem.from_synth(p), precision=prec, cg_max=3000,
+                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7)
+    st.set(alg.l, s_prev, s, alg.O, -alg.dual_multiplier())
+    st.step(1)
+    g = st.get()
+    ref = one_iteration(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, 1.0, s, alg.O)
+    tol = 1e-9 if prec == acs.PREC_FP64 else 1e-5
+    for k in ("s", "x", "z"):
+        err = np.linalg.norm(g[k] - ref[k]) / np.linalg.norm(ref[k])
+        print(k, f"{err:.2e}")
+        assert err <= tol, k
+
+
+def test_edge_case_solve():
+    p = _edge_problem(5)
+    x, y, z, info = acs.solve(acs.Problem.from_synth(p), precision=acs.PREC_FP64, eps_kkt=1e-6, max_iter=20000)
+    rec = kkt_errors(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, x, y, z)
+    print(info.as_dict(), rec)
+    assert info.status == acs.SOLVED and rec["kkt"] <= 1.05e-6
+    assert abs(rec["pobj"] - p.p_star) <= 1e-5 * (1 + abs(p.p_star))

@@ -1,0 +1,170 @@
+"""Plants plausible mistakes in the oracle (on the CPU) and checks that the
+pin tests catch each one: a pin suite that passed on a wrong oracle would
+not pin anything.  Each mutation replaces one oracle function for the
+duration of the test; the pins are the functions of the other oracle test
+modules, run as plain calls."""
+import numpy as np
+import pytest
+
+import oracle.alg2 as alg2
+import oracle.cones as cones
+import oracle.subspace as subspace
+from tests import test_oracle_alg2 as P2
+from tests import test_oracle_cones as PC
+from tests import test_oracle_subspace as PS
+
+PINS = [
+    lambda: PC.test_moreau_decomposition(3),
+    lambda: PC.test_moreau_decomposition(17),
+    PC.test_orthant_is_size_one_lorentz,
+    PC.test_product_cone_properties,
+    lambda: PS.test_projector_matches_numpy_pinv(0),
+    PS.test_projector_algebra,
+    PS.test_paper_example_condition_numbers,
+    P2.test_ratio_worked_orthant,
+    P2.test_ratio_worked_soc,
+    P2.test_normalisation_within_range_is_identity_power,
+    P2.test_normalisation_caps_log_range,
+    P2.test_normalisation_guards,
+    P2.test_lemma1_norm_and_inner_product,
+    lambda: P2.test_lemma2_planted_fixed_point(1.0),
+    P2.test_lemma2_in_any_scaling,
+    P2.test_lemma3_monotone_distance,
+    lambda: P2.test_algorithm1_is_douglas_rachford(True),
+    P2.test_paper_example_reaches_vertex_optimum,
+    P2.test_fused_update_identity,
+]
+
+
+def _caught():
+    for pin in PINS:
+        try:
+            pin()
+        except Exception:
+            return True
+    return False
+
+
+def _mut_abs_dropped_term(v, n_orth, soc_sizes):
+    return cones.proj_K(v, n_orth, soc_sizes)
+
+
+def _mut_lorentz_scale(v):
+    v = np.asarray(v, dtype=np.float64)
+    nv = float(np.linalg.norm(v[1:]))
+    if nv <= v[0]:
+        return v.copy()
+    if nv <= -v[0]:
+        return np.zeros_like(v)
+    a = v[0] + nv  # missing the factor 1/2
+    out = np.empty_like(v)
+    out[0] = a
+    out[1:] = (a / nv) * v[1:]
+    return out
+
+
+def _mut_reflect(self, v):
+    return self.project(v) - np.asarray(v)  # missing factor 2
+
+
+def _mut_pinv_transposed(self, b):
+    return self.B.T @ np.asarray(b)  # B^T b instead of B^T (B B^T)^+ b
+
+
+def _mut_ratio_inverted(x, z, n_orth, soc_sizes):
+    return alg2_orig_ratio(z, x, n_orth, soc_sizes)
+
+
+def _mut_no_cap(o_raw, t):
+    o = np.abs(np.asarray(o_raw, dtype=np.float64))
+    o = np.where(np.isnan(o), 1.0, o)
+    valid = np.isfinite(o) & (o > 0)
+    if not valid.any():
+        return np.ones_like(o)
+    lo, hi = o[valid].min(), o[valid].max()
+    o = np.where(o == 0, lo, np.where(np.isinf(o), hi, o))
+    span = np.log(hi) - np.log(lo)
+    return o ** (1.0 if span <= 0 else t / span)  # min(1, .) dropped
+
+
+alg2_orig_ratio = alg2.conditioning_ratio
+
+
+def _patched_step(kind):
+    orig = alg2.Algorithm2.step
+
+    def step(self):
+        self.l += 1
+        if self.l in self.schedule:
+            self.condition()
+        s = self.s
+        p = cones.abs_K(s, self.n_orth, self.soc_sizes)
+        r = self.proj.reflect(p)
+        if kind == "sign18":
+            s_new = 0.5 * s + 0.5 * r + self.d
+        else:
+            s_new = 0.5 * s - 0.5 * r + self.d
+        if kind == "x_without_O":
+            self.x = (p + s_new) / 2.0
+        else:
+            self.x = self.O * (p + s_new) / 2.0
+        self.z = (p - s_new) / (2.0 * self.mu * self.O)
+        self.p = p
+        self.s = s_new
+
+    return step, orig
+
+
+def _patched_condition_recast():
+    def condition(self):
+        o = alg2.conditioning_ratio(self.x, self.z, self.n_orth, self.soc_sizes)
+        O = alg2.normalize_scaling(o, self.t)
+        self.O = O
+        self.proj = subspace.RangeProjector(self.A, O, method=self.method)
+        Oc = O * self.c
+        self.d = self.proj.pinv_apply(self.b) + 0.5 * self.mu * (self.proj.reflect(Oc) - Oc)
+        self.s = self.x * O - self.mu * self.z / O  # step 14 with the scaling inverted
+
+    return condition
+
+
+def _patched_condition_no_pinv_b():
+    def condition(self):
+        o = alg2.conditioning_ratio(self.x, self.z, self.n_orth, self.soc_sizes)
+        O = alg2.normalize_scaling(o, self.t)
+        self.O = O
+        self.proj = subspace.RangeProjector(self.A, O, method=self.method)
+        Oc = O * self.c
+        self.d = 0.5 * self.mu * (self.proj.reflect(Oc) - Oc)  # (AO)^dagger b dropped
+        self.s = self.x / O - self.mu * O * self.z
+
+    return condition
+
+
+MUTATIONS = {
+    "abs_K returns proj_K": (cones, "abs_K", _mut_abs_dropped_term),
+    "Lorentz projection scale": (cones, "proj_lorentz", _mut_lorentz_scale),
+    "reflection without factor 2": (subspace.RangeProjector, "reflect", _mut_reflect),
+    "pseudo-inverse without (BB^T)^+": (subspace.RangeProjector, "pinv_apply", _mut_pinv_transposed),
+    "ratio inverted": (alg2, "conditioning_ratio", _mut_ratio_inverted),
+    "exponent not capped at 1": (alg2, "normalize_scaling", _mut_no_cap),
+    "step 18 sign": (alg2.Algorithm2, "step", _patched_step("sign18")[0]),
+    "step 19 without O": (alg2.Algorithm2, "step", _patched_step("x_without_O")[0]),
+    "step 14 scaling inverted": (alg2.Algorithm2, "condition", _patched_condition_recast()),
+    "step 13 drops (AO)^dagger b": (alg2.Algorithm2, "condition", _patched_condition_no_pinv_b()),
+}
+
+
+def test_unmutated_oracle_passes_every_pin():
+    assert not _caught()
+
+
+@pytest.mark.parametrize("name", list(MUTATIONS))
+def test_mutation_is_caught(name, monkeypatch):
+    target, attr, repl = MUTATIONS[name]
+    monkeypatch.setattr(target, attr, repl)
+    # modules that imported the name directly see the mutation too
+    for mod in (alg2, subspace, P2, PC, PS):
+        if hasattr(mod, attr) and mod is not target and callable(getattr(mod, attr)) and target in (cones, alg2):
+            monkeypatch.setattr(mod, attr, repl)
+    assert _caught(), f"no pin caught: {name}"
