@@ -214,7 +214,9 @@ int acs_batch_autotune(acs_batch* b, int32_t sample, int32_t iters, const char* 
 int acs_batch_run(acs_batch* b, int32_t iter_budget, int32_t use_graph, double* ms);
 /* Host outputs of instance i (any may be NULL); x, z length n_i, y length m_i. */
 int acs_batch_result(acs_batch* b, int32_t i, double* x, double* y, double* z, acs_info* info);
-/* Lanes per row chosen for instance i. */
+/* Sweep schedule chosen for instance i (rows of A and of A^T): G > 0 lanes per
+ * row reading the matrix directly, or -S for LDS-staged row blocks of at most
+ * S nonzeros. */
 int acs_batch_lanes(acs_batch* b, int32_t i, int32_t* g_a, int32_t* g_t);
 /* One-shot: create, run to completion (max_iter), copy results, destroy.
  * x[i], y[i], z[i] are per-instance host buffers (the arrays may be NULL). */

@@ -12,9 +12,21 @@
 namespace acs {
 
 // Per-instance descriptor and resident state (device memory).
+// Sweep schedule of one matrix of an instance: `staged` = 0 sums each row
+// with `param` lanes reading the matrix directly; `staged` = 1 walks
+// host-built row blocks of at most `param` nonzeros staged through LDS.
+struct Sched {
+  int32_t staged;
+  int32_t param;
+};
+
 struct BInst {
   int32_t m, n, nnz, n_orth, n_soc;
-  int32_t g_a, g_t;  // lanes per row for rows of A_s and of A_s^T (autotuned)
+  int32_t g_a, g_t;  // lanes per row for rows of A_s and of A_s^T (direct schedule)
+  int32_t st_a, st_t;  // 1: staged schedule for rows of A_s / of A_s^T
+  int32_t a_nblk, t_nblk;
+  const RowBlock* a_blk;
+  const RowBlock* t_blk;
   const int32_t* a_rp;
   const int32_t* a_col;
   const double* a_orig;
@@ -65,8 +77,10 @@ struct BInst {
 struct InstLayout {
   size_t a_rp, a_col, a_orig, t_rp, t_col, t_perm, soc_off, b, c, const_end;
   size_t a_val, a_val64, t_val, t_val64, O, chat, dsq, dinv, bs, w, s0, s1, p, v, t, r, q, zt, x, y, z, xhat, ounit;
+  size_t a_blk, t_blk;  // room for the row blocks of the smallest stage
   size_t end;
 };
+constexpr int kBatchStageMin = 512;  // smallest stage the autotuner tries
 // Lay out one instance starting at byte `base`.
 InstLayout layout_instance(const Problem& p, size_t base);
 // Copy the constant arrays (pattern, values, b, c, cones) into the arena.
@@ -74,9 +88,12 @@ void upload_instance_const(char* d_arena, const InstLayout& o, const Problem& p,
 // Descriptor with device pointers, settings and the initial state (x = z = e_K, O = 1, w = 0);
 // uploads the initial vectors.
 void init_instance_state(BInst& I, char* d_arena, const InstLayout& o, const Problem& p, const acs_settings& s,
-                         int g_a, int g_t, hipStream_t st);
+                         Sched sa, Sched st_sched, hipStream_t st);
 // Lanes per row: next power of two of the mean row length, in [1, 64].
 int default_lanes(double mean_row);
+// Default schedules of an instance (staged, 2048-nonzero blocks).
+Sched default_sched_a(const Problem& p);
+Sched default_sched_t(const Problem& p);
 
 // Launch the persistent kernel over `count` descriptors; `order` lists
 // descriptor indices in the order workgroups take them; every instance runs

@@ -103,10 +103,64 @@ __device__ __forceinline__ void lproj(double v0, double nv, double& a0, double& 
   }
 }
 
+constexpr int kStageMax = 2048;  // LDS stage of the staged schedule (nonzeros)
+
 struct Shared {
   double red[kBB / 64];
-  BInst inst;  // the running instance's descriptor, kept in LDS
+  double stage[kStageMax];  // staged products (double, or float in the first half)
+  BInst inst;               // the running instance's descriptor, kept in LDS
 };
+
+// One sweep over the rows of A_s (which = 0) or of A_s^T (which = 1) with the
+// instance's schedule: direct (G lanes per row) or LDS-staged row blocks.
+template <typename Acc, class Prod, class Epi>
+__device__ __forceinline__ void bsweep(const BInst& I, int which, Prod& prod, Epi& epi, Shared& sh) {
+  const int32_t* __restrict__ rp = which ? I.t_rp : I.a_rp;
+  if (!(which ? I.st_t : I.st_a)) {
+    bspmv<Acc>(rp, which ? I.n : I.m, which ? I.g_t : I.g_a, prod, epi);
+    return;
+  }
+  const RowBlock* __restrict__ blk = which ? I.t_blk : I.a_blk;
+  const int nb = which ? I.t_nblk : I.a_nblk;
+  Acc* lds = reinterpret_cast<Acc*>(sh.stage);
+  const int tid = threadIdx.x;
+  for (int b = 0; b < nb; ++b) {
+    const RowBlock rb = blk[b];
+    const int k0 = rp[rb.r0], k1 = rp[rb.r1];
+    if (k1 - k0 > kStageMax) {  // one row longer than the stage: the whole workgroup
+      Acc s = 0;
+      for (int k = k0 + tid; k < k1; k += kBB) s += prod(k);
+      s = wsum(s);
+      if ((tid & 63) == 0) sh.red[tid >> 6] = double(s);
+      __syncthreads();
+      if (tid == 0) {
+        double tot = sh.red[0];
+        for (int i = 1; i < kBB / 64; ++i) tot += sh.red[i];
+        epi(rb.r0, Acc(tot));
+      }
+      __syncthreads();
+      continue;
+    }
+#pragma unroll
+    for (int it = 0; it < kStageMax / kBB; ++it) {
+      const int k = k0 + it * kBB + tid;
+      if (k < k1) lds[k - k0] = prod(k);
+    }
+    __syncthreads();
+    const int nrows = rb.r1 - rb.r0;
+    int G = 64;
+    while (G > 1 && G * nrows > kBB) G >>= 1;
+    const int grp = tid / G, lane = tid & (G - 1), ngrp = kBB / G;
+    for (int r = rb.r0 + grp; r < rb.r1; r += ngrp) {
+      const int a = rp[r] - k0, e = rp[r + 1] - k0;
+      Acc sacc = 0;
+      for (int k = a + lane; k < e; k += G) sacc += lds[k];
+      for (int off = G >> 1; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
+      if (lane == 0) epi(r, sacc);
+    }
+    __syncthreads();
+  }
+}
 
 // p = abs_K(s), v = p - zt on the Lorentz cones of s (thread per cone)
 __device__ void cones_next(BInst& I, const float* __restrict__ s) {
@@ -171,7 +225,7 @@ __device__ void sweep_update(BInst& I, int mode, bool check, double (&acc)[9], S
         I.zt[j] = zt;
     }
   };
-  bspmv<double>(I.t_rp, I.n, I.g_t, prod, epi);
+  bsweep<double>(I, 1, prod, epi, sh);
   __syncthreads();
   if (I.n_soc > 0) {
     if (check) {  // cone distances of x and z (written above)
@@ -288,20 +342,20 @@ __device__ void condition(BInst& I, Shared& sh) {
     I.dinv[i] = 1.0 / ds;
     I.bs[i] = I.b[i] / ds;
   };
-  bspmv<double>(I.a_rp, I.m, I.g_a, prodD, epiD);
+  bsweep<double>(I, 0, prodD, epiD, sh);
   __syncthreads();
   auto fa = [&](int i, int k) {
     const double a = I.a_orig[k] * I.O[I.a_col[k]] * I.dinv[i];
     I.a_val64[k] = a;
     I.a_val[k] = float(a);
   };
-  bforeach(I.a_rp, I.m, I.g_a, fa);
+  bforeach(I.a_rp, I.m, I.st_a ? 16 : I.g_a, fa);
   auto ft = [&](int j, int k) {
     const double a = I.a_orig[I.t_perm[k]] * I.O[j] * I.dinv[I.t_col[k]];
     I.t_val64[k] = a;
     I.t_val[k] = float(a);
   };
-  bforeach(I.t_rp, I.n, I.g_t, ft);
+  bforeach(I.t_rp, I.n, I.st_t ? 16 : I.g_t, ft);
   __syncthreads();
   if (threadIdx.x == 0) {
     I.conds += 1;
@@ -342,7 +396,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh) {
         I.r[i] = ri;
         acc += double(ri) * double(ri);
       };
-      bspmv<double>(I.a_rp, I.m, I.g_a, prod, epi);
+      bsweep<double>(I, 0, prod, epi, sh);
     }
     double rho = bsum(acc, sh.red);
     const double tol2 = fmax(I.cg_red2 * rho, I.cg_abs2);
@@ -362,7 +416,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh) {
           I.t[j] = tj;
           acc += double(tj) * double(tj);
         };
-        bspmv<float>(I.t_rp, I.n, I.g_t, prod, epi);
+        bsweep<float>(I, 1, prod, epi, sh);
       }
       const double tt = bsum(acc, sh.red);
       if (!(tt > 0.0) || isinf(tt)) {
@@ -386,7 +440,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh) {
           I.r[i] = rn;
           acc += double(rn) * double(rn);
         };
-        bspmv<float>(I.a_rp, I.m, I.g_a, prod, epi);
+        bsweep<float>(I, 0, prod, epi, sh);
       }
       const double rn = bsum(acc, sh.red);
       bad = !(rn == rn) || isinf(rn);
@@ -419,7 +473,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh) {
         I.y[i] = yi;
         a2[1] += I.b[i] * yi;
       };
-      bspmv<double>(I.a_rp, I.m, I.g_a, prod, epi);
+      bsweep<double>(I, 0, prod, epi, sh);
       double tot[9];
       for (int i = 0; i < 8; ++i) tot[i] = bsum(ac[i], sh.red);
       const double pres2 = bsum(a2[0], sh.red), bty = bsum(a2[1], sh.red);

@@ -45,6 +45,8 @@ static int size_class(const Problem& p) {
 
 
 int default_lanes(double mean_row) { return pow2_at_least(mean_row, 1, 64); }
+Sched default_sched_a(const Problem&) { return Sched{1, 2048}; }
+Sched default_sched_t(const Problem&) { return Sched{1, 2048}; }
 
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -90,6 +92,10 @@ InstLayout layout_instance(const Problem& p, size_t base) {
   o.z = take(8 * n);
   o.xhat = take(8 * n);
   o.ounit = take(8 * units);
+  const size_t nba = make_row_blocks(p.row_ptr.data(), p.m, kBatchStageMin).size();
+  const size_t nbt = make_row_blocks(p.t_row_ptr.data(), p.n, kBatchStageMin).size();
+  o.a_blk = take(sizeof(RowBlock) * (nba + 1));
+  o.t_blk = take(sizeof(RowBlock) * (nbt + 1));
   o.end = off;
   return o;
 }
@@ -113,9 +119,26 @@ void upload_instance_const(char* d_arena, const InstLayout& o, const Problem& p,
   BHIP(hipStreamSynchronize(st));
 }
 
-void init_instance_state(BInst& I, char* B, const InstLayout& o, const Problem& p, const acs_settings& s, int g_a,
-                         int g_t, hipStream_t st) {
+void init_instance_state(BInst& I, char* B, const InstLayout& o, const Problem& p, const acs_settings& s, Sched sa,
+                         Sched stt, hipStream_t st) {
   std::memset(&I, 0, sizeof(I));
+  const int g_a = sa.staged ? 1 : sa.param, g_t = stt.staged ? 1 : stt.param;
+  I.st_a = sa.staged;
+  I.st_t = stt.staged;
+  I.a_blk = reinterpret_cast<RowBlock*>(B + o.a_blk);
+  I.t_blk = reinterpret_cast<RowBlock*>(B + o.t_blk);
+  if (sa.staged) {
+    const std::vector<RowBlock> bl = make_row_blocks(p.row_ptr.data(), p.m, std::max(sa.param, kBatchStageMin));
+    I.a_nblk = int32_t(bl.size());
+    BHIP(hipMemcpyAsync(B + o.a_blk, bl.data(), sizeof(RowBlock) * bl.size(), hipMemcpyHostToDevice, st));
+    BHIP(hipStreamSynchronize(st));
+  }
+  if (stt.staged) {
+    const std::vector<RowBlock> bl = make_row_blocks(p.t_row_ptr.data(), p.n, std::max(stt.param, kBatchStageMin));
+    I.t_nblk = int32_t(bl.size());
+    BHIP(hipMemcpyAsync(B + o.t_blk, bl.data(), sizeof(RowBlock) * bl.size(), hipMemcpyHostToDevice, st));
+    BHIP(hipStreamSynchronize(st));
+  }
   I.m = p.m;
   I.n = p.n;
   I.nnz = int32_t(p.nnz);
@@ -205,12 +228,11 @@ class Batch {
     settings_.resize(count);
     for (int i = 0; i < count; ++i) settings_[i] = resolve_settings(s, *probs_[i]);
     layout_and_upload();
-    // default lanes per row: next power of two of the mean row length
+    // default schedules: LDS-staged row blocks of 2048 nonzeros
     g_.resize(count);
     for (int i = 0; i < count; ++i) {
-      const Problem& p = *probs_[i];
-      g_[i].first = default_lanes(double(p.nnz) / std::max(1, p.m));
-      g_[i].second = default_lanes(double(p.nnz) / std::max(1, p.n));
+      g_[i].first = default_sched_a(*probs_[i]);
+      g_[i].second = default_sched_t(*probs_[i]);
     }
     order_.resize(count);
     std::iota(order_.begin(), order_.end(), 0);
@@ -289,35 +311,46 @@ class Batch {
     }
   }
 
-  // Timed autotuning of the lanes-per-row pair per size class on a sample of
-  // each class, `iters` iterations per trial; results merge into the cache.
+  // Timed autotuning of the sweep schedules per size class (coordinate
+  // search: rows of A_s first, then rows of A_s^T) on a sample of each class,
+  // `iters` iterations per trial; results merge into the on-disk cache.
   void autotune(int sample, int iters, const char* cache_path) {
-    std::map<int, std::pair<int, int>> cache = load_cache(cache_path);
+    std::map<int, std::pair<Sched, Sched>> cache = load_cache(cache_path);
     std::map<int, std::vector<int>> classes;
     for (int i = 0; i < count(); ++i) classes[size_class(*probs_[i])].push_back(i);
     for (auto& kv : classes) {
       const int cls = kv.first;
       std::vector<int>& members = kv.second;
-      auto it = cache.find(cls);
-      if (it == cache.end()) {
+      if (cache.find(cls) == cache.end()) {
         std::vector<int> pick;
-        for (size_t k = 0; k < members.size() && int(pick.size()) < sample; k += std::max<size_t>(1, members.size() / sample))
+        for (size_t k = 0; k < members.size() && int(pick.size()) < sample;
+             k += std::max<size_t>(1, members.size() / sample))
           pick.push_back(members[k]);
-        const int ga0 = g_[pick[0]].first, gt0 = g_[pick[0]].second;
-        double best = 1e300;
-        std::pair<int, int> bestg{ga0, gt0};
-        for (int fa : {-1, 0, 1})
-          for (int ft : {-1, 0, 1}) {
-            const int ga = std::clamp(fa < 0 ? ga0 / 2 : (fa > 0 ? ga0 * 2 : ga0), 1, 64);
-            const int gt = std::clamp(ft < 0 ? gt0 / 2 : (ft > 0 ? gt0 * 2 : gt0), 1, 64);
-            const double ms = trial(pick, ga, gt, iters);
-            if (ms < best) {
-              best = ms;
-              bestg = {ga, gt};
-            }
+        const Problem& p0 = *probs_[pick[0]];
+        auto candidates = [&](double mean_row) {
+          const int g0 = default_lanes(mean_row);
+          std::vector<Sched> c = {Sched{1, 512}, Sched{1, 1024}, Sched{1, 2048}};
+          for (int g : {std::max(1, g0 / 2), g0, std::min(64, g0 * 2)}) c.push_back(Sched{0, g});
+          return c;
+        };
+        Sched best_a = default_sched_a(p0), best_t = default_sched_t(p0);
+        double best = trial(pick, best_a, best_t, iters);
+        for (const Sched& ca : candidates(double(p0.nnz) / std::max(1, p0.m))) {
+          const double ms = trial(pick, ca, best_t, iters);
+          if (ms < best) {
+            best = ms;
+            best_a = ca;
           }
-        cache[cls] = bestg;
-        tuned_.push_back({cls, bestg.first, bestg.second, best});
+        }
+        for (const Sched& ct : candidates(double(p0.nnz) / std::max(1, p0.n))) {
+          const double ms = trial(pick, best_a, ct, iters);
+          if (ms < best) {
+            best = ms;
+            best_t = ct;
+          }
+        }
+        cache[cls] = {best_a, best_t};
+        tuned_.push_back({cls, best_a, best_t, best});
       }
       for (int i : members) g_[i] = cache[cls];
     }
@@ -325,36 +358,36 @@ class Batch {
     reset_all();
   }
 
-  const std::vector<std::pair<int, int>>& lanes() const { return g_; }
+  const std::vector<std::pair<Sched, Sched>>& lanes() const { return g_; }
 
  private:
   struct Tuned {
-    int cls, ga, gt;
+    int cls;
+    Sched a, t;
     double ms;
   };
 
-  std::map<int, std::pair<int, int>> load_cache(const char* path) {
-    std::map<int, std::pair<int, int>> c;
+  // cache lines: "gfx950 <class> <staged_a> <param_a> <staged_t> <param_t>"
+  std::map<int, std::pair<Sched, Sched>> load_cache(const char* path) {
+    std::map<int, std::pair<Sched, Sched>> c;
     if (!path || !*path) return c;
     std::ifstream f(path);
-    int cls, ga, gt;
+    int cls, sa, pa, stt, pt;
     std::string arch;
-    while (f >> arch >> cls >> ga >> gt)
-      if (arch == "gfx950") c[cls] = {ga, gt};
+    while (f >> arch >> cls >> sa >> pa >> stt >> pt)
+      if (arch == "gfx950") c[cls] = {Sched{sa, pa}, Sched{stt, pt}};
     return c;
   }
-  void save_cache(const char* path, const std::map<int, std::pair<int, int>>& c) {
+  void save_cache(const char* path, const std::map<int, std::pair<Sched, Sched>>& c) {
     if (!path || !*path) return;
     std::ofstream f(path);
-    for (auto& kv : c) f << "gfx950 " << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
+    for (auto& kv : c)
+      f << "gfx950 " << kv.first << " " << kv.second.first.staged << " " << kv.second.first.param << " "
+        << kv.second.second.staged << " " << kv.second.second.param << "\n";
   }
 
-  double trial(const std::vector<int>& pick, int ga, int gt, int iters) {
-    for (int i : pick) {
-      init_instance(i);
-      host_inst_[i].g_a = ga;
-      host_inst_[i].g_t = gt;
-    }
+  double trial(const std::vector<int>& pick, Sched sa, Sched stt, int iters) {
+    for (int i : pick) init_instance_state(host_inst_[i], d_arena_, offs_[i], *probs_[i], settings_[i], sa, stt, st_);
     std::vector<int32_t> ord(pick.begin(), pick.end());
     int32_t* d_ord = nullptr;
     BHIP(hipMalloc(&d_ord, sizeof(int32_t) * ord.size()));
@@ -400,8 +433,9 @@ class Batch {
   }
 
   void init_instance(int i) {
-    init_instance_state(host_inst_[i], d_arena_, offs_[i], *probs_[i], settings_[i], g_.empty() ? 1 : g_[i].first,
-                        g_.empty() ? 1 : g_[i].second, st_);
+    init_instance_state(host_inst_[i], d_arena_, offs_[i], *probs_[i], settings_[i],
+                        g_.empty() ? default_sched_a(*probs_[i]) : g_[i].first,
+                        g_.empty() ? default_sched_t(*probs_[i]) : g_[i].second, st_);
   }
 
   void upload_desc() {
@@ -455,7 +489,7 @@ class Batch {
   std::vector<acs_settings> settings_;
   std::vector<InstLayout> offs_;
   std::vector<BInst> host_inst_;
-  std::vector<std::pair<int, int>> g_;
+  std::vector<std::pair<Sched, Sched>> g_;
   std::vector<int32_t> order_;
   std::vector<Tuned> tuned_;
   hipStream_t st_ = nullptr;
@@ -530,8 +564,9 @@ int acs_batch_lanes(acs_batch* b, int32_t i, int32_t* g_a, int32_t* g_t) {
   return guarded([&] {
     if (!b || i < 0 || i >= b->b->count()) throw AcsError(ACS_ERR_ARG, "bad argument");
     const auto& g = b->b->lanes()[i];
-    if (g_a) *g_a = g.first;
-    if (g_t) *g_t = g.second;
+    // staged schedules are reported as the negated stage size
+    if (g_a) *g_a = g.first.staged ? -g.first.param : g.first.param;
+    if (g_t) *g_t = g.second.staged ? -g.second.param : g.second.param;
   });
 }
 

@@ -249,8 +249,7 @@ class Server {
       SHIP(hipMemsetAsync(sl.arena, 0, sl.lay.end, pool_stream_));
       upload_instance_const(sl.arena, sl.lay, *r->p, pool_stream_);
       const Problem& p = *r->p;
-      init_instance_state(sl.host, sl.arena, sl.lay, p, r->s, default_lanes(double(p.nnz) / std::max(1, p.m)),
-                          default_lanes(double(p.nnz) / std::max(1, p.n)), pool_stream_);
+      init_instance_state(sl.host, sl.arena, sl.lay, p, r->s, default_sched_a(p), default_sched_t(p), pool_stream_);
       SHIP(hipMemcpy(d_inst_ + idx, &sl.host, sizeof(BInst), hipMemcpyHostToDevice));
       sl.r = r;
       sl.active = true;
