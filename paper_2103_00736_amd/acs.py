@@ -90,6 +90,15 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_00736_amd.build`")
+    # One HIP runtime per process: when torch is installed, load it first so
+    # that libacs binds to the HIP runtime torch already holds (same soname)
+    # and torch-allocated device buffers and streams are valid in libacs.  A
+    # second runtime loaded beside an initialised one leaves torch without a
+    # device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "acs_version": (ctypes.c_char_p, []),
