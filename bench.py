@@ -109,11 +109,14 @@ def finish_cpu_baseline(proc, timeout_s=600):
 # algorithmic bytes per launch of the two CG kernels (value type bytes vt)
 # ----------------------------------------------------------------------------
 def kernel_bytes(m, n, nnz, vt=4, slices=8):
-    # k_cg_a_part, rows of the 8 column slices of A_s: 8 row pointers, col+val, t gathered (each entry
-    # once), 8 partial row-sum vectors written
-    cg_a = slices * 4 * (m + 1) + (4 + vt) * nnz + vt * n + slices * vt * m
-    # k_cg_t, rows of A_s^T: row_ptr, col+val, r gathered (each entry once), t_old read + t write
-    cg_t = 4 * (n + 1) + (4 + vt) * nnz + vt * m + 2 * vt * n
+    """Algorithmic bytes of one launch: what the product needs in CSR form, each
+    array once (index + value per nonzero, row pointers, the gathered vector,
+    the output), not what this layout adds (SELL padding, chunk row tables,
+    slice partials)."""
+    # k_cg_a_part: q = A_s t (its 8 column slices together)
+    cg_a = (4 + vt) * nnz + 4 * (m + 1) + vt * n + vt * m
+    # k_cg_t: t = A_s^T r + beta t_old
+    cg_t = (4 + vt) * nnz + 4 * (n + 1) + vt * m + 2 * vt * n
     # k_cg_a_comb: 8 partials read, r and q read + written, w (FP64) read + written
     comb = slices * vt * m + 4 * vt * m + 16 * m
     return {"cg_a": cg_a, "cg_t": cg_t, "cg_comb": comb}

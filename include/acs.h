@@ -131,8 +131,12 @@ int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr
                        const double* val, const double* b, const double* c, int32_t n_orth, int32_t n_soc,
                        const int32_t* soc_sizes, acs_problem** out);
 void acs_problem_destroy(acs_problem* p);
-/* Device bytes a solve of `p` in `precision` allocates (for budgeting). */
+/* Device bytes a one-instance solve of `p` in `precision` allocates (for
+ * budgeting; includes the SELL layouts of the CG products).  Host code. */
 int64_t acs_problem_device_bytes(const acs_problem* p, int32_t precision);
+/* Device bytes `p` takes as one instance of a batch arena or a server pool
+ * slot (the persistent kernel's layout).  Host code. */
+int64_t acs_batch_device_bytes(const acs_problem* p);
 
 /*
  * One-shot solve (Alg. 2 until KKT <= eps_kkt or max_iter).  x, z (length n)
@@ -195,8 +199,8 @@ int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_m
  * eps_kkt or the iteration budget runs out.  The same iteration as the
  * one-instance path (fused steps 16-20, conditioning steps 5-14, same
  * precision split); per-instance t and L follow the class when auto_params=1.
- * Device memory: one arena for all instances (acs_problem_device_bytes
- * summed, roughly); ACS_ERR_NOMEM if it does not fit.
+ * Device memory: one arena for all instances (acs_batch_device_bytes
+ * summed); ACS_ERR_NOMEM if it does not fit.
  */
 typedef struct acs_batch acs_batch;
 int acs_batch_create(int32_t count, const acs_problem* const* probs, const acs_settings* s, void* stream,

@@ -30,7 +30,7 @@ KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
-    "acs_problem_destroy", "acs_problem_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
+    "acs_problem_destroy", "acs_problem_device_bytes", "acs_batch_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
     "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
     "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_batch_create", "acs_batch_destroy",
     "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_lanes", "acs_batch_solve",
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
                                               ctypes.c_int32, ctypes.c_int32, I32P, ctypes.POINTER(P)]),
         "acs_problem_destroy": (None, [P]),
         "acs_problem_device_bytes": (ctypes.c_int64, [P, ctypes.c_int32]),
+        "acs_batch_device_bytes": (ctypes.c_int64, [P]),
         "acs_solve": (ctypes.c_int, [P, ctypes.POINTER(Settings), DP, DP, DP, ctypes.POINTER(Info), P]),
         "acs_state_create": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, ctypes.POINTER(P)]),
         "acs_state_destroy": (None, [P]),
@@ -204,6 +205,9 @@ class Problem:
 
     def device_bytes(self, precision: int = PREC_MIXED) -> int:
         return int(lib().acs_problem_device_bytes(self.handle, precision))
+
+    def batch_device_bytes(self) -> int:
+        return int(lib().acs_batch_device_bytes(self.handle))
 
     def close(self):
         if getattr(self, "handle", None):

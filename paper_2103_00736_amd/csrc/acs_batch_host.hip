@@ -292,7 +292,11 @@ class Batch {
     const BInst& h = host_inst_[i];
     if (x) BHIP(hipMemcpy(x, h.x, sizeof(double) * p.n, hipMemcpyDeviceToHost));
     if (z) BHIP(hipMemcpy(z, h.z, sizeof(double) * p.n, hipMemcpyDeviceToHost));
-    if (y) BHIP(hipMemcpy(y, h.y, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+    if (y) {  // internal row order -> caller's
+      std::vector<double> yi(p.m);
+      BHIP(hipMemcpy(yi.data(), h.y, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+      for (int k = 0; k < p.m; ++k) y[p.row_perm[k]] = yi[k];
+    }
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->status = h.status < 0 ? ACS_MAX_ITER : h.status;
@@ -517,6 +521,11 @@ struct acs_batch {
 };
 
 extern "C" {
+
+int64_t acs_batch_device_bytes(const acs_problem* p) {
+  if (!p) return -1;
+  return int64_t(layout_instance(*p->p, 0).end);
+}
 
 int acs_batch_create(int32_t count, const acs_problem* const* probs, const acs_settings* s, void* stream,
                      acs_batch** out) {

@@ -3,6 +3,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -22,11 +23,53 @@ struct RowBlock {
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kStageNnz = 2048;   // products staged in LDS per multi-row block
 constexpr int kSlices = 8;        // column slices of A, one per XCD
+constexpr int kSellChunk = 64;    // rows per SELL chunk (one per lane of a wave64)
+constexpr int kSellMaxLen = 32;   // longest row packed into a chunk
+constexpr int kWaveRowMax = 2048; // longest row given to one wave; longer rows get a workgroup
+constexpr int kSellWindow = 4096; // rows sorted by length within windows of this many rows
+
+// SELL-64 layout of the products of the CG (each output row is a dot product
+// of a sparse row with a gathered vector).  The rows are split into slices
+// (column ranges of A for A t, one per XCD; a single slice for A^T r).  Per
+// slice, a row longer than kWaveRowMax is a "long task" run by a whole
+// workgroup; every other row belongs to a "wave task": a row longer than
+// kSellMaxLen gets a wave of its own (lanes stride the row), shorter rows are
+// packed 64 to a chunk (one row per lane, entries stored column-major so a
+// wave's loads are contiguous, padded to the chunk's longest row).  Within a
+// window of kSellWindow rows the chunk rows are sorted by length, which keeps
+// padding small while the rows written by neighbouring chunks stay close.
+// Every row of every slice is covered exactly once (empty rows too, so that
+// each output is written).
+struct Sell {
+  int32_t slices = 0;
+  std::vector<int32_t> long_off;            // slices+1 offsets into long_*
+  std::vector<int32_t> long_row, long_beg;  // row and first entry of each long task
+  std::vector<int32_t> long_end;
+  std::vector<int32_t> wt_off;  // slices+1 offsets into wt_*
+  std::vector<int32_t> wt_ptr;  // first entry of the task
+  std::vector<int32_t> wt_len;  // entries of the row (wave row) or per lane (chunk)
+  std::vector<int32_t> wt_row;  // >= 0: row of a wave-row task; < 0: -1 - chunk index
+  std::vector<int32_t> chunk_row;  // kSellChunk per chunk: row of each lane, -1 = unused lane
+  std::vector<int32_t> col;        // column of each entry
+  std::vector<int32_t> src;        // position of the entry in A's CSR, -1 = padding
+  std::vector<int32_t> wg;         // workgroups of each slice: long tasks + ceil(wave tasks / 4)
+  int32_t wg_max = 0;
+};
+
+struct SellPair {
+  Sell a;  // A t, kSlices column slices of A
+  Sell t;  // A^T r, one slice
+};
 
 // Host copy of a validated problem (Sec. II): CSR of A, b, c, cone list.
+// Rows are renumbered by decreasing length (ties in the caller's order): the
+// vector gathered by the A^T products then has its most used entries packed
+// together.  Internal row i is the caller's row row_perm[i]; every m-vector
+// crossing the C ABI (y, w) is mapped with it.
 struct Problem {
   int32_t m = 0, n = 0;
   int64_t nnz = 0;
+  std::vector<int32_t> row_perm;  // m
   std::vector<int32_t> row_ptr;  // m+1
   std::vector<int32_t> col;      // nnz
   std::vector<double> val;       // nnz
@@ -37,15 +80,16 @@ struct Problem {
   // pattern of A^T (CSR over columns of A): t_row_ptr (n+1), t_col (row of A), t_perm (index into val)
   std::vector<int32_t> t_row_ptr, t_col, t_perm;
   std::vector<RowBlock> a_blocks, t_blocks;
-  // A split by column ranges [x*w, (x+1)*w), w = ceil(n/kSlices): the nonzeros
-  // of slice x in row order; s_row_ptr holds kSlices row pointers of m+1
-  // absolute offsets; s_perm maps to the position in A's CSR.
-  std::vector<int32_t> s_row_ptr, s_col, s_perm;
-  std::vector<RowBlock> s_blocks;     // row blocks of every slice, slice after slice
-  std::vector<int32_t> s_blk_off;     // kSlices + 1 offsets into s_blocks
   double bnorm = 0, cnorm = 0;
   int32_t max_soc = 0;
   bool is_socp() const { return !soc_size.empty(); }
+  // SELL layouts of the CG products, built on first use by the one-instance
+  // path (the batched kernel does not use them).
+  const SellPair& sell() const;
+
+ private:
+  mutable std::once_flag sell_once_;
+  mutable std::unique_ptr<SellPair> sell_;
 };
 
 // Validates and copies a problem; on failure returns false and sets err.
@@ -57,6 +101,14 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
 // most `stage` nonzeros; a longer row gets a block of its own).  Long-row
 // blocks are placed first so they start early.
 std::vector<RowBlock> make_row_blocks(const int32_t* row_ptr, int32_t rows, int32_t stage);
+
+// SELL layout of rp.size() slices: slice x has rows 0..rows-1 with entries
+// [rp[x][i], rp[x][i+1]) of (col, src); pad[x] is the column that padding
+// entries point at.  Throws AcsError if the layout would exceed 2^31-1 entries.
+void build_sell(const std::vector<const int32_t*>& rp, int32_t rows, const int32_t* col, const int32_t* src,
+                const std::vector<int32_t>& pad, Sell* out);
+// Checks that every row of every slice is covered once and every entry once.
+bool check_sell(const Sell& s, int32_t rows, int64_t entries, std::string* err);
 
 // Error reporting (thread-local message).
 void set_error(const std::string& msg);

@@ -49,33 +49,49 @@ struct HostStatus {
   int32_t pad;
 };
 
+// Device view of a Sell layout (see acs_internal.h).
+struct SellDev {
+  const int32_t* long_row;
+  const int32_t* long_beg;
+  const int32_t* long_end;
+  const int32_t* wt_ptr;
+  const int32_t* wt_len;
+  const int32_t* wt_row;
+  const int32_t* chunk_row;
+  const int32_t* col;
+  const int32_t* src;
+  int64_t entries;
+  int32_t long_off[kSlices + 1];
+  int32_t wt_off[kSlices + 1];
+  int32_t wg[kSlices];
+  int32_t wg_max;
+  int32_t slices;
+};
+
 template <typename VT>
 struct Dev {
   int32_t m, n, n_orth, n_soc;
   int32_t a_rp_nnz;  // nnz
   double mu;
-  // CSR of A (rows i) and of A^T (rows j); *_val hold A_s, a_orig the problem's values
+  // CSR of A (rows i) and of A^T (rows j) with FP64 values of A_s for the
+  // once-per-iteration residual / update / check sweeps (iterative refinement
+  // of the CG); a_orig holds the problem's values
   const int32_t* a_rp;
   const int32_t* a_col;
-  VT* a_val;
   const double* a_orig;
   const int32_t* t_rp;
   const int32_t* t_col;
-  VT* t_val;
   const int32_t* t_perm;
-  // FP64 copies of A_s for the once-per-iteration residual / update / check
-  // sweeps (iterative refinement of the FP32 CG); alias *_val when VT = double
   double* a_val64;
   double* t_val64;
-  // column slices of A (one per XCD) for the CG product A_s t
-  const int32_t* s_rp;     // kSlices x (m+1), absolute offsets
-  const int32_t* s_col;
-  VT* s_val;
-  const int32_t* s_perm;
-  const RowBlock* s_blk;   // row blocks of every slice
-  int32_t s_off[kSlices + 1];
-  int32_t s_nblk_max;      // most row blocks of any slice
-  VT* part;                // kSlices x m partial row sums
+  // SELL layouts of the CG products A_s t (column slices, one per XCD) and
+  // A_s^T r, with their values in VT
+  SellDev sa, st;
+  VT* sa_val;
+  VT* st_val;
+  VT* part;                // kSlices x m partial row sums of A_s t
+  const int32_t* row_perm; // internal row -> caller's row
+  VT* mtmp;                // m-vector scratch of the plain products
   const RowBlock* a_blk;
   int32_t a_nblk;
   const RowBlock* t_blk;
@@ -132,6 +148,8 @@ template <typename VT> void launch_cond_ratio(const Dev<VT>& d, const VT* s_prev
                                               hipStream_t st);
 template <typename VT> void launch_cond_scale(const Dev<VT>& d, VT* s_cur, hipStream_t st);
 template <typename VT> void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st);
+// plain product with the current A_s through the CG's SELL kernels; m-vectors
+// in the caller's row order
 template <typename VT> void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st);
 template <typename VT> void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st);
 

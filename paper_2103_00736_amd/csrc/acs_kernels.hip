@@ -160,6 +160,64 @@ __device__ __forceinline__ void rows_foreach(const int32_t* __restrict__ rp, Row
   }
 }
 
+// Rows of one slice x of a SELL layout for the workgroup's task lb (see Sell
+// in acs_internal.h); epi(row, sum) runs on one lane per row.  A long task
+// uses the whole workgroup and a barrier, so lb must be uniform across the
+// workgroup; waves without a task return at once.  Chunk lanes sum their
+// entries in storage order, so results are reproducible.
+template <typename VT, class Epi>
+__device__ __forceinline__ void sell_rows(const SellDev& S, const VT* __restrict__ val, int x, int lb,
+                                          const VT* __restrict__ vec, Epi& epi) {
+  const int tid = threadIdx.x;
+  const int nl = S.long_off[x + 1] - S.long_off[x];
+  const int32_t* __restrict__ col = S.col;
+  if (lb < nl) {
+    __shared__ VT red[kBlock / 64];
+    const int li = S.long_off[x] + lb;
+    const int beg = S.long_beg[li], end = S.long_end[li];
+    VT s = 0;
+    for (int k = beg + tid; k < end; k += kBlock) s += val[k] * vec[col[k]];
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+      VT tot = red[0];
+      for (int i = 1; i < kBlock / 64; ++i) tot += red[i];
+      epi(S.long_row[li], tot);
+    }
+    return;
+  }
+  const int t = S.wt_off[x] + (lb - nl) * 4 + (tid >> 6);
+  if (t >= S.wt_off[x + 1]) return;
+  const int lane = tid & 63;
+  const int ptr = S.wt_ptr[t], len = S.wt_len[t], row = S.wt_row[t];
+  if (row >= 0) {  // one row per wave
+    VT s = 0;
+    for (int k = ptr + lane; k < ptr + len; k += 64) s += val[k] * vec[col[k]];
+    s = wave_sum(s);
+    if (lane == 0) epi(row, s);
+    return;
+  }
+  const int32_t* __restrict__ c = col + ptr + lane;  // chunk: one row per lane, column-major
+  const VT* __restrict__ v = val + ptr + lane;
+  VT s = 0;
+  int k = 0;
+  for (; k + 4 <= len; k += 4) {
+    int32_t cc[4];
+    VT vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cc[u] = c[(k + u) * kSellChunk];
+      vv[u] = v[(k + u) * kSellChunk];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += vv[u] * vec[cc[u]];
+  }
+  for (; k < len; ++k) s += v[k * kSellChunk] * vec[c[k * kSellChunk]];
+  const int r = S.chunk_row[size_t(-1 - row) * kSellChunk + lane];
+  if (r >= 0) epi(r, s);
+}
+
 __device__ __forceinline__ double lorentz_dist2(double u0, double nb) {
   if (nb <= u0) return 0.0;
   if (nb <= -u0) return u0 * u0 + nb * nb;
@@ -311,20 +369,15 @@ template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
   if (d.ctl->done) return;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const RowBlock rb = d.t_blk[blk];
-  const VT* __restrict__ tv = d.t_val;
-  const int32_t* __restrict__ tc = d.t_col;
-  const VT* __restrict__ r = d.r;
   const double beta = d.ctl->beta;
   const VT vbeta = VT(beta);
-  auto prod = [&](int k) -> VT { return tv[k] * r[tc[k]]; };
   double acc[1] = {0};
   auto epi = [&](int j, VT sum) {
     const VT tj = (beta != 0.0) ? sum + vbeta * d.t[j] : sum;
     d.t[j] = tj;
     acc[0] += double(tj) * double(tj);
   };
-  rows_block<VT>(d.t_rp, rb, prod, epi);
+  sell_rows<VT>(d.st, d.st_val, 0, blk, d.r, epi);
   block_store_partials<1>(acc, d.partials, blk);
 }
 
@@ -353,15 +406,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
     }
   }
   const int x = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
-  if (lb >= d.s_off[x + 1] - d.s_off[x]) return;
-  const RowBlock rb = d.s_blk[d.s_off[x] + lb];
-  const VT* __restrict__ sv = d.s_val;
-  const int32_t* __restrict__ sc = d.s_col;
-  const VT* __restrict__ t = d.t;
+  if (lb >= d.sa.wg[x]) return;
   VT* __restrict__ part = d.part + size_t(x) * d.m;
-  auto prod = [&](int k) -> VT { return sv[k] * t[sc[k]]; };
   auto epi = [&](int i, VT sum) { part[i] = sum; };
-  rows_block<VT>(d.s_rp + size_t(x) * (d.m + 1), rb, prod, epi);
+  sell_rows<VT>(d.sa, d.sa_val, x, lb, d.t, epi);
 }
 
 // Mq_i = sum over slices (fixed order); q = r + beta q; w += alpha q; r -= alpha Mq
@@ -387,9 +435,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_comb(Dev<VT> d) {
   block_store_partials<1>(acc, d.partials, blockIdx.x);
 }
 
+// values of a SELL layout from the FP64 A_s (padding entries hold 0)
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_scale_s(Dev<VT> d, int nnz) {
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nnz; k += gridDim.x * kBlock) d.s_val[k] = VT(d.a_val64[d.s_perm[k]]);
+__global__ __launch_bounds__(kBlock) void k_sell_vals(const int32_t* __restrict__ src, int64_t count,
+                                                      const double* __restrict__ a64, VT* __restrict__ val) {
+  for (int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x; e < count; e += int64_t(gridDim.x) * kBlock) {
+    const int32_t k = src[e];
+    val[e] = k >= 0 ? VT(a64[k]) : VT(0);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -582,7 +635,6 @@ __global__ __launch_bounds__(kBlock) void k_scale_a(Dev<VT> d) {
     const int i = one ? rb.r0 : rowof[k - k0];
     const double a = d.a_orig[k] * d.O[d.a_col[k]] * d.dinv[i];
     d.a_val64[k] = a;
-    d.a_val[k] = VT(a);
   }
 }
 
@@ -598,7 +650,6 @@ __global__ __launch_bounds__(kBlock) void k_scale_t(Dev<VT> d) {
     const int j = one ? rb.r0 : rowof[k - k0];
     const double a = d.a_orig[d.t_perm[k]] * d.O[j] * d.dinv[d.t_col[k]];
     d.t_val64[k] = a;
-    d.t_val[k] = VT(a);
   }
 }
 
@@ -612,14 +663,38 @@ __global__ __launch_bounds__(kBlock) void k_chat(Dev<VT> d) {
 // plain products with the current scaled matrix (tests, bandwidth timing)
 // ----------------------------------------------------------------------------
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_spmv(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                 const VT* __restrict__ val, const RowBlock* __restrict__ blocks,
-                                                 const VT* __restrict__ x, VT* __restrict__ y) {
+__global__ __launch_bounds__(kBlock) void k_spmv_t(Dev<VT> d, const VT* __restrict__ x, VT* __restrict__ y) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const RowBlock rb = blocks[blk];
-  auto prod = [&](int k) -> VT { return val[k] * x[col[k]]; };
-  auto epi = [&](int i, VT s) { y[i] = s; };
-  rows_block<VT>(rp, rb, prod, epi);
+  auto epi = [&](int j, VT s) { y[j] = s; };
+  sell_rows<VT>(d.st, d.st_val, 0, blk, x, epi);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_spmv_a(Dev<VT> d, const VT* __restrict__ x) {
+  const int xs = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
+  if (lb >= d.sa.wg[xs]) return;
+  VT* __restrict__ part = d.part + size_t(xs) * d.m;
+  auto epi = [&](int i, VT s) { part[i] = s; };
+  sell_rows<VT>(d.sa, d.sa_val, xs, lb, x, epi);
+}
+
+// y[row_perm[i]] = sum of the slice partials of row i (same order as the CG)
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_spmv_comb(Dev<VT> d, VT* __restrict__ y) {
+  const int m = d.m;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+    VT s = d.part[i];
+#pragma unroll
+    for (int x = 1; x < kSlices; ++x) s += d.part[size_t(x) * m + i];
+    y[d.row_perm[i]] = s;
+  }
+}
+
+// internal order of a caller's m-vector: mtmp[i] = x[row_perm[i]]
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_perm_in(Dev<VT> d, const VT* __restrict__ x) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < d.m) d.mtmp[i] = x[d.row_perm[i]];
 }
 
 template <typename VT>
@@ -823,19 +898,19 @@ void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipS
 
 template <typename VT>
 void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_t<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL((k_cg_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.t_nblk);
+  hipLaunchKernelGGL((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.st.wg[0]);
 }
 
 static inline int comb_blocks(int m) { return std::min(ceil_div(m, kBlock), 2048); }
 
 template <typename VT>
 void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_a_part<VT>), dim3(kSlices * d.s_nblk_max), dim3(kBlock), 0, st, d, d.t_nblk);
+  hipLaunchKernelGGL((k_cg_a_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
 }
 
 template <typename VT>
@@ -874,18 +949,23 @@ void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
   hipLaunchKernelGGL((k_rowsum<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, wmode);
   hipLaunchKernelGGL((k_scale_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL((k_scale_t<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d);
-  const int nnz = d.a_rp_nnz;
-  hipLaunchKernelGGL((k_scale_s<VT>), dim3(std::max(1, std::min(ceil_div(nnz, kBlock), 8192))), dim3(kBlock), 0, st, d,
-                     nnz);
+  for (const auto* S : {&d.sa, &d.st}) {
+    const int nb = int(std::max<int64_t>(1, std::min<int64_t>((S->entries + kBlock - 1) / kBlock, 8192)));
+    hipLaunchKernelGGL((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, S->src, S->entries, d.a_val64,
+                       S == &d.sa ? d.sa_val : d.st_val);
+  }
   hipLaunchKernelGGL((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st) {
-  if (which == 0)
-    hipLaunchKernelGGL((k_spmv<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d.a_rp, d.a_col, d.a_val, d.a_blk, x, y);
-  else
-    hipLaunchKernelGGL((k_spmv<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d.t_rp, d.t_col, d.t_val, d.t_blk, x, y);
+  if (which == 0) {
+    hipLaunchKernelGGL((k_spmv_a<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, x);
+    hipLaunchKernelGGL((k_spmv_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d, y);
+  } else {
+    hipLaunchKernelGGL((k_perm_in<VT>), dim3(ceil_div(d.m, kBlock)), dim3(kBlock), 0, st, d, x);
+    hipLaunchKernelGGL((k_spmv_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d, d.mtmp, y);
+  }
 }
 
 template <typename VT>

@@ -22,43 +22,37 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
   if (n_soc > 0 && !soc_sizes) return fail(err, "soc_sizes is null");
   if (row_ptr[0] != 0) return fail(err, "row_ptr[0] must be 0");
   if (row_ptr[m] != nnz) return fail(err, "row_ptr[m] must equal nnz");
-  Problem& p = *out;
-  p.m = m;
-  p.n = n;
-  p.nnz = nnz;
-  p.row_ptr.resize(size_t(m) + 1);
-  for (int32_t i = 0; i <= m; ++i) {
-    if (i > 0 && row_ptr[i] < row_ptr[i - 1]) {
+  for (int32_t i = 0; i < m; ++i) {
+    if (row_ptr[i + 1] < row_ptr[i]) {
       std::ostringstream os;
-      os << "row_ptr decreases at row " << i - 1;
+      os << "row_ptr decreases at row " << i;
       return fail(err, os.str());
     }
-    p.row_ptr[i] = int32_t(row_ptr[i]);
   }
-  p.col.assign(col_idx, col_idx + nnz);
-  p.val.assign(val, val + nnz);
   for (int32_t i = 0; i < m; ++i) {
-    for (int32_t k = p.row_ptr[i]; k < p.row_ptr[i + 1]; ++k) {
-      int32_t j = p.col[k];
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int32_t j = col_idx[k];
       if (j < 0 || j >= n) {
         std::ostringstream os;
         os << "column index " << j << " out of range in row " << i;
         return fail(err, os.str());
       }
-      if (k > p.row_ptr[i] && j <= p.col[k - 1]) {
+      if (k > row_ptr[i] && j <= col_idx[k - 1]) {
         std::ostringstream os;
         os << "column indices not strictly ascending in row " << i;
         return fail(err, os.str());
       }
-      if (!std::isfinite(p.val[k])) return fail(err, "non-finite matrix value");
+      if (!std::isfinite(val[k])) return fail(err, "non-finite matrix value");
     }
   }
-  p.b.assign(b, b + m);
-  p.c.assign(c, c + n);
-  for (double v : p.b)
-    if (!std::isfinite(v)) return fail(err, "non-finite entry in b");
-  for (double v : p.c)
-    if (!std::isfinite(v)) return fail(err, "non-finite entry in c");
+  for (int32_t i = 0; i < m; ++i)
+    if (!std::isfinite(b[i])) return fail(err, "non-finite entry in b");
+  for (int32_t j = 0; j < n; ++j)
+    if (!std::isfinite(c[j])) return fail(err, "non-finite entry in c");
+  Problem& p = *out;
+  p.m = m;
+  p.n = n;
+  p.nnz = nnz;
   int64_t total = n_orth;
   p.n_orth = n_orth;
   p.soc_size.assign(soc_sizes, soc_sizes + n_soc);
@@ -74,6 +68,27 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
   }
   if (total != n) return fail(err, "n_orth + sum(soc_sizes) must equal n");
 
+  // rows by decreasing length, ties in the caller's order
+  p.row_perm.resize(m);
+  for (int32_t i = 0; i < m; ++i) p.row_perm[i] = i;
+  std::stable_sort(p.row_perm.begin(), p.row_perm.end(), [&](int32_t a, int32_t b2) {
+    return row_ptr[a + 1] - row_ptr[a] > row_ptr[b2 + 1] - row_ptr[b2];
+  });
+  p.row_ptr.resize(size_t(m) + 1);
+  p.col.resize(nnz);
+  p.val.resize(nnz);
+  p.b.resize(m);
+  p.row_ptr[0] = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t o = p.row_perm[i];
+    const int64_t k0 = row_ptr[o], len = row_ptr[o + 1] - k0;
+    std::copy(col_idx + k0, col_idx + k0 + len, p.col.begin() + p.row_ptr[i]);
+    std::copy(val + k0, val + k0 + len, p.val.begin() + p.row_ptr[i]);
+    p.row_ptr[i + 1] = p.row_ptr[i] + int32_t(len);
+    p.b[i] = b[o];
+  }
+  p.c.assign(c, c + n);
+
   // transpose pattern by counting sort over columns (columns ascending in A^T rows = rows of A)
   p.t_row_ptr.assign(size_t(n) + 1, 0);
   for (int64_t k = 0; k < nnz; ++k) p.t_row_ptr[p.col[k] + 1]++;
@@ -88,41 +103,6 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
       p.t_perm[pos] = k;
     }
   }
-  // column slices of A (one per XCD): gathers of an n-vector stay within 1/kSlices of it
-  {
-    const int64_t w = (int64_t(n) + kSlices - 1) / kSlices;
-    p.s_row_ptr.assign(size_t(kSlices) * (m + 1), 0);
-    for (int32_t i = 0; i < m; ++i)
-      for (int32_t k = p.row_ptr[i]; k < p.row_ptr[i + 1]; ++k) {
-        const int x = int(p.col[k] / w);
-        p.s_row_ptr[size_t(x) * (m + 1) + i + 1]++;
-      }
-    int32_t base = 0;
-    for (int x = 0; x < kSlices; ++x) {
-      int32_t* rp = &p.s_row_ptr[size_t(x) * (m + 1)];
-      rp[0] = base;
-      for (int32_t i = 0; i < m; ++i) rp[i + 1] += rp[i];
-      base = rp[m];
-    }
-    p.s_col.resize(nnz);
-    p.s_perm.resize(nnz);
-    std::vector<int32_t> fill(size_t(kSlices) * m);
-    for (int x = 0; x < kSlices; ++x)
-      for (int32_t i = 0; i < m; ++i) fill[size_t(x) * m + i] = p.s_row_ptr[size_t(x) * (m + 1) + i];
-    for (int32_t i = 0; i < m; ++i)
-      for (int32_t k = p.row_ptr[i]; k < p.row_ptr[i + 1]; ++k) {
-        const int x = int(p.col[k] / w);
-        const int32_t pos = fill[size_t(x) * m + i]++;
-        p.s_col[pos] = p.col[k];
-        p.s_perm[pos] = k;
-      }
-    p.s_blk_off.assign(kSlices + 1, 0);
-    for (int x = 0; x < kSlices; ++x) {
-      std::vector<RowBlock> b = make_row_blocks(&p.s_row_ptr[size_t(x) * (m + 1)], m, kStageNnz);
-      p.s_blocks.insert(p.s_blocks.end(), b.begin(), b.end());
-      p.s_blk_off[x + 1] = int32_t(p.s_blocks.size());
-    }
-  }
   p.a_blocks = make_row_blocks(p.row_ptr.data(), m, kStageNnz);
   p.t_blocks = make_row_blocks(p.t_row_ptr.data(), n, kStageNnz);
   double bb = 0, cc = 0;
@@ -130,6 +110,154 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
   for (double v : p.c) cc += v * v;
   p.bnorm = std::sqrt(bb);
   p.cnorm = std::sqrt(cc);
+  return true;
+}
+
+const SellPair& Problem::sell() const {
+  std::call_once(sell_once_, [this] {
+    auto sp = std::make_unique<SellPair>();
+    // A t by column slices [x*w, (x+1)*w), w = ceil(n/kSlices): slice x holds
+    // the nonzeros of its columns, in row order
+    const int64_t w = (int64_t(n) + kSlices - 1) / kSlices;
+    std::vector<int32_t> srp(size_t(kSlices) * (m + 1), 0), scol(nnz), ssrc(nnz);
+    for (int32_t i = 0; i < m; ++i)
+      for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) srp[size_t(col[k] / w) * (m + 1) + i + 1]++;
+    int32_t base = 0;
+    for (int x = 0; x < kSlices; ++x) {
+      int32_t* rp = &srp[size_t(x) * (m + 1)];
+      rp[0] = base;
+      for (int32_t i = 0; i < m; ++i) rp[i + 1] += rp[i];
+      base = rp[m];
+    }
+    std::vector<int32_t> fill(size_t(kSlices) * m);
+    for (int x = 0; x < kSlices; ++x)
+      for (int32_t i = 0; i < m; ++i) fill[size_t(x) * m + i] = srp[size_t(x) * (m + 1) + i];
+    for (int32_t i = 0; i < m; ++i)
+      for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        const int32_t pos = fill[size_t(col[k] / w) * m + i]++;
+        scol[pos] = col[k];
+        ssrc[pos] = k;
+      }
+    std::vector<const int32_t*> rps;
+    std::vector<int32_t> pads;
+    for (int x = 0; x < kSlices; ++x) {
+      rps.push_back(&srp[size_t(x) * (m + 1)]);
+      pads.push_back(int32_t(std::min<int64_t>(x * w, n - 1)));
+    }
+    build_sell(rps, m, scol.data(), ssrc.data(), pads, &sp->a);
+    build_sell({t_row_ptr.data()}, n, t_col.data(), t_perm.data(), {0}, &sp->t);
+    std::string err;
+    if (!check_sell(sp->a, m, nnz, &err) || !check_sell(sp->t, n, nnz, &err))
+      throw AcsError(ACS_ERR_DEVICE, "internal error in the SELL layout: " + err);
+    sell_ = std::move(sp);
+  });
+  return *sell_;
+}
+
+void build_sell(const std::vector<const int32_t*>& rps, int32_t rows, const int32_t* col, const int32_t* src,
+                const std::vector<int32_t>& pad, Sell* out) {
+  Sell& S = *out;
+  S = Sell();
+  S.slices = int32_t(rps.size());
+  S.long_off.push_back(0);
+  S.wt_off.push_back(0);
+  int64_t used = 0;
+  auto append = [&](int32_t c, int32_t s) {
+    S.col.push_back(c);
+    S.src.push_back(s);
+    if (++used >= (int64_t(1) << 31) - 1) throw AcsError(ACS_ERR_ARG, "matrix too large for the SELL layout");
+  };
+  for (int x = 0; x < S.slices; ++x) {
+    const int32_t* rp = rps[x];
+    auto len = [&](int32_t i) { return rp[i + 1] - rp[i]; };
+    std::vector<int32_t> longs, waves;
+    for (int32_t i = 0; i < rows; ++i) {
+      if (len(i) > kWaveRowMax)
+        longs.push_back(i);
+      else if (len(i) > kSellMaxLen)
+        waves.push_back(i);
+    }
+    auto by_len = [&](int32_t a, int32_t b) { return len(a) > len(b); };
+    std::stable_sort(longs.begin(), longs.end(), by_len);
+    std::stable_sort(waves.begin(), waves.end(), by_len);
+    for (int32_t i : longs) {
+      S.long_row.push_back(i);
+      S.long_beg.push_back(int32_t(used));
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) append(col[k], src[k]);
+      S.long_end.push_back(int32_t(used));
+    }
+    for (int32_t i : waves) {
+      S.wt_ptr.push_back(int32_t(used));
+      S.wt_len.push_back(len(i));
+      S.wt_row.push_back(i);
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) append(col[k], src[k]);
+    }
+    std::vector<int32_t> win;
+    for (int32_t w0 = 0; w0 < rows; w0 += kSellWindow) {
+      win.clear();
+      const int32_t w1 = std::min<int32_t>(rows, w0 + kSellWindow);
+      for (int32_t i = w0; i < w1; ++i)
+        if (len(i) <= kSellMaxLen) win.push_back(i);
+      std::stable_sort(win.begin(), win.end(), by_len);
+      for (size_t c0 = 0; c0 < win.size(); c0 += kSellChunk) {
+        const size_t c1 = std::min(win.size(), c0 + kSellChunk);
+        int32_t clen = 0;
+        for (size_t q = c0; q < c1; ++q) clen = std::max(clen, len(win[q]));
+        const int32_t chunk = int32_t(S.chunk_row.size() / kSellChunk);
+        S.wt_ptr.push_back(int32_t(used));
+        S.wt_len.push_back(clen);
+        S.wt_row.push_back(-1 - chunk);
+        for (int l = 0; l < kSellChunk; ++l) S.chunk_row.push_back(c0 + l < c1 ? win[c0 + l] : -1);
+        for (int32_t k = 0; k < clen; ++k)
+          for (int l = 0; l < kSellChunk; ++l) {
+            const int32_t i = c0 + l < c1 ? win[c0 + l] : -1;
+            if (i >= 0 && k < len(i))
+              append(col[rp[i] + k], src[rp[i] + k]);
+            else
+              append(pad[x], -1);
+          }
+      }
+    }
+    S.long_off.push_back(int32_t(S.long_row.size()));
+    S.wt_off.push_back(int32_t(S.wt_ptr.size()));
+    const int32_t nl = S.long_off[x + 1] - S.long_off[x], nw = S.wt_off[x + 1] - S.wt_off[x];
+    S.wg.push_back(nl + (nw + 3) / 4);
+    S.wg_max = std::max(S.wg_max, S.wg.back());
+  }
+}
+
+bool check_sell(const Sell& S, int32_t rows, int64_t entries, std::string* err) {
+  int64_t real = 0;
+  std::vector<uint8_t> seen;
+  for (int x = 0; x < S.slices; ++x) {
+    seen.assign(rows, 0);
+    auto mark = [&](int32_t i) {
+      if (i < 0 || i >= rows || seen[i]) return false;
+      seen[i] = 1;
+      return true;
+    };
+    for (int32_t t = S.long_off[x]; t < S.long_off[x + 1]; ++t) {
+      if (!mark(S.long_row[t])) return fail(err, "long row repeated or out of range");
+      real += S.long_end[t] - S.long_beg[t];
+    }
+    for (int32_t t = S.wt_off[x]; t < S.wt_off[x + 1]; ++t) {
+      if (S.wt_row[t] >= 0) {
+        if (!mark(S.wt_row[t])) return fail(err, "wave row repeated or out of range");
+        real += S.wt_len[t];
+      } else {
+        const int32_t c = -1 - S.wt_row[t];
+        for (int l = 0; l < kSellChunk; ++l) {
+          const int32_t i = S.chunk_row[size_t(c) * kSellChunk + l];
+          if (i >= 0 && !mark(i)) return fail(err, "chunk row repeated or out of range");
+          for (int32_t k = 0; k < S.wt_len[t]; ++k)
+            if (S.src[size_t(S.wt_ptr[t]) + size_t(k) * kSellChunk + l] >= 0) ++real;
+        }
+      }
+    }
+    for (int32_t i = 0; i < rows; ++i)
+      if (!seen[i]) return fail(err, "row not covered");
+  }
+  if (real != entries) return fail(err, "entry count mismatch");
   return true;
 }
 

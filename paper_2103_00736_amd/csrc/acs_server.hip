@@ -293,7 +293,11 @@ class Server {
       r->y.resize(p.m);
       SHIP(hipMemcpy(r->x.data(), sl.host.x, sizeof(double) * p.n, hipMemcpyDeviceToHost));
       SHIP(hipMemcpy(r->z.data(), sl.host.z, sizeof(double) * p.n, hipMemcpyDeviceToHost));
-      SHIP(hipMemcpy(r->y.data(), sl.host.y, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+      {
+        std::vector<double> yi(p.m);  // internal row order -> caller's
+        SHIP(hipMemcpy(yi.data(), sl.host.y, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+        for (int k = 0; k < p.m; ++k) r->y[p.row_perm[k]] = yi[k];
+      }
       acs_info& in = r->info;
       std::memset(&in, 0, sizeof(in));
       in.status = st.status < 0 ? ACS_MAX_ITER : st.status;

@@ -222,15 +222,19 @@ class DeviceArena {
 static int64_t estimate_bytes(const Problem& p, int precision) {
   const int64_t vt = precision == ACS_PREC_FP64 ? 8 : 4;
   const int64_t nnz = p.nnz, m = p.m, n = p.n;
+  const SellPair& sp = p.sell();
   int64_t b = 0;
-  b += 4 * (m + 1) + 4 * nnz + vt * nnz + 8 * nnz;       // A pattern, scaled values, original values
-  b += 4 * (n + 1) + 4 * nnz + vt * nnz + 4 * nnz;       // A^T pattern, values, perm
-  if (vt == 4) b += 16 * nnz;                            // FP64 copies for the refinement sweeps
-  b += (8 + vt) * nnz + 4 * kSlices * (m + 1) + vt * kSlices * m;  // column-sliced copy of A + partials
+  b += 4 * (m + 1) + 4 * nnz + 8 * nnz + 8 * nnz;        // A pattern, original and FP64 scaled values
+  b += 4 * (n + 1) + 4 * nnz + 8 * nnz + 4 * nnz;        // A^T pattern, FP64 values, perm
+  for (const Sell* S : {&sp.a, &sp.t})                   // SELL layouts: entries, tasks, chunk rows
+    b += (8 + vt) * int64_t(S->col.size()) + 12 * int64_t(S->wt_ptr.size() + S->long_row.size()) +
+         4 * int64_t(S->chunk_row.size());
+  b += vt * kSlices * m + (4 + vt) * m;                  // slice partials, row permutation, scratch
   b += 8 * int64_t(p.a_blocks.size() + p.t_blocks.size());
   b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
-  b += 8 * 8 * int64_t(std::max<size_t>(std::max(p.a_blocks.size(), p.t_blocks.size()), size_t(n / kBlock + 2)));
-  b += 8 * int64_t(p.s_blocks.size()) + 64 * 256;  // sliced row blocks, per-array alignment
+  const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max),
+                                         size_t(n / kBlock + 2)});
+  b += 8 * 8 * int64_t(parts) + 64 * 256;                // partials, per-array alignment
   return b;
 }
 
@@ -334,41 +338,50 @@ class Instance final : public InstanceBase {
     d.a_rp = a_rp;
     d.a_col = a_col;
     d.a_orig = a_orig;
-    d.a_val = arena_.alloc<VT>(p.nnz);
     d.t_rp = t_rp;
     d.t_col = t_col;
     d.t_perm = t_perm;
-    d.t_val = arena_.alloc<VT>(p.nnz);
-    if (sizeof(VT) == sizeof(double)) {
-      d.a_val64 = reinterpret_cast<double*>(d.a_val);
-      d.t_val64 = reinterpret_cast<double*>(d.t_val);
-    } else {
-      d.a_val64 = arena_.alloc<double>(p.nnz);
-      d.t_val64 = arena_.alloc<double>(p.nnz);
-    }
+    d.a_val64 = arena_.alloc<double>(p.nnz);
+    d.t_val64 = arena_.alloc<double>(p.nnz);
     d.a_blk = a_blk;
     d.a_nblk = int(p.a_blocks.size());
     d.a_rp_nnz = int32_t(p.nnz);
     {
-      int32_t* s_rp = arena_.alloc<int32_t>(p.s_row_ptr.size());
-      int32_t* s_col = arena_.alloc<int32_t>(p.nnz);
-      int32_t* s_perm = arena_.alloc<int32_t>(p.nnz);
-      RowBlock* s_blk = arena_.alloc<RowBlock>(p.s_blocks.size());
-      up(s_rp, p.s_row_ptr);
-      if (p.nnz) {
-        up(s_col, p.s_col);
-        up(s_perm, p.s_perm);
-      }
-      up(s_blk, p.s_blocks);
-      d.s_rp = s_rp;
-      d.s_col = s_col;
-      d.s_perm = s_perm;
-      d.s_blk = s_blk;
-      d.s_val = arena_.alloc<VT>(p.nnz);
-      d.s_nblk_max = 1;
-      for (int x = 0; x <= kSlices; ++x) d.s_off[x] = p.s_blk_off[x];
-      for (int x = 0; x < kSlices; ++x) d.s_nblk_max = std::max(d.s_nblk_max, p.s_blk_off[x + 1] - p.s_blk_off[x]);
+      const SellPair& sp = p.sell();
+      auto sell_dev = [&](const Sell& S, SellDev* D) {
+        auto put = [&](const std::vector<int32_t>& v) -> const int32_t* {
+          int32_t* ptr = arena_.alloc<int32_t>(std::max<size_t>(v.size(), 1));
+          if (!v.empty()) up(ptr, v);
+          return ptr;
+        };
+        std::memset(D, 0, sizeof(*D));
+        D->long_row = put(S.long_row);
+        D->long_beg = put(S.long_beg);
+        D->long_end = put(S.long_end);
+        D->wt_ptr = put(S.wt_ptr);
+        D->wt_len = put(S.wt_len);
+        D->wt_row = put(S.wt_row);
+        D->chunk_row = put(S.chunk_row);
+        D->col = put(S.col);
+        D->src = put(S.src);
+        D->entries = int64_t(S.col.size());
+        D->slices = S.slices;
+        for (int x = 0; x <= S.slices; ++x) {
+          D->long_off[x] = S.long_off[x];
+          D->wt_off[x] = S.wt_off[x];
+        }
+        for (int x = 0; x < S.slices; ++x) D->wg[x] = S.wg[x];
+        D->wg_max = S.wg_max;
+      };
+      sell_dev(sp.a, &d.sa);
+      sell_dev(sp.t, &d.st);
+      d.sa_val = arena_.alloc<VT>(std::max<size_t>(sp.a.col.size(), 1));
+      d.st_val = arena_.alloc<VT>(std::max<size_t>(sp.t.col.size(), 1));
       d.part = arena_.alloc<VT>(size_t(kSlices) * p.m);
+      int32_t* rperm = arena_.alloc<int32_t>(p.m);
+      up(rperm, p.row_perm);
+      d.row_perm = rperm;
+      d.mtmp = arena_.alloc<VT>(p.m);
     }
     d.t_blk = t_blk;
     d.t_nblk = int(p.t_blocks.size());
@@ -396,7 +409,7 @@ class Instance final : public InstanceBase {
     d.ounit = arena_.alloc<double>(size_t(p.n_orth) + p.soc_size.size());
     d.ctl = arena_.alloc<Ctl>(1);
     const size_t units = size_t(p.n_orth) + p.soc_size.size();
-    nparts_ = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), units / kBlock + 1,
+    nparts_ = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(d.st.wg_max), units / kBlock + 1,
                                  p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, 1});
     d.partials = arena_.alloc<double>(nparts_ * 8);
     s_buf_[0] = arena_.alloc<VT>(p.n);
@@ -469,7 +482,12 @@ class Instance final : public InstanceBase {
     upload_vt(s_buf_[0], s, p.n);
     upload_vt(s_buf_[1], s_prev, p.n);
     HIP_CHECK(hipMemcpyAsync(d_.O, O, sizeof(double) * p.n, hipMemcpyHostToDevice, st_));
-    HIP_CHECK(hipMemcpyAsync(d_.w, w, sizeof(double) * p.m, hipMemcpyHostToDevice, st_));
+    {
+      std::vector<double> wi(p.m);  // internal row order
+      for (int i = 0; i < p.m; ++i) wi[i] = w[p.row_perm[i]];
+      HIP_CHECK(hipMemcpyAsync(d_.w, wi.data(), sizeof(double) * p.m, hipMemcpyHostToDevice, st_));
+      HIP_CHECK(hipStreamSynchronize(st_));
+    }
     launch_ctl_reset(d_, S.cg_max, st_);
     launch_rescale(d_, 2, st_);  // A_s, b_s, chat for O; w -> scaled
     check_launch();
@@ -719,13 +737,17 @@ class Instance final : public InstanceBase {
       std::vector<double> ws(p.m), di(p.m);
       HIP_CHECK(hipMemcpy(ws.data(), d_.w, sizeof(double) * p.m, hipMemcpyDeviceToHost));
       HIP_CHECK(hipMemcpy(di.data(), d_.dinv, sizeof(double) * p.m, hipMemcpyDeviceToHost));
-      for (int i = 0; i < p.m; ++i) w[i] = ws[i] * di[i];
+      for (int i = 0; i < p.m; ++i) w[p.row_perm[i]] = ws[i] * di[i];
     }
     if (x || y || z) {
       if (!have_xyz_) throw AcsError(ACS_ERR_STATE, "x, y, z need at least one iteration after the state was set");
       if (x) HIP_CHECK(hipMemcpy(x, d_.xout, sizeof(double) * p.n, hipMemcpyDeviceToHost));
       if (z) HIP_CHECK(hipMemcpy(z, d_.zout, sizeof(double) * p.n, hipMemcpyDeviceToHost));
-      if (y) HIP_CHECK(hipMemcpy(y, d_.yout, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+      if (y) {
+        std::vector<double> yi(p.m);
+        HIP_CHECK(hipMemcpy(yi.data(), d_.yout, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+        for (int i = 0; i < p.m; ++i) y[p.row_perm[i]] = yi[i];
+      }
     }
   }
 

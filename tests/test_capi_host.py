@@ -91,3 +91,12 @@ def test_no_gpu_here_is_a_clean_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert acs.lib().acs_init(0) == acs.ACS_ERR_DEVICE
+
+
+def test_device_byte_estimates_are_host_code():
+    p = synth.config3(3, m=300)
+    h = acs.Problem.from_synth(p)
+    one, fp64, pool = h.device_bytes(), h.device_bytes(acs.PREC_FP64), h.batch_device_bytes()
+    # at least the matrix in CSR (index + FP32 value) and both transposes' indices
+    assert one >= 12 * p.nnz and fp64 > one and pool >= 8 * p.nnz
+    h.close()

@@ -66,7 +66,7 @@ def test_mixed_stream_matches_oracle_and_alone():
 def test_budget_backpressure_and_rejection():
     probs = [synth.config3(i, m=m) for i, m in enumerate([400, 380, 360, 340, 320])]
     handles = [acs.Problem.from_synth(p) for p in probs]
-    one = max(h.device_bytes() for h in handles)
+    one = max(h.batch_device_bytes() for h in handles)  # every request goes to the pool here
     srv = acs.Server(hbm_budget=int(2.5 * one), max_slots=8, small_nnz=1 << 30, workers=1, tick_iters=25)
     tickets = [srv.submit(h) for h in handles]
     res = [srv.wait(t, 120_000) for t in tickets]
