@@ -24,9 +24,9 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kStageNnz = 2048;   // products staged in LDS per multi-row block
 constexpr int kSlices = 8;        // column slices of A, one per XCD
 constexpr int kSellChunk = 64;    // rows per SELL chunk (one per lane of a wave64)
-constexpr int kSellMaxLen = 32;   // longest row packed into a chunk
+constexpr int kSellMaxLen = 64;   // longest row packed into a chunk
 constexpr int kWaveRowMax = 2048; // longest row given to one wave; longer rows get a workgroup
-constexpr int kSellWindow = 4096; // rows sorted by length within windows of this many rows
+constexpr int kSellWindow = 16384; // rows sorted by length within windows of this many rows
 
 // SELL-64 layout of the products of the CG (each output row is a dot product
 // of a sparse row with a gathered vector).  The rows are split into slices
@@ -48,8 +48,9 @@ struct Sell {
   std::vector<int32_t> wt_off;  // slices+1 offsets into wt_*
   std::vector<int32_t> wt_ptr;  // first entry of the task
   std::vector<int32_t> wt_len;  // entries of the row (wave row) or per lane (chunk)
-  std::vector<int32_t> wt_row;  // >= 0: row of a wave-row task; < 0: -1 - chunk index
-  std::vector<int32_t> chunk_row;  // kSellChunk per chunk: row of each lane, -1 = unused lane
+  std::vector<int32_t> wt_row;  // >= 0: row of a wave-row task; -1: a chunk
+  std::vector<int32_t> chunk_row;  // kSellChunk per wave task (indexed by task): row of each
+                                   // lane of a chunk, -1 = unused lane (all -1 for wave rows)
   std::vector<int32_t> col;        // column of each entry
   std::vector<int32_t> src;        // position of the entry in A's CSR, -1 = padding
   std::vector<int32_t> wg;         // workgroups of each slice: long tasks + ceil(wave tasks / 4)
@@ -106,7 +107,8 @@ std::vector<RowBlock> make_row_blocks(const int32_t* row_ptr, int32_t rows, int3
 // [rp[x][i], rp[x][i+1]) of (col, src); pad[x] is the column that padding
 // entries point at.  Throws AcsError if the layout would exceed 2^31-1 entries.
 void build_sell(const std::vector<const int32_t*>& rp, int32_t rows, const int32_t* col, const int32_t* src,
-                const std::vector<int32_t>& pad, Sell* out);
+                const std::vector<int32_t>& pad, Sell* out, int32_t window = kSellWindow,
+                int32_t max_len = kSellMaxLen);
 // Checks that every row of every slice is covered once and every entry once.
 bool check_sell(const Sell& s, int32_t rows, int64_t entries, std::string* err);
 

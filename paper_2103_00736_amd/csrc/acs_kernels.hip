@@ -160,14 +160,92 @@ __device__ __forceinline__ void rows_foreach(const int32_t* __restrict__ rp, Row
   }
 }
 
+// Dot products over strided SELL entries, s += v[e*stride] * vec[c[e*stride]]
+// in order of e.  The loads of a group of entries are issued together
+// (indices and values, then the gathers) so a lane keeps several requests in
+// flight, and no load sits behind a branch (the compiler would wait for every
+// outstanding load at the join).  Each entry is loaded once.
+
+// exactly N entries
+template <int N, typename VT>
+__device__ __forceinline__ void dot_exact(const int32_t* __restrict__ c, const VT* __restrict__ v, int stride,
+                                          const VT* __restrict__ vec, VT& s) {
+  int32_t cc[N];
+  VT vv[N], g[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    cc[u] = c[u * stride];
+    vv[u] = v[u * stride];
+  }
+#pragma unroll
+  for (int u = 0; u < N; ++u) g[u] = vec[cc[u]];
+#pragma unroll
+  for (int u = 0; u < N; ++u) s += vv[u] * g[u];
+}
+
+// count entries, count uniform across the wave: groups of 8, then the rest
+template <typename VT>
+__device__ __forceinline__ VT dot_uniform(const int32_t* __restrict__ c, const VT* __restrict__ v, int count,
+                                          int stride, const VT* __restrict__ vec) {
+  VT s = 0;
+  int e = 0;
+  for (; e + 8 <= count; e += 8) dot_exact<8>(c + e * stride, v + e * stride, stride, vec, s);
+  c += e * stride;
+  v += e * stride;
+  switch (count - e) {
+    case 1: dot_exact<1>(c, v, stride, vec, s); break;
+    case 2: dot_exact<2>(c, v, stride, vec, s); break;
+    case 3: dot_exact<3>(c, v, stride, vec, s); break;
+    case 4: dot_exact<4>(c, v, stride, vec, s); break;
+    case 5: dot_exact<5>(c, v, stride, vec, s); break;
+    case 6: dot_exact<6>(c, v, stride, vec, s); break;
+    case 7: dot_exact<7>(c, v, stride, vec, s); break;
+    default: break;
+  }
+  return s;
+}
+
+// a row of len >= 1 entries at c[0..len), v[0..len) shared by `lanes` lanes:
+// lane l takes entries l, l + lanes, ...  Groups of up to 8 per lane, the
+// count of groups uniform across the lanes; a lane past the row's end reads
+// the row's last entry again and drops the product.
+template <typename VT>
+__device__ __forceinline__ VT dot_row(const int32_t* __restrict__ c, const VT* __restrict__ v, int len, int lane,
+                                      int lanes, const VT* __restrict__ vec) {
+  const int per = (len + lanes - 1) / lanes;  // entries of the busiest lane
+  VT s = 0;
+  for (int e0 = 0; e0 < per; e0 += 8) {
+    int32_t cc[8];
+    VT vv[8], g[8];
+    bool ok[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = lane + (e0 + u) * lanes;
+      ok[u] = e0 + u < per && e < len;
+      const int ec = ok[u] ? e : len - 1;
+      cc[u] = c[ec];
+      vv[u] = v[ec];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g[u] = vec[cc[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const VT prod = vv[u] * g[u];
+      s += ok[u] ? prod : VT(0);
+    }
+  }
+  return s;
+}
+
 // Rows of one slice x of a SELL layout for the workgroup's task lb (see Sell
-// in acs_internal.h); epi(row, sum) runs on one lane per row.  A long task
-// uses the whole workgroup and a barrier, so lb must be uniform across the
-// workgroup; waves without a task return at once.  Chunk lanes sum their
-// entries in storage order, so results are reproducible.
-template <typename VT, class Epi>
+// in acs_internal.h).  pre(row) runs on the lane owning a row before its
+// product (to start loads the epilogue needs); epi(row, sum, pre_value) runs
+// after it.  A long task uses the whole workgroup and a barrier, so lb must
+// be uniform across the workgroup; waves without a task return at once.
+// Entries are summed in storage order, so results are reproducible.
+template <typename VT, class Pre, class Epi>
 __device__ __forceinline__ void sell_rows(const SellDev& S, const VT* __restrict__ val, int x, int lb,
-                                          const VT* __restrict__ vec, Epi& epi) {
+                                          const VT* __restrict__ vec, Pre& pre, Epi& epi) {
   const int tid = threadIdx.x;
   const int nl = S.long_off[x + 1] - S.long_off[x];
   const int32_t* __restrict__ col = S.col;
@@ -175,15 +253,16 @@ __device__ __forceinline__ void sell_rows(const SellDev& S, const VT* __restrict
     __shared__ VT red[kBlock / 64];
     const int li = S.long_off[x] + lb;
     const int beg = S.long_beg[li], end = S.long_end[li];
-    VT s = 0;
-    for (int k = beg + tid; k < end; k += kBlock) s += val[k] * vec[col[k]];
+    const int row = S.long_row[li];
+    const VT pv = tid == 0 ? pre(row) : VT(0);
+    VT s = dot_row<VT>(col + beg, val + beg, end - beg, tid, kBlock, vec);
     s = wave_sum(s);
     if ((tid & 63) == 0) red[tid >> 6] = s;
     __syncthreads();
     if (tid == 0) {
       VT tot = red[0];
       for (int i = 1; i < kBlock / 64; ++i) tot += red[i];
-      epi(S.long_row[li], tot);
+      epi(row, tot, pv);
     }
     return;
   }
@@ -191,31 +270,18 @@ __device__ __forceinline__ void sell_rows(const SellDev& S, const VT* __restrict
   if (t >= S.wt_off[x + 1]) return;
   const int lane = tid & 63;
   const int ptr = S.wt_ptr[t], len = S.wt_len[t], row = S.wt_row[t];
-  if (row >= 0) {  // one row per wave
-    VT s = 0;
-    for (int k = ptr + lane; k < ptr + len; k += 64) s += val[k] * vec[col[k]];
+  const int r = S.chunk_row[size_t(t) * kSellChunk + lane];  // independent of the loads above
+  if (row >= 0) {  // one row per wave, lanes stride the row
+    const VT pv = lane == 0 ? pre(row) : VT(0);
+    VT s = dot_row<VT>(col + ptr, val + ptr, len, lane, 64, vec);
     s = wave_sum(s);
-    if (lane == 0) epi(row, s);
+    if (lane == 0) epi(row, s, pv);
     return;
   }
-  const int32_t* __restrict__ c = col + ptr + lane;  // chunk: one row per lane, column-major
-  const VT* __restrict__ v = val + ptr + lane;
-  VT s = 0;
-  int k = 0;
-  for (; k + 4 <= len; k += 4) {
-    int32_t cc[4];
-    VT vv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      cc[u] = c[(k + u) * kSellChunk];
-      vv[u] = v[(k + u) * kSellChunk];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) s += vv[u] * vec[cc[u]];
-  }
-  for (; k < len; ++k) s += v[k * kSellChunk] * vec[c[k * kSellChunk]];
-  const int r = S.chunk_row[size_t(-1 - row) * kSellChunk + lane];
-  if (r >= 0) epi(r, s);
+  // chunk: one row per lane, entries column-major
+  const VT pv = r >= 0 ? pre(r) : VT(0);
+  const VT s = dot_uniform<VT>(col + ptr + lane, val + ptr + lane, len, kSellChunk, vec);
+  if (r >= 0) epi(r, s, pv);
 }
 
 __device__ __forceinline__ double lorentz_dist2(double u0, double nb) {
@@ -372,12 +438,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
   const double beta = d.ctl->beta;
   const VT vbeta = VT(beta);
   double acc[1] = {0};
-  auto epi = [&](int j, VT sum) {
-    const VT tj = (beta != 0.0) ? sum + vbeta * d.t[j] : sum;
+  auto pre = [&](int j) -> VT { return beta != 0.0 ? d.t[j] : VT(0); };
+  auto epi = [&](int j, VT sum, VT t_old) {
+    const VT tj = (beta != 0.0) ? sum + vbeta * t_old : sum;
     d.t[j] = tj;
     acc[0] += double(tj) * double(tj);
   };
-  sell_rows<VT>(d.st, d.st_val, 0, blk, d.r, epi);
+  sell_rows<VT>(d.st, d.st_val, 0, blk, d.r, pre, epi);
   block_store_partials<1>(acc, d.partials, blk);
 }
 
@@ -408,8 +475,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
   const int x = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
   if (lb >= d.sa.wg[x]) return;
   VT* __restrict__ part = d.part + size_t(x) * d.m;
-  auto epi = [&](int i, VT sum) { part[i] = sum; };
-  sell_rows<VT>(d.sa, d.sa_val, x, lb, d.t, epi);
+  auto pre = [](int) -> VT { return VT(0); };
+  auto epi = [&](int i, VT sum, VT) { part[i] = sum; };
+  sell_rows<VT>(d.sa, d.sa_val, x, lb, d.t, pre, epi);
 }
 
 // Mq_i = sum over slices (fixed order); q = r + beta q; w += alpha q; r -= alpha Mq
@@ -665,8 +733,9 @@ __global__ __launch_bounds__(kBlock) void k_chat(Dev<VT> d) {
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_spmv_t(Dev<VT> d, const VT* __restrict__ x, VT* __restrict__ y) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  auto epi = [&](int j, VT s) { y[j] = s; };
-  sell_rows<VT>(d.st, d.st_val, 0, blk, x, epi);
+  auto pre = [](int) -> VT { return VT(0); };
+  auto epi = [&](int j, VT s, VT) { y[j] = s; };
+  sell_rows<VT>(d.st, d.st_val, 0, blk, x, pre, epi);
 }
 
 template <typename VT>
@@ -674,8 +743,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_a(Dev<VT> d, const VT* __restri
   const int xs = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
   if (lb >= d.sa.wg[xs]) return;
   VT* __restrict__ part = d.part + size_t(xs) * d.m;
-  auto epi = [&](int i, VT s) { part[i] = s; };
-  sell_rows<VT>(d.sa, d.sa_val, xs, lb, x, epi);
+  auto pre = [](int) -> VT { return VT(0); };
+  auto epi = [&](int i, VT s, VT) { part[i] = s; };
+  sell_rows<VT>(d.sa, d.sa_val, xs, lb, x, pre, epi);
 }
 
 // y[row_perm[i]] = sum of the slice partials of row i (same order as the CG)

@@ -155,7 +155,7 @@ const SellPair& Problem::sell() const {
 }
 
 void build_sell(const std::vector<const int32_t*>& rps, int32_t rows, const int32_t* col, const int32_t* src,
-                const std::vector<int32_t>& pad, Sell* out) {
+                const std::vector<int32_t>& pad, Sell* out, int32_t window, int32_t max_len) {
   Sell& S = *out;
   S = Sell();
   S.slices = int32_t(rps.size());
@@ -174,7 +174,7 @@ void build_sell(const std::vector<const int32_t*>& rps, int32_t rows, const int3
     for (int32_t i = 0; i < rows; ++i) {
       if (len(i) > kWaveRowMax)
         longs.push_back(i);
-      else if (len(i) > kSellMaxLen)
+      else if (len(i) > max_len)
         waves.push_back(i);
     }
     auto by_len = [&](int32_t a, int32_t b) { return len(a) > len(b); };
@@ -190,23 +190,23 @@ void build_sell(const std::vector<const int32_t*>& rps, int32_t rows, const int3
       S.wt_ptr.push_back(int32_t(used));
       S.wt_len.push_back(len(i));
       S.wt_row.push_back(i);
+      for (int l = 0; l < kSellChunk; ++l) S.chunk_row.push_back(-1);
       for (int32_t k = rp[i]; k < rp[i + 1]; ++k) append(col[k], src[k]);
     }
     std::vector<int32_t> win;
-    for (int32_t w0 = 0; w0 < rows; w0 += kSellWindow) {
+    for (int32_t w0 = 0; w0 < rows; w0 += window) {
       win.clear();
-      const int32_t w1 = std::min<int32_t>(rows, w0 + kSellWindow);
+      const int32_t w1 = std::min<int32_t>(rows, w0 + window);
       for (int32_t i = w0; i < w1; ++i)
-        if (len(i) <= kSellMaxLen) win.push_back(i);
+        if (len(i) <= max_len) win.push_back(i);
       std::stable_sort(win.begin(), win.end(), by_len);
       for (size_t c0 = 0; c0 < win.size(); c0 += kSellChunk) {
         const size_t c1 = std::min(win.size(), c0 + kSellChunk);
         int32_t clen = 0;
         for (size_t q = c0; q < c1; ++q) clen = std::max(clen, len(win[q]));
-        const int32_t chunk = int32_t(S.chunk_row.size() / kSellChunk);
         S.wt_ptr.push_back(int32_t(used));
         S.wt_len.push_back(clen);
-        S.wt_row.push_back(-1 - chunk);
+        S.wt_row.push_back(-1);
         for (int l = 0; l < kSellChunk; ++l) S.chunk_row.push_back(c0 + l < c1 ? win[c0 + l] : -1);
         for (int32_t k = 0; k < clen; ++k)
           for (int l = 0; l < kSellChunk; ++l) {
@@ -227,6 +227,7 @@ void build_sell(const std::vector<const int32_t*>& rps, int32_t rows, const int3
 }
 
 bool check_sell(const Sell& S, int32_t rows, int64_t entries, std::string* err) {
+  if (S.chunk_row.size() != S.wt_ptr.size() * kSellChunk) return fail(err, "chunk rows not one block per task");
   int64_t real = 0;
   std::vector<uint8_t> seen;
   for (int x = 0; x < S.slices; ++x) {
@@ -245,9 +246,8 @@ bool check_sell(const Sell& S, int32_t rows, int64_t entries, std::string* err) 
         if (!mark(S.wt_row[t])) return fail(err, "wave row repeated or out of range");
         real += S.wt_len[t];
       } else {
-        const int32_t c = -1 - S.wt_row[t];
         for (int l = 0; l < kSellChunk; ++l) {
-          const int32_t i = S.chunk_row[size_t(c) * kSellChunk + l];
+          const int32_t i = S.chunk_row[size_t(t) * kSellChunk + l];
           if (i >= 0 && !mark(i)) return fail(err, "chunk row repeated or out of range");
           for (int32_t k = 0; k < S.wt_len[t]; ++k)
             if (S.src[size_t(S.wt_ptr[t]) + size_t(k) * kSellChunk + l] >= 0) ++real;

@@ -65,7 +65,7 @@ static std::vector<double> sell_product(const Sell& S, int rows, const std::vect
             const size_t e = size_t(ptr) + size_t(k) * kSellChunk + lane;
             s += vals[e] * vec[S.col[e]];
           }
-          const int r = S.chunk_row[size_t(-1 - row) * kSellChunk + lane];
+          const int r = S.chunk_row[size_t(t) * kSellChunk + lane];
           if (r >= 0) emit(x, r, s);
         }
       }
