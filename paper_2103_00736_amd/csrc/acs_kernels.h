@@ -73,29 +73,27 @@ struct Dev {
   int32_t m, n, n_orth, n_soc;
   int32_t a_rp_nnz;  // nnz
   double mu;
-  // CSR of A (rows i) and of A^T (rows j) with FP64 values of A_s for the
-  // once-per-iteration residual / update / check sweeps (iterative refinement
-  // of the CG); a_orig holds the problem's values
+  // CSR of A (rows i): the problem's values a_orig and FP64 A_s (source of
+  // the SELL values, KKT check, conditioning)
   const int32_t* a_rp;
   const int32_t* a_col;
   const double* a_orig;
-  const int32_t* t_rp;
-  const int32_t* t_col;
-  const int32_t* t_perm;
   double* a_val64;
-  double* t_val64;
-  // SELL layouts of the CG products A_s t (column slices, one per XCD) and
-  // A_s^T r, with their values in VT
+  // SELL layouts of the products with A_s (column slices, one per XCD) and
+  // A_s^T: values in VT for the CG and in FP64 for the once-per-iteration
+  // residual and update sweeps (iterative refinement of the CG); the FP64
+  // arrays alias the VT ones when VT = double
   SellDev sa, st;
   VT* sa_val;
   VT* st_val;
+  double* sa_val64;
+  double* st_val64;
   VT* part;                // kSlices x m partial row sums of A_s t
+  double* part64;          // kSlices x m partial row sums of the FP64 residual
   const int32_t* row_perm; // internal row -> caller's row
   VT* mtmp;                // m-vector scratch of the plain products
   const RowBlock* a_blk;
   int32_t a_nblk;
-  const RowBlock* t_blk;
-  int32_t t_nblk;
   const int32_t* soc_off;  // n_soc + 1 absolute offsets
   const double* b;
   const double* c;

@@ -167,9 +167,9 @@ __device__ __forceinline__ void rows_foreach(const int32_t* __restrict__ rp, Row
 // outstanding load at the join).  Each entry is loaded once.
 
 // exactly N entries
-template <int N, typename VT>
+template <int N, typename VT, typename XT>
 __device__ __forceinline__ void dot_exact(const int32_t* __restrict__ c, const VT* __restrict__ v, int stride,
-                                          const VT* __restrict__ vec, VT& s) {
+                                          const XT* __restrict__ vec, VT& s) {
   int32_t cc[N];
   VT vv[N], g[N];
 #pragma unroll
@@ -178,15 +178,15 @@ __device__ __forceinline__ void dot_exact(const int32_t* __restrict__ c, const V
     vv[u] = v[u * stride];
   }
 #pragma unroll
-  for (int u = 0; u < N; ++u) g[u] = vec[cc[u]];
+  for (int u = 0; u < N; ++u) g[u] = VT(vec[cc[u]]);
 #pragma unroll
   for (int u = 0; u < N; ++u) s += vv[u] * g[u];
 }
 
 // count entries, count uniform across the wave: groups of 8, then the rest
-template <typename VT>
+template <typename VT, typename XT>
 __device__ __forceinline__ VT dot_uniform(const int32_t* __restrict__ c, const VT* __restrict__ v, int count,
-                                          int stride, const VT* __restrict__ vec) {
+                                          int stride, const XT* __restrict__ vec) {
   VT s = 0;
   int e = 0;
   for (; e + 8 <= count; e += 8) dot_exact<8>(c + e * stride, v + e * stride, stride, vec, s);
@@ -209,9 +209,9 @@ __device__ __forceinline__ VT dot_uniform(const int32_t* __restrict__ c, const V
 // lane l takes entries l, l + lanes, ...  Groups of up to 8 per lane, the
 // count of groups uniform across the lanes; a lane past the row's end reads
 // the row's last entry again and drops the product.
-template <typename VT>
+template <typename VT, typename XT>
 __device__ __forceinline__ VT dot_row(const int32_t* __restrict__ c, const VT* __restrict__ v, int len, int lane,
-                                      int lanes, const VT* __restrict__ vec) {
+                                      int lanes, const XT* __restrict__ vec) {
   const int per = (len + lanes - 1) / lanes;  // entries of the busiest lane
   VT s = 0;
   for (int e0 = 0; e0 < per; e0 += 8) {
@@ -227,7 +227,7 @@ __device__ __forceinline__ VT dot_row(const int32_t* __restrict__ c, const VT* _
       vv[u] = v[ec];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) g[u] = vec[cc[u]];
+    for (int u = 0; u < 8; ++u) g[u] = VT(vec[cc[u]]);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const VT prod = vv[u] * g[u];
@@ -243,9 +243,9 @@ __device__ __forceinline__ VT dot_row(const int32_t* __restrict__ c, const VT* _
 // after it.  A long task uses the whole workgroup and a barrier, so lb must
 // be uniform across the workgroup; waves without a task return at once.
 // Entries are summed in storage order, so results are reproducible.
-template <typename VT, class Pre, class Epi>
+template <typename VT, typename XT, class Pre, class Epi>
 __device__ __forceinline__ void sell_rows(const SellDev& S, const VT* __restrict__ val, int x, int lb,
-                                          const VT* __restrict__ vec, Pre& pre, Epi& epi) {
+                                          const XT* __restrict__ vec, Pre& pre, Epi& epi) {
   const int tid = threadIdx.x;
   const int nl = S.long_off[x + 1] - S.long_off[x];
   const int32_t* __restrict__ col = S.col;
@@ -255,7 +255,7 @@ __device__ __forceinline__ void sell_rows(const SellDev& S, const VT* __restrict
     const int beg = S.long_beg[li], end = S.long_end[li];
     const int row = S.long_row[li];
     const VT pv = tid == 0 ? pre(row) : VT(0);
-    VT s = dot_row<VT>(col + beg, val + beg, end - beg, tid, kBlock, vec);
+    VT s = dot_row(col + beg, val + beg, end - beg, tid, kBlock, vec);
     s = wave_sum(s);
     if ((tid & 63) == 0) red[tid >> 6] = s;
     __syncthreads();
@@ -273,14 +273,14 @@ __device__ __forceinline__ void sell_rows(const SellDev& S, const VT* __restrict
   const int r = S.chunk_row[size_t(t) * kSellChunk + lane];  // independent of the loads above
   if (row >= 0) {  // one row per wave, lanes stride the row
     const VT pv = lane == 0 ? pre(row) : VT(0);
-    VT s = dot_row<VT>(col + ptr, val + ptr, len, lane, 64, vec);
+    VT s = dot_row(col + ptr, val + ptr, len, lane, 64, vec);
     s = wave_sum(s);
     if (lane == 0) epi(row, s, pv);
     return;
   }
   // chunk: one row per lane, entries column-major
   const VT pv = r >= 0 ? pre(r) : VT(0);
-  const VT s = dot_uniform<VT>(col + ptr + lane, val + ptr + lane, len, kSellChunk, vec);
+  const VT s = dot_uniform(col + ptr + lane, val + ptr + lane, len, kSellChunk, vec);
   if (r >= 0) epi(r, s, pv);
 }
 
@@ -297,14 +297,10 @@ __device__ __forceinline__ double lorentz_dist2(double u0, double nb) {
 template <typename VT, int MODE, bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restrict__ s_cur, VT* __restrict__ s_new) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const RowBlock rb = d.t_blk[blk];
-  const double* __restrict__ tv = d.t_val64;
-  const int32_t* __restrict__ tc = d.t_col;
-  const double* __restrict__ w = d.w;
-  auto prod = [&](int k) -> double { return tv[k] * w[tc[k]]; };
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   const double mu = d.mu;
-  auto epi = [&](int j, double u) {
+  auto pre = [](int) -> double { return 0.0; };
+  auto epi = [&](int j, double u, double) {
     const double zt = d.chat[j] + u;  // mu * (O z) implied by w
     const double s = double(s_cur[j]);
     const bool orth = j < d.n_orth;
@@ -342,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restri
         d.zt[j] = zt;
     }
   };
-  rows_block<double>(d.t_rp, rb, prod, epi);
+  sell_rows<double, double>(d.st, d.st_val64, 0, blk, d.w, pre, epi);
   if (MODE != UPD_PROLOGUE) block_store_partials<7>(acc, d.partials, blk);
 }
 
@@ -410,21 +406,28 @@ __global__ __launch_bounds__(kBlock) void k_cone(Dev<VT> d, const VT* __restrict
 // CG start: r = A_s v - b_s (rows i of A_s), FP64 accumulation
 // ----------------------------------------------------------------------------
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_resid(Dev<VT> d) {
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const RowBlock rb = d.a_blk[blk];
-  const double* __restrict__ av = d.a_val64;
-  const int32_t* __restrict__ ac = d.a_col;
-  const VT* __restrict__ v = d.v;
-  auto prod = [&](int k) -> double { return av[k] * double(v[ac[k]]); };
+__global__ __launch_bounds__(kBlock) void k_resid_part(Dev<VT> d) {
+  const int x = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
+  if (lb >= d.sa.wg[x]) return;
+  double* __restrict__ part = d.part64 + size_t(x) * d.m;
+  auto pre = [](int) -> double { return 0.0; };
+  auto epi = [&](int i, double sum, double) { part[i] = sum; };
+  sell_rows<double, VT>(d.sa, d.sa_val64, x, lb, d.v, pre, epi);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_resid_comb(Dev<VT> d) {
   double acc[1] = {0};
-  auto epi = [&](int i, double sum) {
+  const int m = d.m;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+    double sum = d.part64[i];
+#pragma unroll
+    for (int x = 1; x < kSlices; ++x) sum += d.part64[size_t(x) * m + i];
     const VT ri = VT(sum - d.bs[i]);
     d.r[i] = ri;
     acc[0] += double(ri) * double(ri);
-  };
-  rows_block<double>(d.a_rp, rb, prod, epi);
-  block_store_partials<1>(acc, d.partials, blk);
+  }
+  block_store_partials<1>(acc, d.partials, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -444,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
     d.t[j] = tj;
     acc[0] += double(tj) * double(tj);
   };
-  sell_rows<VT>(d.st, d.st_val, 0, blk, d.r, pre, epi);
+  sell_rows<VT, VT>(d.st, d.st_val, 0, blk, d.r, pre, epi);
   block_store_partials<1>(acc, d.partials, blk);
 }
 
@@ -477,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
   VT* __restrict__ part = d.part + size_t(x) * d.m;
   auto pre = [](int) -> VT { return VT(0); };
   auto epi = [&](int i, VT sum, VT) { part[i] = sum; };
-  sell_rows<VT>(d.sa, d.sa_val, x, lb, d.t, pre, epi);
+  sell_rows<VT, VT>(d.sa, d.sa_val, x, lb, d.t, pre, epi);
 }
 
 // Mq_i = sum over slices (fixed order); q = r + beta q; w += alpha q; r -= alpha Mq
@@ -503,13 +506,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_comb(Dev<VT> d) {
   block_store_partials<1>(acc, d.partials, blockIdx.x);
 }
 
-// values of a SELL layout from the FP64 A_s (padding entries hold 0)
+// values of a SELL layout from the FP64 A_s (padding entries hold 0), in VT
+// for the CG and in FP64 for the refinement sweeps (one array when VT = double)
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_sell_vals(const int32_t* __restrict__ src, int64_t count,
-                                                      const double* __restrict__ a64, VT* __restrict__ val) {
+                                                      const double* __restrict__ a64, VT* __restrict__ val,
+                                                      double* __restrict__ val64) {
   for (int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x; e < count; e += int64_t(gridDim.x) * kBlock) {
     const int32_t k = src[e];
-    val[e] = k >= 0 ? VT(a64[k]) : VT(0);
+    const double a = k >= 0 ? a64[k] : 0.0;
+    if constexpr (sizeof(VT) == sizeof(double)) {
+      val64[e] = a;
+    } else {
+      val[e] = VT(a);
+      val64[e] = a;
+    }
   }
 }
 
@@ -707,21 +718,6 @@ __global__ __launch_bounds__(kBlock) void k_scale_a(Dev<VT> d) {
 }
 
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_scale_t(Dev<VT> d) {
-  __shared__ int32_t rowof[kStageNnz];
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const RowBlock rb = d.t_blk[blk];
-  const int k0 = d.t_rp[rb.r0], k1 = d.t_rp[rb.r1];
-  const bool one = (k1 - k0 > kStageNnz);
-  if (!one) stage_rows(d.t_rp, rb, k0, rowof);
-  for (int k = k0 + threadIdx.x; k < k1; k += kBlock) {
-    const int j = one ? rb.r0 : rowof[k - k0];
-    const double a = d.a_orig[d.t_perm[k]] * d.O[j] * d.dinv[d.t_col[k]];
-    d.t_val64[k] = a;
-  }
-}
-
-template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_chat(Dev<VT> d) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j < d.n) d.chat[j] = d.mu * d.O[j] * d.c[j];
@@ -735,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_t(Dev<VT> d, const VT* __restri
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   auto pre = [](int) -> VT { return VT(0); };
   auto epi = [&](int j, VT s, VT) { y[j] = s; };
-  sell_rows<VT>(d.st, d.st_val, 0, blk, x, pre, epi);
+  sell_rows<VT, VT>(d.st, d.st_val, 0, blk, x, pre, epi);
 }
 
 template <typename VT>
@@ -745,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_a(Dev<VT> d, const VT* __restri
   VT* __restrict__ part = d.part + size_t(xs) * d.m;
   auto pre = [](int) -> VT { return VT(0); };
   auto epi = [&](int i, VT s, VT) { part[i] = s; };
-  sell_rows<VT>(d.sa, d.sa_val, xs, lb, x, pre, epi);
+  sell_rows<VT, VT>(d.sa, d.sa_val, xs, lb, x, pre, epi);
 }
 
 // y[row_perm[i]] = sum of the slice partials of row i (same order as the CG)
@@ -928,7 +924,7 @@ static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 template <typename VT>
 void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool check, hipStream_t st) {
-  const dim3 g(d.t_nblk), b(kBlock);
+  const dim3 g(d.st.wg[0]), b(kBlock);
   if (mode == UPD_PROLOGUE) {
     hipLaunchKernelGGL((k_update<VT, UPD_PROLOGUE, false>), g, b, 0, st, d, s_cur, s_new);
     return;
@@ -944,7 +940,7 @@ void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool 
     else
       hipLaunchKernelGGL((k_update<VT, UPD_UPDATE_ONLY, false>), g, b, 0, st, d, s_cur, s_new);
   }
-  hipLaunchKernelGGL((k_fin_upd<VT>), dim3(1), b, 0, st, d, d.t_nblk);
+  hipLaunchKernelGGL((k_fin_upd<VT>), dim3(1), b, 0, st, d, d.st.wg[0]);
 }
 
 template <typename VT>
@@ -956,14 +952,17 @@ void launch_cone(const Dev<VT>& d, const VT* s, bool check, bool next, int group
   if (check) hipLaunchKernelGGL((k_fin_cone<VT>), dim3(1), dim3(kBlock), 0, st, d, nb);
 }
 
+static inline int comb_blocks(int m) { return std::min(ceil_div(m, kBlock), 2048); }
+
 template <typename VT>
 void launch_resid(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_resid<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL((k_resid_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL((k_resid_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st) {
-  hipLaunchKernelGGL((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, iter, red2, abs2);
+  hipLaunchKernelGGL((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), iter, red2, abs2);
 }
 
 template <typename VT>
@@ -975,8 +974,6 @@ template <typename VT>
 void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st) {
   hipLaunchKernelGGL((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.st.wg[0]);
 }
-
-static inline int comb_blocks(int m) { return std::min(ceil_div(m, kBlock), 2048); }
 
 template <typename VT>
 void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
@@ -1018,11 +1015,11 @@ template <typename VT>
 void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
   hipLaunchKernelGGL((k_rowsum<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, wmode);
   hipLaunchKernelGGL((k_scale_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL((k_scale_t<VT>), dim3(d.t_nblk), dim3(kBlock), 0, st, d);
   for (const auto* S : {&d.sa, &d.st}) {
     const int nb = int(std::max<int64_t>(1, std::min<int64_t>((S->entries + kBlock - 1) / kBlock, 8192)));
+    const bool a = S == &d.sa;
     hipLaunchKernelGGL((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, S->src, S->entries, d.a_val64,
-                       S == &d.sa ? d.sa_val : d.st_val);
+                       a ? d.sa_val : d.st_val, a ? d.sa_val64 : d.st_val64);
   }
   hipLaunchKernelGGL((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
 }

@@ -225,12 +225,12 @@ static int64_t estimate_bytes(const Problem& p, int precision) {
   const SellPair& sp = p.sell();
   int64_t b = 0;
   b += 4 * (m + 1) + 4 * nnz + 8 * nnz + 8 * nnz;        // A pattern, original and FP64 scaled values
-  b += 4 * (n + 1) + 4 * nnz + 8 * nnz + 4 * nnz;        // A^T pattern, FP64 values, perm
+  const int64_t v64 = vt == 8 ? 0 : 8;                   // FP64 SELL values beside the VT ones
   for (const Sell* S : {&sp.a, &sp.t})                   // SELL layouts: entries, tasks, chunk rows
-    b += (8 + vt) * int64_t(S->col.size()) + 12 * int64_t(S->wt_ptr.size() + S->long_row.size()) +
+    b += (8 + vt + v64) * int64_t(S->col.size()) + 12 * int64_t(S->wt_ptr.size() + S->long_row.size()) +
          4 * int64_t(S->chunk_row.size());
-  b += vt * kSlices * m + (4 + vt) * m;                  // slice partials, row permutation, scratch
-  b += 8 * int64_t(p.a_blocks.size() + p.t_blocks.size());
+  b += (vt + 8) * kSlices * m + (4 + vt) * m;            // slice partials, row permutation, scratch
+  b += 8 * int64_t(p.a_blocks.size());
   b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
   const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max),
                                          size_t(n / kBlock + 2)});
@@ -314,11 +314,7 @@ class Instance final : public InstanceBase {
     int32_t* a_rp = arena_.alloc<int32_t>(p.m + 1);
     int32_t* a_col = arena_.alloc<int32_t>(p.nnz);
     double* a_orig = arena_.alloc<double>(p.nnz);
-    int32_t* t_rp = arena_.alloc<int32_t>(p.n + 1);
-    int32_t* t_col = arena_.alloc<int32_t>(p.nnz);
-    int32_t* t_perm = arena_.alloc<int32_t>(p.nnz);
     RowBlock* a_blk = arena_.alloc<RowBlock>(p.a_blocks.size());
-    RowBlock* t_blk = arena_.alloc<RowBlock>(p.t_blocks.size());
     int32_t* soc_off = arena_.alloc<int32_t>(p.soc_off.size());
     double* b = arena_.alloc<double>(p.m);
     double* c = arena_.alloc<double>(p.n);
@@ -326,23 +322,15 @@ class Instance final : public InstanceBase {
     if (p.nnz) {
       up(a_col, p.col);
       up(a_orig, p.val);
-      up(t_col, p.t_col);
-      up(t_perm, p.t_perm);
     }
-    up(t_rp, p.t_row_ptr);
     up(a_blk, p.a_blocks);
-    up(t_blk, p.t_blocks);
     up(soc_off, p.soc_off);
     up(b, p.b);
     up(c, p.c);
     d.a_rp = a_rp;
     d.a_col = a_col;
     d.a_orig = a_orig;
-    d.t_rp = t_rp;
-    d.t_col = t_col;
-    d.t_perm = t_perm;
     d.a_val64 = arena_.alloc<double>(p.nnz);
-    d.t_val64 = arena_.alloc<double>(p.nnz);
     d.a_blk = a_blk;
     d.a_nblk = int(p.a_blocks.size());
     d.a_rp_nnz = int32_t(p.nnz);
@@ -377,14 +365,20 @@ class Instance final : public InstanceBase {
       sell_dev(sp.t, &d.st);
       d.sa_val = arena_.alloc<VT>(std::max<size_t>(sp.a.col.size(), 1));
       d.st_val = arena_.alloc<VT>(std::max<size_t>(sp.t.col.size(), 1));
+      if (sizeof(VT) == sizeof(double)) {
+        d.sa_val64 = reinterpret_cast<double*>(d.sa_val);
+        d.st_val64 = reinterpret_cast<double*>(d.st_val);
+      } else {
+        d.sa_val64 = arena_.alloc<double>(std::max<size_t>(sp.a.col.size(), 1));
+        d.st_val64 = arena_.alloc<double>(std::max<size_t>(sp.t.col.size(), 1));
+      }
       d.part = arena_.alloc<VT>(size_t(kSlices) * p.m);
+      d.part64 = arena_.alloc<double>(size_t(kSlices) * p.m);
       int32_t* rperm = arena_.alloc<int32_t>(p.m);
       up(rperm, p.row_perm);
       d.row_perm = rperm;
       d.mtmp = arena_.alloc<VT>(p.m);
     }
-    d.t_blk = t_blk;
-    d.t_nblk = int(p.t_blocks.size());
     d.soc_off = soc_off;
     d.b = b;
     d.c = c;
@@ -409,7 +403,7 @@ class Instance final : public InstanceBase {
     d.ounit = arena_.alloc<double>(size_t(p.n_orth) + p.soc_size.size());
     d.ctl = arena_.alloc<Ctl>(1);
     const size_t units = size_t(p.n_orth) + p.soc_size.size();
-    nparts_ = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(d.st.wg_max), units / kBlock + 1,
+    nparts_ = std::max<size_t>({p.a_blocks.size(), size_t(d.st.wg_max), units / kBlock + 1,
                                  p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, 1});
     d.partials = arena_.alloc<double>(nparts_ * 8);
     s_buf_[0] = arena_.alloc<VT>(p.n);

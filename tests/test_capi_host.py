@@ -46,7 +46,9 @@ def _lp():
 def test_valid_problem_and_device_bytes():
     p = acs.Problem.from_synth(_lp())
     assert p.device_bytes(acs.PREC_MIXED) > 0
-    assert p.device_bytes(acs.PREC_FP64) > p.device_bytes(acs.PREC_MIXED)
+    # mixed mode keeps FP32 and FP64 copies of the matrix values, FP64 mode one FP64 copy:
+    # the two estimates differ but neither dominates for every shape
+    assert p.device_bytes(acs.PREC_FP64) > 0 and p.device_bytes(acs.PREC_FP64) != p.device_bytes(acs.PREC_MIXED)
     p.close()
 
 
@@ -97,6 +99,6 @@ def test_device_byte_estimates_are_host_code():
     p = synth.config3(3, m=300)
     h = acs.Problem.from_synth(p)
     one, fp64, pool = h.device_bytes(), h.device_bytes(acs.PREC_FP64), h.batch_device_bytes()
-    # at least the matrix in CSR (index + FP32 value) and both transposes' indices
-    assert one >= 12 * p.nnz and fp64 > one and pool >= 8 * p.nnz
+    # at least the matrix's indices and values in the SELL layouts of both products
+    assert one >= 24 * p.nnz and fp64 >= 16 * p.nnz and pool >= 8 * p.nnz
     h.close()
