@@ -183,11 +183,16 @@ int acs_state_check(acs_state* st, acs_info* info);
  */
 int acs_state_spmv(acs_state* st, int32_t which, const void* x, void* y, int32_t reps, double* avg_ms);
 /* Per-kernel-class event timing over subsequent acs_state_step calls.
- * enable = 1 starts, 0 stops; acs_state_timing reads {count, total_ms} for
- * class k (0 = update sweep k_update, 1 = residual sweep k_resid, 2 = CG
- * sweep k_cg_t, 3 = CG sliced sweep k_cg_a_part, 4 = cone k_cone, 5 = check
- * k_pres, 6 = conditioning, 7 = one-workgroup finalizers, 8 = CG combine
- * k_cg_a_comb). */
+ * `enable` is a bit mask of the classes to time (bit k = class k; 0 stops;
+ * ACS_PROF_ALL times every class); each timed launch is bracketed by HIP
+ * events on the state's stream, which costs a few microseconds per launch, so
+ * timing only the class of interest keeps the overhead small.  A nonzero mask
+ * resets the counts.  acs_state_timing reads {count, total_ms} for class k
+ * (0 = update sweep k_update, 1 = residual sweep k_resid_part +
+ * k_resid_comb, 2 = CG sweep k_cg_t, 3 = CG sliced sweep k_cg_a_part, 4 =
+ * cone k_cone, 5 = check k_pres, 6 = conditioning, 7 = one-workgroup
+ * finalizers, 8 = CG combine k_cg_a_comb). */
+#define ACS_PROF_ALL 0x1ff
 int acs_state_profile(acs_state* st, int32_t enable);
 int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_ms);
 

@@ -27,6 +27,7 @@ PREC_MIXED, PREC_FP64 = 0, 1
 
 # timing classes of acs_state_timing
 KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG_COMB = range(9)
+PROF_ALL = (1 << 9) - 1  # ACS_PROF_ALL
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
@@ -268,8 +269,18 @@ class State:
         _check(lib().acs_state_spmv(self.handle, int(which), P(x_ptr), P(y_ptr), int(reps), ctypes.byref(ms)))
         return ms.value
 
-    def profile(self, enable: bool):
-        _check(lib().acs_state_profile(self.handle, 1 if enable else 0))
+    def profile(self, classes=True):
+        """Time kernel classes with HIP events: True = every class, False = stop,
+        or an iterable of KC_* classes."""
+        if classes is True:
+            mask = PROF_ALL
+        elif classes is False or classes is None:
+            mask = 0
+        else:
+            mask = 0
+            for k in classes:
+                mask |= 1 << int(k)
+        _check(lib().acs_state_profile(self.handle, mask))
 
     def timing(self, cls: int) -> Tuple[int, float]:
         cnt = ctypes.c_int64()

@@ -43,9 +43,20 @@ __device__ __forceinline__ T wave_min(T v) {
   return v;
 }
 
+// Progress records in pinned host memory.  host_store releases at system
+// scope: every earlier write of the kernel is visible to the host first, which
+// costs a write-back of the L2 before the next kernel starts; it is used only
+// where the host then reads other results (the KKT check).  host_post is a
+// relaxed system-scope store for the CG progress records, which the host uses
+// only to decide what to launch next.
 template <typename T>
 __device__ __forceinline__ void host_store(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <typename T>
+__device__ __forceinline__ void host_post(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Per-block partial sums (N values) -> partials[blk * N + i].
@@ -470,8 +481,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
       } else {
         c->alpha = 0.0;
         c->done = 1;
-        if (!(tt[0] == tt[0])) host_store(&d.hs->numeric, 1);
-        host_store(&d.hs->cg_done_iter, c->iter);
+        if (!(tt[0] == tt[0])) host_post(&d.hs->numeric, 1);
+        host_post(&d.hs->cg_done_iter, c->iter);
       }
     }
   }
@@ -820,8 +831,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_resid(Dev<VT> d, int nb, int ite
     const bool bad = !(rho == rho) || isinf(rho);
     const int done = (bad || rho <= c->tol2 || c->cg_max <= 0) ? 1 : 0;
     c->done = done;
-    if (bad) host_store(&d.hs->numeric, 1);
-    if (done) host_store(&d.hs->cg_done_iter, iter);
+    if (bad) host_post(&d.hs->numeric, 1);
+    if (done) host_post(&d.hs->cg_done_iter, iter);
   }
 }
 
@@ -839,8 +850,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_t(Dev<VT> d, int nb) {
     } else {
       c->alpha = 0.0;
       c->done = 1;
-      if (!(tt == tt)) host_store(&d.hs->numeric, 1);
-      host_store(&d.hs->cg_done_iter, c->iter);
+      if (!(tt == tt)) host_post(&d.hs->numeric, 1);
+      host_post(&d.hs->cg_done_iter, c->iter);
     }
   }
 }
@@ -861,11 +872,11 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_a(Dev<VT> d, int nb, long lon
       c->cg_total += 1;
       const int done = (bad || rn <= c->tol2 || c->k >= c->cg_max) ? 1 : 0;
       c->done = done;
-      if (bad) host_store(&d.hs->numeric, 1);
-      if (done) host_store(&d.hs->cg_done_iter, c->iter);
+      if (bad) host_post(&d.hs->numeric, 1);
+      if (done) host_post(&d.hs->cg_done_iter, c->iter);
     }
   }
-  if (threadIdx.x == 0) host_store(&d.hs->launch_seq, launch_id);
+  if (threadIdx.x == 0) host_post(&d.hs->launch_seq, launch_id);
 }
 
 // KKT relative errors of the check iteration

@@ -249,7 +249,7 @@ class InstanceBase {
   virtual void get(int* l, double* s_prev, double* s, double* O, double* w, double* x, double* y, double* z) = 0;
   virtual void spmv(int which, const void* x, void* y, int reps, double* avg_ms) = 0;
   virtual void check_now() = 0;
-  virtual void profile(bool on) = 0;
+  virtual void profile(uint32_t mask) = 0;
   virtual void timing(int cls, int64_t* count, double* total_ms) = 0;
   virtual int current_l() const = 0;
   acs_info info{};
@@ -472,6 +472,11 @@ class Instance final : public InstanceBase {
       for (int e = p.soc_off[i] + 1; e < p.soc_off[i + 1]; ++e)
         if (O[e] != O[p.soc_off[i]]) throw AcsError(ACS_ERR_ARG, "O must be constant on every cone");
     HIP_CHECK(hipStreamSynchronize(st_));
+    // progress records compare against iteration numbers: start them afresh,
+    // since l may be earlier than the iterations already run
+    __atomic_store_n(&hs_->cg_done_iter, -1, __ATOMIC_RELEASE);
+    __atomic_store_n(&hs_->check_iter, -1, __ATOMIC_RELEASE);
+    checked_iter_ = -1;
     cur_ = 0;
     upload_vt(s_buf_[0], s, p.n);
     upload_vt(s_buf_[1], s_prev, p.n);
@@ -526,7 +531,7 @@ class Instance final : public InstanceBase {
   };
   template <class F>
   void timed(int cls, F&& f) {
-    if (!profiling_) {
+    if (!(prof_mask_ >> cls & 1u)) {
       f();
       check_launch();
       return;
@@ -558,15 +563,15 @@ class Instance final : public InstanceBase {
     }
     prof_pending_.clear();
   }
-  void profile(bool on) override {
+  void profile(uint32_t mask) override {
     collect_profile();
-    if (on) {
+    if (mask) {
       for (int i = 0; i < KC_N; ++i) {
         prof_count_[i] = 0;
         prof_ms_[i] = 0;
       }
     }
-    profiling_ = on;
+    prof_mask_ = mask & ((1u << KC_N) - 1);
   }
   void timing(int cls, int64_t* count, double* total_ms) override {
     if (cls < 0 || cls >= KC_N) throw AcsError(ACS_ERR_ARG, "timing class out of range");
@@ -781,7 +786,7 @@ class Instance final : public InstanceBase {
   int cone_group_ = 4;
   size_t nparts_ = 1;
   HostStatus* hs_ = nullptr;
-  bool profiling_ = false;
+  uint32_t prof_mask_ = 0;  // kernel classes timed with events
   std::vector<ProfEv> prof_pending_, prof_free_;
   int64_t prof_count_[KC_N] = {0};
   double prof_ms_[KC_N] = {0};
@@ -969,7 +974,7 @@ int acs_state_spmv(acs_state* st, int32_t which, const void* x, void* y, int32_t
 int acs_state_profile(acs_state* st, int32_t enable) {
   return guarded([&] {
     if (!st) throw AcsError(ACS_ERR_ARG, "null state");
-    st->inst->profile(enable != 0);
+    st->inst->profile(uint32_t(enable));
   });
 }
 
