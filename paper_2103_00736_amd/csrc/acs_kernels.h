@@ -14,11 +14,25 @@
 // which equals the listing's r = abs_{A_hat}(p), s+ = s/2 - r/2 + d.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "acs_internal.h"
 
 namespace acs {
+
+// Timing of kernel launches.  While a LaunchEvents slot is installed on the
+// calling thread, the launchers start the first kernel with `start` and every
+// kernel with `stop` through hipExtLaunchKernelGGL, which takes both
+// timestamps from the kernel dispatch itself (as a profiler does), so
+// stop - start spans exactly the kernels launched, without separate event
+// records on the stream.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  int launches = 0;
+};
+LaunchEvents*& launch_events();  // thread-local slot, nullptr when not timing
 
 // Device control block of one instance (CG scalars, reductions, flags).
 struct Ctl {

@@ -18,6 +18,24 @@
 
 namespace acs {
 
+LaunchEvents*& launch_events() {
+  static thread_local LaunchEvents* slot = nullptr;
+  return slot;
+}
+
+// hipLaunchKernelGGL, or the timed launch while a LaunchEvents slot is set
+#define ACS_LAUNCH(kernel, grid, block, shmem, stream, ...)                                          \
+  do {                                                                                                \
+    LaunchEvents* ev_ = launch_events();                                                              \
+    if (ev_) {                                                                                        \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_->launches == 0 ? ev_->start : nullptr, \
+                            ev_->stop, 0u, __VA_ARGS__);                                               \
+      ++ev_->launches;                                                                                \
+    } else {                                                                                          \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                            \
+    }                                                                                                 \
+  } while (0)
+
 // ----------------------------------------------------------------------------
 // helpers
 // ----------------------------------------------------------------------------
@@ -937,21 +955,21 @@ template <typename VT>
 void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool check, hipStream_t st) {
   const dim3 g(d.st.wg[0]), b(kBlock);
   if (mode == UPD_PROLOGUE) {
-    hipLaunchKernelGGL((k_update<VT, UPD_PROLOGUE, false>), g, b, 0, st, d, s_cur, s_new);
+    ACS_LAUNCH((k_update<VT, UPD_PROLOGUE, false>), g, b, 0, st, d, s_cur, s_new);
     return;
   }
   if (mode == UPD_UPDATE) {
     if (check)
-      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE, true>), g, b, 0, st, d, s_cur, s_new);
+      ACS_LAUNCH((k_update<VT, UPD_UPDATE, true>), g, b, 0, st, d, s_cur, s_new);
     else
-      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE, false>), g, b, 0, st, d, s_cur, s_new);
+      ACS_LAUNCH((k_update<VT, UPD_UPDATE, false>), g, b, 0, st, d, s_cur, s_new);
   } else {
     if (check)
-      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE_ONLY, true>), g, b, 0, st, d, s_cur, s_new);
+      ACS_LAUNCH((k_update<VT, UPD_UPDATE_ONLY, true>), g, b, 0, st, d, s_cur, s_new);
     else
-      hipLaunchKernelGGL((k_update<VT, UPD_UPDATE_ONLY, false>), g, b, 0, st, d, s_cur, s_new);
+      ACS_LAUNCH((k_update<VT, UPD_UPDATE_ONLY, false>), g, b, 0, st, d, s_cur, s_new);
   }
-  hipLaunchKernelGGL((k_fin_upd<VT>), dim3(1), b, 0, st, d, d.st.wg[0]);
+  ACS_LAUNCH((k_fin_upd<VT>), dim3(1), b, 0, st, d, d.st.wg[0]);
 }
 
 template <typename VT>
@@ -959,52 +977,52 @@ void launch_cone(const Dev<VT>& d, const VT* s, bool check, bool next, int group
   if (d.n_soc == 0) return;
   const int gpb = kBlock / group;
   const int nb = ceil_div(d.n_soc, gpb);
-  hipLaunchKernelGGL((k_cone<VT>), dim3(nb), dim3(kBlock), 0, st, d, s, int(check), int(next), group);
-  if (check) hipLaunchKernelGGL((k_fin_cone<VT>), dim3(1), dim3(kBlock), 0, st, d, nb);
+  ACS_LAUNCH((k_cone<VT>), dim3(nb), dim3(kBlock), 0, st, d, s, int(check), int(next), group);
+  if (check) ACS_LAUNCH((k_fin_cone<VT>), dim3(1), dim3(kBlock), 0, st, d, nb);
 }
 
 static inline int comb_blocks(int m) { return std::min(ceil_div(m, kBlock), 2048); }
 
 template <typename VT>
 void launch_resid(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_resid_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL((k_resid_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_resid_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_resid_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st) {
-  hipLaunchKernelGGL((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), iter, red2, abs2);
+  ACS_LAUNCH((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), iter, red2, abs2);
 }
 
 template <typename VT>
 void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_cg_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.st.wg[0]);
+  ACS_LAUNCH((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.st.wg[0]);
 }
 
 template <typename VT>
 void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_a_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
+  ACS_LAUNCH((k_cg_a_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
 }
 
 template <typename VT>
 void launch_cg_comb(const Dev<VT>& d, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_a_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_cg_a_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
-  hipLaunchKernelGGL((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), launch_id);
+  ACS_LAUNCH((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), launch_id);
 }
 
 template <typename VT>
 void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st) {
-  hipLaunchKernelGGL((k_pres<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL((k_fin_pres<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, iter, bnorm, cnorm,
+  ACS_LAUNCH((k_pres<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_fin_pres<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, iter, bnorm, cnorm,
                      int(d.n_soc > 0));
 }
 
@@ -1012,43 +1030,43 @@ template <typename VT>
 void launch_cond_ratio(const Dev<VT>& d, const VT* s_prev, const VT* s_cur, double t_cap, hipStream_t st) {
   const int units = d.n_orth + d.n_soc;
   const int nb = ceil_div(units, kBlock);
-  hipLaunchKernelGGL((k_cond_ratio<VT>), dim3(nb), dim3(kBlock), 0, st, d, s_prev, s_cur);
-  hipLaunchKernelGGL((k_fin_cond<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, t_cap);
+  ACS_LAUNCH((k_cond_ratio<VT>), dim3(nb), dim3(kBlock), 0, st, d, s_prev, s_cur);
+  ACS_LAUNCH((k_fin_cond<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, t_cap);
 }
 
 template <typename VT>
 void launch_cond_scale(const Dev<VT>& d, VT* s_cur, hipStream_t st) {
   const int units = d.n_orth + d.n_soc;
-  hipLaunchKernelGGL((k_cond_scale<VT>), dim3(ceil_div(units, kBlock)), dim3(kBlock), 0, st, d, s_cur);
+  ACS_LAUNCH((k_cond_scale<VT>), dim3(ceil_div(units, kBlock)), dim3(kBlock), 0, st, d, s_cur);
 }
 
 template <typename VT>
 void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
-  hipLaunchKernelGGL((k_rowsum<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, wmode);
-  hipLaunchKernelGGL((k_scale_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_rowsum<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, wmode);
+  ACS_LAUNCH((k_scale_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
   for (const auto* S : {&d.sa, &d.st}) {
     const int nb = int(std::max<int64_t>(1, std::min<int64_t>((S->entries + kBlock - 1) / kBlock, 8192)));
     const bool a = S == &d.sa;
-    hipLaunchKernelGGL((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, S->src, S->entries, d.a_val64,
+    ACS_LAUNCH((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, S->src, S->entries, d.a_val64,
                        a ? d.sa_val : d.st_val, a ? d.sa_val64 : d.st_val64);
   }
-  hipLaunchKernelGGL((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st) {
   if (which == 0) {
-    hipLaunchKernelGGL((k_spmv_a<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, x);
-    hipLaunchKernelGGL((k_spmv_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d, y);
+    ACS_LAUNCH((k_spmv_a<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, x);
+    ACS_LAUNCH((k_spmv_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d, y);
   } else {
-    hipLaunchKernelGGL((k_perm_in<VT>), dim3(ceil_div(d.m, kBlock)), dim3(kBlock), 0, st, d, x);
-    hipLaunchKernelGGL((k_spmv_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d, d.mtmp, y);
+    ACS_LAUNCH((k_perm_in<VT>), dim3(ceil_div(d.m, kBlock)), dim3(kBlock), 0, st, d, x);
+    ACS_LAUNCH((k_spmv_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d, d.mtmp, y);
   }
 }
 
 template <typename VT>
 void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
-  hipLaunchKernelGGL((k_ctl_reset<VT>), dim3(1), dim3(64), 0, st, d, cg_max);
+  ACS_LAUNCH((k_ctl_reset<VT>), dim3(1), dim3(64), 0, st, d, cg_max);
 }
 
 #define ACS_INSTANTIATE(VT)                                                                            \

@@ -545,10 +545,20 @@ class Instance final : public InstanceBase {
       prof_free_.pop_back();
       e.cls = cls;
     }
-    HIP_CHECK(hipEventRecord(e.a, st_));
-    f();
+    LaunchEvents le{e.a, e.b, 0};
+    struct Slot {
+      explicit Slot(LaunchEvents* p) { launch_events() = p; }
+      ~Slot() { launch_events() = nullptr; }
+    };
+    {
+      Slot slot(&le);
+      f();
+    }
     check_launch();
-    HIP_CHECK(hipEventRecord(e.b, st_));
+    if (le.launches == 0) {  // nothing launched (e.g. no cones): not counted
+      prof_free_.push_back(e);
+      return;
+    }
     prof_pending_.push_back(e);
   }
   void collect_profile() {
