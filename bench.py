@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy"], default="lp2m",
+    ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy", "gather"], default="lp2m",
                     help="lp2m: iterations/s on the 2M-variable LP (default); batch: 4096 small LPs in one "
                          "persistent launch; serve: Poisson request stream through the serving loop")
     ap.add_argument("--count", type=int, default=4096, help="batch: number of instances")
@@ -150,6 +150,8 @@ def main():
         return bench_serve(args)
     if args.workload == "copy":
         return bench_copy()
+    if args.workload == "gather":
+        return bench_gather()
 
     from paper_2103_00736_amd import acs, synth
 
@@ -255,6 +257,51 @@ def bench_copy():
     ms = e0.elapsed_time(e1) / 10
     print(json.dumps({"metric": "copy GB/s (read+write)", "value": 2 * (1 << 30) / ms / 1e6, "unit": "GB/s",
                       "bytes_each_way": 1 << 30, "ms": ms}), flush=True)
+    return 0
+
+
+def bench_gather():
+    """Gather ceiling of the CG's product kernels: the library's own SELL
+    products (acs_state_spmv, FP32) on matrices with 5 random rows per column,
+    so that every nonzero costs one random 4-byte read of the gathered vector,
+    compared with the 2M-variable LP itself.  A^T x gathers from the m-vector
+    (2 MB for m = 500k, 32 KB for m = 8192: resident in L1); A x gathers from
+    the n-vector, 1 MB per XCD through the column slices."""
+    import torch
+    from paper_2103_00736_amd import acs, synth
+
+    rc = acs.lib().acs_init(0)
+    if rc != 0:
+        raise RuntimeError(acs.lib().acs_last_error().decode())
+    cases = [("uniform rows, m=500k (2 MB gathered by A^T x)", lambda: synth.lp_percol(500_000, 2_000_000, 5, 11)),
+             ("uniform rows, m=8192 (32 KB gathered by A^T x)", lambda: synth.lp_percol(8192, 2_000_000, 5, 12)),
+             ("2M-variable LP, power-law rows", lambda: synth.config1())]
+    out = {}
+    dev = torch.device("cuda:0")
+    for name, make in cases:
+        _progress(f"gather case: {name}")
+        p = make()
+        st = acs.State(acs.Problem.from_synth(p))
+        st.step(1)  # scaled values in place
+        xn = torch.ones(p.n, dtype=torch.float32, device=dev)
+        xm = torch.ones(p.m, dtype=torch.float32, device=dev)
+        ym = torch.empty(p.m, dtype=torch.float32, device=dev)
+        yn = torch.empty(p.n, dtype=torch.float32, device=dev)
+        st.spmv(1, xm.data_ptr(), yn.data_ptr(), 5)
+        st.spmv(0, xn.data_ptr(), ym.data_ptr(), 5)
+        t_ms = st.spmv(1, xm.data_ptr(), yn.data_ptr(), 50)
+        a_ms = st.spmv(0, xn.data_ptr(), ym.data_ptr(), 50)
+        st.close()
+        out[name] = {"m": p.m, "n": p.n, "nnz": int(p.nnz),
+                     "At_x_us": t_ms * 1e3, "At_x_Ggather_per_s": p.nnz / (t_ms * 1e-3) / 1e9,
+                     "A_x_us": a_ms * 1e3, "A_x_Ggather_per_s": p.nnz / (a_ms * 1e-3) / 1e9}
+    first = next(iter(out.values()))
+    print(json.dumps({"metric": "gather rate of the CG product kernels (A^T x, uniform rows, 2 MB vector)",
+                      "value": first["At_x_Ggather_per_s"], "unit": "Ggather/s", "higher_is_better": True,
+                      "data": "synthetic", "dtype": "f32",
+                      "what": "acs_state_spmv with 50 back-to-back launches timed by HIP events; A x includes "
+                              "the slice-combine kernel, A^T x the row-order permutation of its input",
+                      "cases": out}), flush=True)
     return 0
 
 
