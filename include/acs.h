@@ -130,12 +130,26 @@ void acs_settings_default(acs_settings* s);
 int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                        const double* val, const double* b, const double* c, int32_t n_orth, int32_t n_soc,
                        const int32_t* soc_sizes, acs_problem** out);
+/*
+ * Dense problem (Sec. V: the paper's random LP and SOCP instances have dense
+ * A with U[-1,1] entries).  a is row-major m x n (HOST, copied; the caller
+ * may free it on return); b, c and the cone list as for acs_problem_create.
+ * The products stream A in FP32 (plus the FP32 rounding error of each value
+ * when some value is not an FP32 number, for the FP64 sweeps); the scalings
+ * D and O of Alg. 2 step 12 are applied to vectors, so A is never rewritten.
+ * Validation: m, n >= 1, finite values, m * round_up(n, 64) < 2^31.  Solved
+ * by acs_solve and acs_state_*; the batch and the server pool take sparse
+ * problems (a server runs dense requests on its worker streams).  Host code.
+ */
+int acs_problem_create_dense(int32_t m, int32_t n, const double* a, const double* b, const double* c, int32_t n_orth,
+                             int32_t n_soc, const int32_t* soc_sizes, acs_problem** out);
 void acs_problem_destroy(acs_problem* p);
 /* Device bytes a one-instance solve of `p` in `precision` allocates (for
  * budgeting; includes the SELL layouts of the CG products).  Host code. */
 int64_t acs_problem_device_bytes(const acs_problem* p, int32_t precision);
 /* Device bytes `p` takes as one instance of a batch arena or a server pool
- * slot (the persistent kernel's layout).  Host code. */
+ * slot (the persistent kernel's layout); -1 for a dense problem, which the
+ * batch does not take.  Host code. */
 int64_t acs_batch_device_bytes(const acs_problem* p);
 
 /*

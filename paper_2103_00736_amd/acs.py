@@ -31,7 +31,7 @@ PROF_ALL = (1 << 9) - 1  # ACS_PROF_ALL
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
-    "acs_problem_destroy", "acs_problem_device_bytes", "acs_batch_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
+    "acs_problem_destroy", "acs_problem_create_dense", "acs_problem_device_bytes", "acs_batch_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
     "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
     "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_batch_create", "acs_batch_destroy",
     "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_lanes", "acs_batch_solve",
@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
         "acs_problem_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, I64P, I32P, DP, DP, DP,
                                               ctypes.c_int32, ctypes.c_int32, I32P, ctypes.POINTER(P)]),
         "acs_problem_destroy": (None, [P]),
+        "acs_problem_create_dense": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, DP, DP, DP, ctypes.c_int32,
+                                                    ctypes.c_int32, I32P, ctypes.POINTER(P)]),
         "acs_problem_device_bytes": (ctypes.c_int64, [P, ctypes.c_int32]),
         "acs_batch_device_bytes": (ctypes.c_int64, [P]),
         "acs_solve": (ctypes.c_int, [P, ctypes.POINTER(Settings), DP, DP, DP, ctypes.POINTER(Info), P]),
@@ -202,7 +204,32 @@ class Problem:
 
     @classmethod
     def from_synth(cls, p) -> "Problem":
+        if hasattr(p, "A"):
+            return cls.from_dense(p.A, p.b, p.c, p.n_orth, p.soc_sizes)
         return cls(p.m, p.n, p.row_ptr, p.col_idx, p.val, p.b, p.c, p.n_orth, p.soc_sizes)
+
+    @classmethod
+    def from_dense(cls, A, b, c, n_orth, soc_sizes=()) -> "Problem":
+        """Dense A (m x n, row-major) through acs_problem_create_dense."""
+        self = cls.__new__(cls)
+        a = np.ascontiguousarray(A, dtype=np.float64)
+        if a.ndim != 2:
+            raise AcsError(ACS_ERR_ARG, "A must be a 2-D array")
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        cc = np.ascontiguousarray(c, dtype=np.float64)
+        ss = np.ascontiguousarray(soc_sizes, dtype=np.int32)
+        self.m, self.n = int(a.shape[0]), int(a.shape[1])
+        if len(bb) != self.m or len(cc) != self.n:
+            raise AcsError(ACS_ERR_ARG, "b must have m entries and c n entries")
+        self.n_orth = int(n_orth)
+        self.soc_sizes = ss
+        h = P()
+        _check(lib().acs_problem_create_dense(self.m, self.n, a.ctypes.data_as(DP), bb.ctypes.data_as(DP),
+                                              cc.ctypes.data_as(DP), self.n_orth, len(ss),
+                                              ss.ctypes.data_as(I32P), ctypes.byref(h)))
+        self.handle = h
+        self._keep = None
+        return self
 
     def device_bytes(self, precision: int = PREC_MIXED) -> int:
         return int(lib().acs_problem_device_bytes(self.handle, precision))

@@ -523,7 +523,7 @@ struct acs_batch {
 extern "C" {
 
 int64_t acs_batch_device_bytes(const acs_problem* p) {
-  if (!p) return -1;
+  if (!p || p->p->dense) return -1;
   return int64_t(layout_instance(*p->p, 0).end);
 }
 
@@ -536,6 +536,7 @@ int acs_batch_create(int32_t count, const acs_problem* const* probs, const acs_s
     v.reserve(count);
     for (int i = 0; i < count; ++i) {
       if (!probs[i]) throw AcsError(ACS_ERR_ARG, "null problem in batch");
+      if (probs[i]->p->dense) throw AcsError(ACS_ERR_ARG, "dense problems are solved one at a time (acs_solve)");
       v.push_back(probs[i]->p);
     }
     auto b = std::make_unique<acs_batch>();
@@ -586,6 +587,7 @@ int acs_batch_solve(int32_t count, const acs_problem* const* probs, const acs_se
     std::vector<std::shared_ptr<const Problem>> v;
     for (int i = 0; i < count; ++i) {
       if (!probs[i]) throw AcsError(ACS_ERR_ARG, "null problem in batch");
+      if (probs[i]->p->dense) throw AcsError(ACS_ERR_ARG, "dense problems are solved one at a time (acs_solve)");
       v.push_back(probs[i]->p);
     }
     Batch b(std::move(v), *s, static_cast<hipStream_t>(stream));

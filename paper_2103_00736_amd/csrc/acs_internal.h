@@ -70,6 +70,14 @@ struct SellPair {
 struct Problem {
   int32_t m = 0, n = 0;
   int64_t nnz = 0;
+  // Dense A (acs_problem_create_dense): row-major, leading dimension ld (n
+  // rounded up to 64, padding zero), FP32 values; dlo holds the FP32 rounding
+  // error of each value when some value is not an FP32 number (empty
+  // otherwise), so hi + lo is the value for the FP64 sweeps.  The sparse
+  // fields below are then empty and row_perm is the identity.
+  bool dense = false;
+  int32_t ld = 0;
+  std::vector<float> dhi, dlo;
   std::vector<int32_t> row_perm;  // m
   std::vector<int32_t> row_ptr;  // m+1
   std::vector<int32_t> col;      // nnz
@@ -92,6 +100,10 @@ struct Problem {
   mutable std::once_flag sell_once_;
   mutable std::unique_ptr<SellPair> sell_;
 };
+
+// Validates and copies a dense problem (A row-major m x n).
+bool build_problem_dense(int32_t m, int32_t n, const double* a, const double* b, const double* c, int32_t n_orth,
+                         int32_t n_soc, const int32_t* soc_sizes, Problem* out, std::string* err);
 
 // Validates and copies a problem; on failure returns false and sets err.
 bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,

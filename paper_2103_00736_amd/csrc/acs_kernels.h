@@ -106,6 +106,19 @@ struct Dev {
   double* part64;          // kSlices x m partial row sums of the FP64 residual
   const int32_t* row_perm; // internal row -> caller's row
   VT* mtmp;                // m-vector scratch of the plain products
+  // dense A (row-major, leading dimension ld, padding columns zero): FP32
+  // values, dlo = FP32 rounding error of each value or nullptr; products
+  // apply D and O to vectors.  Column products run over row chunks of dchunk
+  // rows into dpart (dnchunk x ld partial sums), then a reduction kernel.
+  int32_t dense;
+  int32_t ld;
+  int32_t dchunk, dnchunk;
+  const float* dhi;
+  const float* dlo;
+  double* dpart;
+  VT* dx32;      // ld-vector input of the FP32 row products (O t, O x)
+  double* dx64;  // ld-vector input of the FP64 row products (O v, O xhat, O^2)
+  double* partials2;  // ||t||^2 partials of the dense CG, read by the row product
   const RowBlock* a_blk;
   int32_t a_nblk;
   const int32_t* soc_off;  // n_soc + 1 absolute offsets

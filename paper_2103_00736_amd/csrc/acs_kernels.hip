@@ -13,6 +13,7 @@
 // contiguous range of row blocks.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "acs_kernels.h"
 
@@ -323,13 +324,16 @@ __device__ __forceinline__ double lorentz_dist2(double u0, double nb) {
 // ----------------------------------------------------------------------------
 // step 18 (+19-20 on checks, +16 of the next iteration): rows j of A_s^T
 // ----------------------------------------------------------------------------
+// Per column j of A_s^T, given u = (A_s^T w)_j: steps 16-20 fused (see the
+// header), and the check reductions.  Shared by the sparse and dense sweeps.
 template <typename VT, int MODE, bool CHECK>
-__global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restrict__ s_cur, VT* __restrict__ s_new) {
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  const double mu = d.mu;
-  auto pre = [](int) -> double { return 0.0; };
-  auto epi = [&](int j, double u, double) {
+struct UpdateEpi {
+  const Dev<VT>& d;
+  const VT* __restrict__ s_cur;
+  VT* __restrict__ s_new;
+  double (&acc)[7];
+  __device__ __forceinline__ void operator()(int j, double u) const {
+    const double mu = d.mu;
     const double zt = d.chat[j] + u;  // mu * (O z) implied by w
     const double s = double(s_cur[j]);
     const bool orth = j < d.n_orth;
@@ -366,7 +370,16 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restri
       else
         d.zt[j] = zt;
     }
-  };
+  }
+};
+
+template <typename VT, int MODE, bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restrict__ s_cur, VT* __restrict__ s_new) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  UpdateEpi<VT, MODE, CHECK> upd{d, s_cur, s_new, acc};
+  auto pre = [](int) -> double { return 0.0; };
+  auto epi = [&](int j, double u, double) { upd(j, u); };
   sell_rows<double, double>(d.st, d.st_val64, 0, blk, d.w, pre, epi);
   if (MODE != UPD_PROLOGUE) block_store_partials<7>(acc, d.partials, blk);
 }
@@ -512,6 +525,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
   sell_rows<VT, VT>(d.sa, d.sa_val, x, lb, d.t, pre, epi);
 }
 
+// CG update of row i given (M q)_i: q = r + beta q; w += alpha q; r -= alpha M q
+template <typename VT>
+__device__ __forceinline__ void cg_row_update(const Dev<VT>& d, int i, VT mq, double alpha, double beta, VT valpha,
+                                              VT vbeta, double& rr) {
+  const VT ri = d.r[i];
+  const VT qi = (beta != 0.0) ? ri + vbeta * d.q[i] : ri;
+  d.q[i] = qi;
+  d.w[i] += alpha * double(qi);
+  const VT rn = ri - valpha * mq;
+  d.r[i] = rn;
+  rr += double(rn) * double(rn);
+}
+
 // Mq_i = sum over slices (fixed order); q = r + beta q; w += alpha q; r -= alpha Mq
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_cg_a_comb(Dev<VT> d) {
@@ -524,13 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_comb(Dev<VT> d) {
     VT mq = d.part[i];
 #pragma unroll
     for (int x = 1; x < kSlices; ++x) mq += d.part[size_t(x) * m + i];
-    const VT ri = d.r[i];
-    const VT qi = (beta != 0.0) ? ri + vbeta * d.q[i] : ri;
-    d.q[i] = qi;
-    d.w[i] += alpha * double(qi);
-    const VT rn = ri - valpha * mq;
-    d.r[i] = rn;
-    acc[0] += double(rn) * double(rn);
+    cg_row_update(d, i, mq, alpha, beta, valpha, vbeta, acc[0]);
   }
   block_store_partials<1>(acc, d.partials, blockIdx.x);
 }
@@ -557,6 +577,16 @@ __global__ __launch_bounds__(kBlock) void k_sell_vals(const int32_t* __restrict_
 // KKT check (rows i of A_s): ||A x - b||^2 = sum (d_i^-1 ((A_s xhat)_i - b_s,i))^2,
 // y = -d w / mu, b^T y; the last workgroup assembles the relative errors
 // ----------------------------------------------------------------------------
+// check, row i given (A_s xhat)_i: ||A x - b||^2 term, y_i, b^T y term
+template <typename VT>
+__device__ __forceinline__ void pres_row(const Dev<VT>& d, int i, double ax, double mu, double (&acc)[2]) {
+  const double res = (ax - d.bs[i]) * d.dsq[i];
+  acc[0] += res * res;
+  const double yi = -d.dinv[i] * d.w[i] / mu;
+  d.yout[i] = yi;
+  acc[1] += d.b[i] * yi;
+}
+
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -567,13 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d) {
   auto prod = [&](int k) -> double { return av[k] * xh[ac[k]]; };
   double acc[2] = {0, 0};
   const double mu = d.mu;
-  auto epi = [&](int i, double ax) {
-    const double res = (ax - d.bs[i]) * d.dsq[i];
-    acc[0] += res * res;
-    const double yi = -d.dinv[i] * d.w[i] / mu;
-    d.yout[i] = yi;
-    acc[1] += d.b[i] * yi;
-  };
+  auto epi = [&](int i, double ax) { pres_row(d, i, ax, mu, acc); };
   rows_block<double>(d.a_rp, rb, prod, epi);
   block_store_partials<2>(acc, d.partials, blk);
 }
@@ -693,6 +717,18 @@ __global__ __launch_bounds__(kBlock) void k_cond_scale(Dev<VT> d, VT* __restrict
 // step 12: rebuild A_s = diag(d) A O; d_i = (sum_j a_ij^2 O_j^2)^(-1/2)
 // wmode: 0 keep w, 1 rescale w by d_old/d_new, 2 w holds unscaled w -> multiply by 1/d
 // ----------------------------------------------------------------------------
+// step 12, row i given D = sum_j a_ij^2 O_j^2: d_i, 1/d_i, b_s; w rescaled (wmode)
+template <typename VT>
+__device__ __forceinline__ void rowsum_row(const Dev<VT>& d, int i, double D, int wmode) {
+  if (!(D > 0.0)) D = 1.0;  // empty row: unit diagonal
+  const double ds = sqrt(D);
+  if (wmode == 1) d.w[i] *= ds / d.dsq[i];
+  if (wmode == 2) d.w[i] *= ds;
+  d.dsq[i] = ds;
+  d.dinv[i] = 1.0 / ds;
+  d.bs[i] = d.b[i] / ds;
+}
+
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_rowsum(Dev<VT> d, int wmode) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -704,15 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(Dev<VT> d, int wmode) {
     const double g = ao[k] * O[ac[k]];
     return g * g;
   };
-  auto epi = [&](int i, double D) {
-    if (!(D > 0.0)) D = 1.0;  // empty row: unit diagonal
-    const double ds = sqrt(D);
-    if (wmode == 1) d.w[i] *= ds / d.dsq[i];
-    if (wmode == 2) d.w[i] *= ds;
-    d.dsq[i] = ds;
-    d.dinv[i] = 1.0 / ds;
-    d.bs[i] = d.b[i] / ds;
-  };
+  auto epi = [&](int i, double D) { rowsum_row(d, i, D, wmode); };
   rows_block<double>(d.a_rp, rb, prod, epi);
 }
 
@@ -947,12 +975,300 @@ __global__ __launch_bounds__(kBlock) void k_fin_cond(Dev<VT> d, int nb, double t
 }
 
 // ----------------------------------------------------------------------------
+// Dense A, row-major with leading dimension ld (Sec. V instances).  Products
+// apply the scalings to vectors: (A_s x)_i = d_i sum_j a_ij (O_j x_j) and
+// (A_s^T y)_j = O_j sum_i a_ij (d_i y_i), with d_i = 1/sqrt(D_i).  They stream
+// A once each with 16-byte loads: rows of A by a wave per 4 rows (the x chunk
+// loaded once for the 4 rows); columns by strips of 1024 columns (4 per lane)
+// over chunks of rows into partial sums, added in fixed order by a second
+// kernel.  FP64 sweeps add the FP32 low part of each value when present.
+// ----------------------------------------------------------------------------
+enum DenseKind { DK_CG = 0, DK_RESID = 1, DK_PRES = 2, DK_ROWSUM = 3, DK_SPMV = 4, DK_UPDATE = 5 };
+constexpr int kDenseRows = 4;                      // rows per wave of the row products
+constexpr int kDenseStrip = kBlock * 4;            // columns per workgroup of the column products
+
+template <typename ACC, typename XT>
+__device__ __forceinline__ void load_x4(const XT* __restrict__ x, int c, ACC (&xv)[4]) {
+  if constexpr (sizeof(XT) == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(x + c);
+    xv[0] = ACC(v.x);
+    xv[1] = ACC(v.y);
+    xv[2] = ACC(v.z);
+    xv[3] = ACC(v.w);
+  } else {
+    const double2 v0 = *reinterpret_cast<const double2*>(x + c);
+    const double2 v1 = *reinterpret_cast<const double2*>(x + c + 2);
+    xv[0] = ACC(v0.x);
+    xv[1] = ACC(v0.y);
+    xv[2] = ACC(v1.x);
+    xv[3] = ACC(v1.y);
+  }
+}
+
+template <typename ACC, bool SQ>
+__device__ __forceinline__ void fma4(ACC& s, const float4 a, const float4* lo, const ACC (&xv)[4]) {
+  ACC a0 = ACC(a.x), a1 = ACC(a.y), a2 = ACC(a.z), a3 = ACC(a.w);
+  if (lo) {
+    a0 += ACC(lo->x);
+    a1 += ACC(lo->y);
+    a2 += ACC(lo->z);
+    a3 += ACC(lo->w);
+  }
+  if (SQ) {
+    a0 *= a0;
+    a1 *= a1;
+    a2 *= a2;
+    a3 *= a3;
+  }
+  s += a0 * xv[0];
+  s += a1 * xv[1];
+  s += a2 * xv[2];
+  s += a3 * xv[3];
+}
+
+// sum_j a_ij x_j (a_ij^2 x_j if SQ) for the wave's rows i0..i0+3 (clamped to
+// m), in ACC; result on every lane.  x has ld entries (padding zero).
+template <typename VT, typename ACC, typename XT, bool SQ>
+__device__ __forceinline__ void dense_rows4(const Dev<VT>& d, int i0, const XT* __restrict__ x, bool use_lo,
+                                            ACC (&s)[kDenseRows]) {
+  const int lane = threadIdx.x & 63;
+  const float* rows[kDenseRows];
+  const float* rlo[kDenseRows];
+#pragma unroll
+  for (int r = 0; r < kDenseRows; ++r) {
+    const size_t i = size_t(min(i0 + r, d.m - 1));
+    rows[r] = d.dhi + i * d.ld;
+    rlo[r] = use_lo ? d.dlo + i * d.ld : nullptr;
+    s[r] = 0;
+  }
+  for (int c = lane * 4; c < d.ld; c += 256) {
+    ACC xv[4];
+    float4 a[kDenseRows];
+#pragma unroll
+    for (int r = 0; r < kDenseRows; ++r) a[r] = *reinterpret_cast<const float4*>(rows[r] + c);
+    load_x4<ACC, XT>(x, c, xv);
+    if (use_lo) {
+      float4 l[kDenseRows];
+#pragma unroll
+      for (int r = 0; r < kDenseRows; ++r) l[r] = *reinterpret_cast<const float4*>(rlo[r] + c);
+#pragma unroll
+      for (int r = 0; r < kDenseRows; ++r) fma4<ACC, SQ>(s[r], a[r], &l[r], xv);
+    } else {
+#pragma unroll
+      for (int r = 0; r < kDenseRows; ++r) fma4<ACC, SQ>(s[r], a[r], nullptr, xv);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kDenseRows; ++r) s[r] = wave_sum(s[r]);
+}
+
+// Row products.  CG: (A_s t)_i from dx32 = O t, then the CG update of row i
+// (alpha from the ||t||^2 partials, computed by every workgroup in the same
+// order).  RESID: r = A_s v - b_s from dx64 = O v.  PRES: the check from
+// dx64 = O xhat.  ROWSUM: D_i from dx64 = O^2 (wmode as k_rowsum).  SPMV:
+// y = A_s x from dx32 = O x.
+template <typename VT, int KIND>
+__global__ __launch_bounds__(kBlock) void k_dense_rows(Dev<VT> d, int aux, VT* __restrict__ y) {
+  __shared__ int bad_sh;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = (blockIdx.x * (kBlock / 64) + wave) * kDenseRows;
+  double acc[2] = {0, 0};
+  double alpha = 0, beta = 0;
+  if (KIND == DK_CG) {
+    if (d.ctl->done) return;
+    double tt[1];
+    sum_partials<1>(d.partials2, aux, tt);
+    if (threadIdx.x == 0) bad_sh = !(tt[0] > 0.0) || isinf(tt[0]);
+    __syncthreads();
+    if (bad_sh) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctl* c = d.ctl;
+        c->alpha = 0.0;
+        c->done = 1;
+        if (!(tt[0] == tt[0])) host_post(&d.hs->numeric, 1);
+        host_post(&d.hs->cg_done_iter, c->iter);
+      }
+      return;
+    }
+    alpha = d.ctl->rho / tt[0];
+    beta = d.ctl->beta;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.ctl->alpha = alpha;
+  }
+  if (KIND == DK_CG || KIND == DK_SPMV) {
+    VT s[kDenseRows];  // FP64 mode keeps the exact values (the low part)
+    dense_rows4<VT, VT, VT, false>(d, i0, d.dx32, sizeof(VT) == sizeof(double) && d.dlo != nullptr, s);
+    if (lane == 0) {
+      for (int r = 0; r < kDenseRows; ++r) {
+        const int i = i0 + r;
+        if (i >= d.m) break;
+        const VT mq = VT(d.dinv[i]) * s[r];
+        if (KIND == DK_CG)
+          cg_row_update(d, i, mq, alpha, beta, VT(alpha), VT(beta), acc[0]);
+        else
+          y[i] = mq;
+      }
+    }
+  } else {
+    double s[kDenseRows];
+    if (KIND == DK_ROWSUM)
+      dense_rows4<VT, double, double, true>(d, i0, d.dx64, d.dlo != nullptr, s);
+    else
+      dense_rows4<VT, double, double, false>(d, i0, d.dx64, d.dlo != nullptr, s);
+    if (lane == 0) {
+      for (int r = 0; r < kDenseRows; ++r) {
+        const int i = i0 + r;
+        if (i >= d.m) break;
+        if (KIND == DK_RESID) {
+          const VT ri = VT(d.dinv[i] * s[r] - d.bs[i]);
+          d.r[i] = ri;
+          acc[0] += double(ri) * double(ri);
+        } else if (KIND == DK_PRES) {
+          pres_row(d, i, d.dinv[i] * s[r], d.mu, acc);
+        } else {
+          rowsum_row(d, i, s[r], aux);
+        }
+      }
+    }
+  }
+  if (KIND == DK_CG || KIND == DK_RESID) {
+    double a1[1] = {acc[0]};
+    block_store_partials<1>(a1, d.partials, blockIdx.x);
+  } else if (KIND == DK_PRES) {
+    block_store_partials<2>(acc, d.partials, blockIdx.x);
+  }
+}
+
+// Column products, partial sums over one chunk of rows: part[chunk][j] =
+// sum_i a_ij y_i with y_i = d_i r_i (CG, VT), d_i w_i (UPDATE, FP64) or d_i
+// x_i (SPMV, VT; x in the caller's order, which is the internal one here).
+template <typename VT, int KIND>
+__global__ __launch_bounds__(kBlock) void k_dense_cols(Dev<VT> d, const VT* __restrict__ xin) {
+  using ACC = typename std::conditional<KIND == DK_UPDATE, double, VT>::type;
+  if (KIND == DK_CG && d.ctl->done) return;
+  const int c = (blockIdx.x * kBlock + threadIdx.x) * 4;
+  if (c >= d.ld) return;
+  const int r0 = blockIdx.y * d.dchunk, r1 = min(d.m, r0 + d.dchunk);
+  const bool use_lo = sizeof(ACC) == sizeof(double) && d.dlo != nullptr;  // FP64 sums keep the exact values
+  ACC s[4] = {0, 0, 0, 0};
+  for (int i = r0; i < r1; ++i) {
+    ACC yi;
+    if (KIND == DK_CG)
+      yi = ACC(d.dinv[i]) * ACC(d.r[i]);
+    else if (KIND == DK_UPDATE)
+      yi = d.dinv[i] * d.w[i];
+    else
+      yi = ACC(d.dinv[i]) * ACC(xin[i]);
+    const float4 a = *reinterpret_cast<const float4*>(d.dhi + size_t(i) * d.ld + c);
+    ACC a0 = ACC(a.x), a1 = ACC(a.y), a2 = ACC(a.z), a3 = ACC(a.w);
+    if (use_lo) {
+      const float4 l = *reinterpret_cast<const float4*>(d.dlo + size_t(i) * d.ld + c);
+      a0 += ACC(l.x);
+      a1 += ACC(l.y);
+      a2 += ACC(l.z);
+      a3 += ACC(l.w);
+    }
+    s[0] += a0 * yi;
+    s[1] += a1 * yi;
+    s[2] += a2 * yi;
+    s[3] += a3 * yi;
+  }
+  ACC* part = reinterpret_cast<ACC*>(d.dpart) + size_t(blockIdx.y) * d.ld + c;
+  if constexpr (sizeof(ACC) == 4) {
+    *reinterpret_cast<float4*>(part) = make_float4(s[0], s[1], s[2], s[3]);
+  } else {
+    *reinterpret_cast<double2*>(part) = make_double2(s[0], s[1]);
+    *reinterpret_cast<double2*>(part + 2) = make_double2(s[2], s[3]);
+  }
+}
+
+// Column products, the chunk partials added in fixed order and the step of
+// the column: CG t = O_j sum + beta t_old, dx32 = O t, ||t||^2 partials;
+// UPDATE the fused update (UpdateEpi); SPMV y_j = O_j sum.
+template <typename VT, int KIND, int MODE, bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_dense_cols_fin(Dev<VT> d, const VT* __restrict__ s_cur,
+                                                           VT* __restrict__ s_new) {
+  using ACC = typename std::conditional<KIND == DK_UPDATE, double, VT>::type;
+  if (KIND == DK_CG && d.ctl->done) return;
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const ACC* part = reinterpret_cast<const ACC*>(d.dpart);
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (j < d.n) {
+    ACC sum = part[j];
+    for (int ch = 1; ch < d.dnchunk; ++ch) sum += part[size_t(ch) * d.ld + j];
+    if (KIND == DK_CG) {
+      const double beta = d.ctl->beta;
+      const VT t = VT(d.O[j]) * sum;
+      const VT tj = (beta != 0.0) ? t + VT(beta) * d.t[j] : t;
+      d.t[j] = tj;
+      d.dx32[j] = VT(d.O[j]) * tj;
+      acc[0] = double(tj) * double(tj);
+    } else if (KIND == DK_UPDATE) {
+      UpdateEpi<VT, MODE, CHECK> upd{d, s_cur, s_new, acc};
+      upd(j, d.O[j] * double(sum));
+    } else {
+      s_new[j] = VT(d.O[j]) * sum;
+    }
+  }
+  if (KIND == DK_CG) {
+    double a1[1] = {acc[0]};
+    block_store_partials<1>(a1, d.partials2, blockIdx.x);
+  } else if (KIND == DK_UPDATE && MODE != UPD_PROLOGUE) {
+    block_store_partials<7>(acc, d.partials, blockIdx.x);
+  }
+}
+
+// inputs of the row products: dx64 = O v (0), O xhat (1), O^2 (2); dx32 = O x (3)
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_dense_prep(Dev<VT> d, int what, const VT* __restrict__ x) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= d.n) return;
+  const double o = d.O[j];
+  if (what == 0)
+    d.dx64[j] = o * double(d.v[j]);
+  else if (what == 1)
+    d.dx64[j] = o * d.xhat[j];
+  else if (what == 2)
+    d.dx64[j] = o * o;
+  else
+    d.dx32[j] = VT(o) * x[j];
+}
+
+static inline int dense_row_blocks(int m) { return (m + kDenseRows * (kBlock / 64) - 1) / (kDenseRows * (kBlock / 64)); }
+
+// ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
 static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 template <typename VT>
+static void launch_dense_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool check, hipStream_t st) {
+  const dim3 gc(ceil_div(d.ld, kDenseStrip), d.dnchunk), b(kBlock);
+  ACS_LAUNCH((k_dense_cols<VT, DK_UPDATE>), gc, b, 0, st, d, static_cast<const VT*>(nullptr));
+  const dim3 gf(ceil_div(d.n, kBlock));
+  if (mode == UPD_PROLOGUE) {
+    ACS_LAUNCH((k_dense_cols_fin<VT, DK_UPDATE, UPD_PROLOGUE, false>), gf, b, 0, st, d, s_cur, s_new);
+    return;
+  }
+  if (mode == UPD_UPDATE) {
+    if (check)
+      ACS_LAUNCH((k_dense_cols_fin<VT, DK_UPDATE, UPD_UPDATE, true>), gf, b, 0, st, d, s_cur, s_new);
+    else
+      ACS_LAUNCH((k_dense_cols_fin<VT, DK_UPDATE, UPD_UPDATE, false>), gf, b, 0, st, d, s_cur, s_new);
+  } else {
+    if (check)
+      ACS_LAUNCH((k_dense_cols_fin<VT, DK_UPDATE, UPD_UPDATE_ONLY, true>), gf, b, 0, st, d, s_cur, s_new);
+    else
+      ACS_LAUNCH((k_dense_cols_fin<VT, DK_UPDATE, UPD_UPDATE_ONLY, false>), gf, b, 0, st, d, s_cur, s_new);
+  }
+  ACS_LAUNCH((k_fin_upd<VT>), dim3(1), b, 0, st, d, int(gf.x));
+}
+
+template <typename VT>
 void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool check, hipStream_t st) {
+  if (d.dense) {
+    launch_dense_update(d, s_cur, s_new, mode, check, st);
+    return;
+  }
   const dim3 g(d.st.wg[0]), b(kBlock);
   if (mode == UPD_PROLOGUE) {
     ACS_LAUNCH((k_update<VT, UPD_PROLOGUE, false>), g, b, 0, st, d, s_cur, s_new);
@@ -985,17 +1301,32 @@ static inline int comb_blocks(int m) { return std::min(ceil_div(m, kBlock), 2048
 
 template <typename VT>
 void launch_resid(const Dev<VT>& d, hipStream_t st) {
+  if (d.dense) {
+    ACS_LAUNCH((k_dense_prep<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d, 0,
+               static_cast<const VT*>(nullptr));
+    ACS_LAUNCH((k_dense_rows<VT, DK_RESID>), dim3(dense_row_blocks(d.m)), dim3(kBlock), 0, st, d, 0,
+               static_cast<VT*>(nullptr));
+    return;
+  }
   ACS_LAUNCH((k_resid_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d);
   ACS_LAUNCH((k_resid_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st) {
-  ACS_LAUNCH((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), iter, red2, abs2);
+  const int nb = d.dense ? dense_row_blocks(d.m) : comb_blocks(d.m);
+  ACS_LAUNCH((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, iter, red2, abs2);
 }
 
 template <typename VT>
 void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
+  if (d.dense) {
+    ACS_LAUNCH((k_dense_cols<VT, DK_CG>), dim3(ceil_div(d.ld, kDenseStrip), d.dnchunk), dim3(kBlock), 0, st, d,
+               static_cast<const VT*>(nullptr));
+    ACS_LAUNCH((k_dense_cols_fin<VT, DK_CG, 0, false>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d,
+               static_cast<const VT*>(nullptr), static_cast<VT*>(nullptr));
+    return;
+  }
   ACS_LAUNCH((k_cg_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d);
 }
 
@@ -1006,24 +1337,38 @@ void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st) {
 
 template <typename VT>
 void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
+  if (d.dense) {  // the row product and the CG update of each row in one kernel
+    ACS_LAUNCH((k_dense_rows<VT, DK_CG>), dim3(dense_row_blocks(d.m)), dim3(kBlock), 0, st, d, ceil_div(d.n, kBlock),
+               static_cast<VT*>(nullptr));
+    return;
+  }
   ACS_LAUNCH((k_cg_a_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
 }
 
 template <typename VT>
 void launch_cg_comb(const Dev<VT>& d, hipStream_t st) {
+  if (d.dense) return;  // fused into the row product
   ACS_LAUNCH((k_cg_a_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
-  ACS_LAUNCH((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, comb_blocks(d.m), launch_id);
+  const int nb = d.dense ? dense_row_blocks(d.m) : comb_blocks(d.m);
+  ACS_LAUNCH((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, launch_id);
 }
 
 template <typename VT>
 void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st) {
-  ACS_LAUNCH((k_pres<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
-  ACS_LAUNCH((k_fin_pres<VT>), dim3(1), dim3(kBlock), 0, st, d, d.a_nblk, iter, bnorm, cnorm,
-                     int(d.n_soc > 0));
+  int nb = d.a_nblk;
+  if (d.dense) {
+    nb = dense_row_blocks(d.m);
+    ACS_LAUNCH((k_dense_prep<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d, 1,
+               static_cast<const VT*>(nullptr));
+    ACS_LAUNCH((k_dense_rows<VT, DK_PRES>), dim3(nb), dim3(kBlock), 0, st, d, 0, static_cast<VT*>(nullptr));
+  } else {
+    ACS_LAUNCH((k_pres<VT>), dim3(nb), dim3(kBlock), 0, st, d);
+  }
+  ACS_LAUNCH((k_fin_pres<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, iter, bnorm, cnorm, int(d.n_soc > 0));
 }
 
 template <typename VT>
@@ -1042,6 +1387,14 @@ void launch_cond_scale(const Dev<VT>& d, VT* s_cur, hipStream_t st) {
 
 template <typename VT>
 void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
+  if (d.dense) {  // D from the stored A and O; the products scale on the fly
+    ACS_LAUNCH((k_dense_prep<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d, 2,
+               static_cast<const VT*>(nullptr));
+    ACS_LAUNCH((k_dense_rows<VT, DK_ROWSUM>), dim3(dense_row_blocks(d.m)), dim3(kBlock), 0, st, d, wmode,
+               static_cast<VT*>(nullptr));
+    ACS_LAUNCH((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
+    return;
+  }
   ACS_LAUNCH((k_rowsum<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d, wmode);
   ACS_LAUNCH((k_scale_a<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
   for (const auto* S : {&d.sa, &d.st}) {
@@ -1055,6 +1408,18 @@ void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
 
 template <typename VT>
 void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st) {
+  if (d.dense) {
+    if (which == 0) {
+      ACS_LAUNCH((k_dense_prep<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d, 3, x);
+      ACS_LAUNCH((k_dense_rows<VT, DK_SPMV>), dim3(dense_row_blocks(d.m)), dim3(kBlock), 0, st, d, 0, y);
+    } else {
+      ACS_LAUNCH((k_dense_cols<VT, DK_SPMV>), dim3(ceil_div(d.ld, kDenseStrip), d.dnchunk), dim3(kBlock), 0, st,
+                 d, x);
+      ACS_LAUNCH((k_dense_cols_fin<VT, DK_SPMV, 0, false>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d,
+                 static_cast<const VT*>(nullptr), y);
+    }
+    return;
+  }
   if (which == 0) {
     ACS_LAUNCH((k_spmv_a<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, x);
     ACS_LAUNCH((k_spmv_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d, y);

@@ -12,6 +12,76 @@ static bool fail(std::string* err, const std::string& msg) {
   return false;
 }
 
+// b, c and the cone list (shared by the sparse and the dense builder)
+static bool set_vectors_and_cones(int32_t m, int32_t n, const double* b, const double* c, int32_t n_orth,
+                                  int32_t n_soc, const int32_t* soc_sizes, Problem* out, std::string* err) {
+  for (int32_t i = 0; i < m; ++i)
+    if (!std::isfinite(b[i])) return fail(err, "non-finite entry in b");
+  for (int32_t j = 0; j < n; ++j)
+    if (!std::isfinite(c[j])) return fail(err, "non-finite entry in c");
+  Problem& p = *out;
+  p.m = m;
+  p.n = n;
+  int64_t total = n_orth;
+  p.n_orth = n_orth;
+  p.soc_size.assign(soc_sizes, soc_sizes + n_soc);
+  p.soc_off.resize(size_t(n_soc) + 1);
+  p.soc_off[0] = n_orth;
+  p.max_soc = 0;
+  for (int32_t i = 0; i < n_soc; ++i) {
+    if (p.soc_size[i] < 1) return fail(err, "second-order cone sizes must be >= 1");
+    total += p.soc_size[i];
+    if (total > n) return fail(err, "cone sizes exceed n");
+    p.soc_off[i + 1] = int32_t(total);
+    p.max_soc = std::max(p.max_soc, p.soc_size[i]);
+  }
+  if (total != n) return fail(err, "n_orth + sum(soc_sizes) must equal n");
+  double bb = 0, cc = 0;
+  for (int32_t i = 0; i < m; ++i) bb += b[i] * b[i];
+  for (int32_t j = 0; j < n; ++j) cc += c[j] * c[j];
+  p.bnorm = std::sqrt(bb);
+  p.cnorm = std::sqrt(cc);
+  return true;
+}
+
+bool build_problem_dense(int32_t m, int32_t n, const double* a, const double* b, const double* c, int32_t n_orth,
+                         int32_t n_soc, const int32_t* soc_sizes, Problem* out, std::string* err) {
+  if (m < 1 || n < 1) return fail(err, "m and n must be >= 1");
+  if (!a || !b || !c) return fail(err, "null array argument");
+  if (n_orth < 0 || n_soc < 0) return fail(err, "n_orth and n_soc must be >= 0");
+  if (n_soc > 0 && !soc_sizes) return fail(err, "soc_sizes is null");
+  const int64_t ld = (int64_t(n) + 63) / 64 * 64;
+  if (ld * m >= (int64_t(1) << 31) - 1) return fail(err, "dense matrix too large (m * n must stay below 2^31)");
+  Problem& p = *out;
+  if (!set_vectors_and_cones(m, n, b, c, n_orth, n_soc, soc_sizes, &p, err)) return false;
+  p.dense = true;
+  p.ld = int32_t(ld);
+  p.nnz = int64_t(m) * n;
+  p.dhi.assign(size_t(ld) * m, 0.0f);
+  bool exact = true;
+  for (int32_t i = 0; i < m; ++i)
+    for (int32_t j = 0; j < n; ++j) {
+      const double v = a[int64_t(i) * n + j];
+      if (!std::isfinite(v)) return fail(err, "non-finite matrix value");
+      const float h = float(v);
+      p.dhi[size_t(i) * ld + j] = h;
+      exact = exact && double(h) == v;
+    }
+  if (!exact) {
+    p.dlo.assign(size_t(ld) * m, 0.0f);
+    for (int32_t i = 0; i < m; ++i)
+      for (int32_t j = 0; j < n; ++j) {
+        const double v = a[int64_t(i) * n + j];
+        p.dlo[size_t(i) * ld + j] = float(v - double(p.dhi[size_t(i) * ld + j]));
+      }
+  }
+  p.row_perm.resize(m);
+  for (int32_t i = 0; i < m; ++i) p.row_perm[i] = i;
+  p.b.assign(b, b + m);
+  p.c.assign(c, c + n);
+  return true;
+}
+
 bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                    const double* val, const double* b, const double* c, int32_t n_orth, int32_t n_soc,
                    const int32_t* soc_sizes, Problem* out, std::string* err) {
@@ -45,28 +115,9 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
       if (!std::isfinite(val[k])) return fail(err, "non-finite matrix value");
     }
   }
-  for (int32_t i = 0; i < m; ++i)
-    if (!std::isfinite(b[i])) return fail(err, "non-finite entry in b");
-  for (int32_t j = 0; j < n; ++j)
-    if (!std::isfinite(c[j])) return fail(err, "non-finite entry in c");
   Problem& p = *out;
-  p.m = m;
-  p.n = n;
+  if (!set_vectors_and_cones(m, n, b, c, n_orth, n_soc, soc_sizes, &p, err)) return false;
   p.nnz = nnz;
-  int64_t total = n_orth;
-  p.n_orth = n_orth;
-  p.soc_size.assign(soc_sizes, soc_sizes + n_soc);
-  p.soc_off.resize(size_t(n_soc) + 1);
-  p.soc_off[0] = n_orth;
-  p.max_soc = 0;
-  for (int32_t i = 0; i < n_soc; ++i) {
-    if (p.soc_size[i] < 1) return fail(err, "second-order cone sizes must be >= 1");
-    total += p.soc_size[i];
-    if (total > n) return fail(err, "cone sizes exceed n");
-    p.soc_off[i + 1] = int32_t(total);
-    p.max_soc = std::max(p.max_soc, p.soc_size[i]);
-  }
-  if (total != n) return fail(err, "n_orth + sum(soc_sizes) must equal n");
 
   // rows by decreasing length, ties in the caller's order
   p.row_perm.resize(m);
@@ -105,15 +156,11 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
   }
   p.a_blocks = make_row_blocks(p.row_ptr.data(), m, kStageNnz);
   p.t_blocks = make_row_blocks(p.t_row_ptr.data(), n, kStageNnz);
-  double bb = 0, cc = 0;
-  for (double v : p.b) bb += v * v;
-  for (double v : p.c) cc += v * v;
-  p.bnorm = std::sqrt(bb);
-  p.cnorm = std::sqrt(cc);
   return true;
 }
 
 const SellPair& Problem::sell() const {
+  if (dense) throw AcsError(ACS_ERR_STATE, "a dense problem has no sparse layout");
   std::call_once(sell_once_, [this] {
     auto sp = std::make_unique<SellPair>();
     // A t by column slices [x*w, (x+1)*w), w = ceil(n/kSlices): slice x holds

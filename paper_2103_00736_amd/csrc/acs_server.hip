@@ -105,7 +105,7 @@ class Server {
     auto r = std::make_shared<Request>();
     r->p = std::move(p);
     r->s = resolve_settings(s, *r->p);
-    r->small = r->p->nnz <= small_nnz_;
+    r->small = !r->p->dense && r->p->nnz <= small_nnz_;  // dense requests run on the worker streams
     r->bytes = r->small ? int64_t(layout_instance(*r->p, 0).end) : instance_device_bytes(*r->p, r->s.precision);
     if (r->bytes > budget_) throw AcsError(ACS_ERR_NOMEM, "request needs more device memory than the server budget");
     r->t_submit = Clock::now();

@@ -219,9 +219,27 @@ class DeviceArena {
   size_t bytes_ = 0;
 };
 
+// rows per chunk of the dense column products: enough workgroups (strips x
+// chunks) to fill the chip, at least 16 rows per chunk
+static void dense_chunks(const Problem& p, int32_t* rows, int32_t* chunks) {
+  const int64_t strips = (int64_t(p.ld) + 1023) / 1024;
+  const int64_t want = std::max<int64_t>(1, 4096 / strips);
+  int64_t r = std::max<int64_t>(16, (int64_t(p.m) + want - 1) / want);
+  *rows = int32_t(r);
+  *chunks = int32_t((int64_t(p.m) + r - 1) / r);
+}
+
 static int64_t estimate_bytes(const Problem& p, int precision) {
   const int64_t vt = precision == ACS_PREC_FP64 ? 8 : 4;
   const int64_t nnz = p.nnz, m = p.m, n = p.n;
+  if (p.dense) {
+    int32_t rows, chunks;
+    dense_chunks(p, &rows, &chunks);
+    int64_t b = 4 * int64_t(p.dhi.size()) + 4 * int64_t(p.dlo.size()) + 8 * int64_t(chunks) * p.ld;
+    b += (vt + 8) * p.ld + n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7 + 4 + vt);
+    b += 8 * 8 * (m / 16 + n / kBlock + 4) + 64 * 256;
+    return b;
+  }
   const SellPair& sp = p.sell();
   int64_t b = 0;
   b += 4 * (m + 1) + 4 * nnz + 8 * nnz + 8 * nnz;        // A pattern, original and FP64 scaled values
@@ -299,34 +317,21 @@ class Instance final : public InstanceBase {
   }
 
   // -------------------------------------------------------------- setup
-  void setup_device() {
+  // CSR of A (conditioning and check sweeps) and the SELL layouts of the products
+  template <class Up>
+  void setup_sparse(Up& up) {
     const Problem& p = *P_;
     Dev<VT>& d = d_;
-    std::memset(&d, 0, sizeof(d));
-    d.m = p.m;
-    d.n = p.n;
-    d.n_orth = p.n_orth;
-    d.n_soc = int(p.soc_size.size());
-    d.mu = S.mu;
-    auto up = [&](auto* dst, const auto& vec) {
-      HIP_CHECK(hipMemcpyAsync(dst, vec.data(), vec.size() * sizeof(vec[0]), hipMemcpyHostToDevice, st_));
-    };
     int32_t* a_rp = arena_.alloc<int32_t>(p.m + 1);
     int32_t* a_col = arena_.alloc<int32_t>(p.nnz);
     double* a_orig = arena_.alloc<double>(p.nnz);
     RowBlock* a_blk = arena_.alloc<RowBlock>(p.a_blocks.size());
-    int32_t* soc_off = arena_.alloc<int32_t>(p.soc_off.size());
-    double* b = arena_.alloc<double>(p.m);
-    double* c = arena_.alloc<double>(p.n);
     up(a_rp, p.row_ptr);
     if (p.nnz) {
       up(a_col, p.col);
       up(a_orig, p.val);
     }
     up(a_blk, p.a_blocks);
-    up(soc_off, p.soc_off);
-    up(b, p.b);
-    up(c, p.c);
     d.a_rp = a_rp;
     d.a_col = a_col;
     d.a_orig = a_orig;
@@ -374,11 +379,62 @@ class Instance final : public InstanceBase {
       }
       d.part = arena_.alloc<VT>(size_t(kSlices) * p.m);
       d.part64 = arena_.alloc<double>(size_t(kSlices) * p.m);
+    }
+  }
+
+  // dense A: FP32 values (+ low part), chunk partials, padded product inputs
+  template <class Up>
+  void setup_dense(Up& up) {
+    const Problem& p = *P_;
+    Dev<VT>& d = d_;
+    d.dense = 1;
+    d.ld = p.ld;
+    float* hi = arena_.alloc<float>(p.dhi.size());
+    up(hi, p.dhi);
+    d.dhi = hi;
+    if (!p.dlo.empty()) {
+      float* lo = arena_.alloc<float>(p.dlo.size());
+      up(lo, p.dlo);
+      d.dlo = lo;
+    }
+    dense_chunks(p, &d.dchunk, &d.dnchunk);
+    d.dpart = arena_.alloc<double>(size_t(d.dnchunk) * p.ld);
+    d.dx32 = arena_.alloc<VT>(p.ld);
+    d.dx64 = arena_.alloc<double>(p.ld);
+    d.partials2 = arena_.alloc<double>(size_t(p.n) / kBlock + 2);
+    // padding columns of the product inputs stay zero
+    HIP_CHECK(hipMemsetAsync(d.dx32, 0, sizeof(VT) * p.ld, st_));
+    HIP_CHECK(hipMemsetAsync(d.dx64, 0, sizeof(double) * p.ld, st_));
+  }
+
+  void setup_device() {
+    const Problem& p = *P_;
+    Dev<VT>& d = d_;
+    std::memset(&d, 0, sizeof(d));
+    d.m = p.m;
+    d.n = p.n;
+    d.n_orth = p.n_orth;
+    d.n_soc = int(p.soc_size.size());
+    d.mu = S.mu;
+    auto up = [&](auto* dst, const auto& vec) {
+      HIP_CHECK(hipMemcpyAsync(dst, vec.data(), vec.size() * sizeof(vec[0]), hipMemcpyHostToDevice, st_));
+    };
+    int32_t* soc_off = arena_.alloc<int32_t>(p.soc_off.size());
+    double* b = arena_.alloc<double>(p.m);
+    double* c = arena_.alloc<double>(p.n);
+    up(soc_off, p.soc_off);
+    up(b, p.b);
+    up(c, p.c);
+    {
       int32_t* rperm = arena_.alloc<int32_t>(p.m);
       up(rperm, p.row_perm);
       d.row_perm = rperm;
       d.mtmp = arena_.alloc<VT>(p.m);
     }
+    if (p.dense)
+      setup_dense(up);
+    else
+      setup_sparse(up);
     d.soc_off = soc_off;
     d.b = b;
     d.c = c;
@@ -404,7 +460,8 @@ class Instance final : public InstanceBase {
     d.ctl = arena_.alloc<Ctl>(1);
     const size_t units = size_t(p.n_orth) + p.soc_size.size();
     nparts_ = std::max<size_t>({p.a_blocks.size(), size_t(d.st.wg_max), units / kBlock + 1,
-                                 p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, 1});
+                                 p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, size_t(p.n) / kBlock + 1,
+                                 size_t(p.m) / 16 + 1, 1});
     d.partials = arena_.alloc<double>(nparts_ * 8);
     s_buf_[0] = arena_.alloc<VT>(p.n);
     s_buf_[1] = arena_.alloc<VT>(p.n);
@@ -900,6 +957,18 @@ int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr
     std::string err;
     if (!build_problem(m, n, nnz, row_ptr, col_idx, val, b, c, n_orth, n_soc, soc_sizes, p.get(), &err))
       throw AcsError(ACS_ERR_ARG, err);
+    *out = new acs_problem{std::move(p)};
+  });
+}
+
+int acs_problem_create_dense(int32_t m, int32_t n, const double* a, const double* b, const double* c, int32_t n_orth,
+                             int32_t n_soc, const int32_t* soc_sizes, acs_problem** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) throw AcsError(ACS_ERR_ARG, "out is null");
+    auto p = std::make_shared<Problem>();
+    std::string err;
+    if (!build_problem_dense(m, n, a, b, c, n_orth, n_soc, soc_sizes, p.get(), &err)) throw AcsError(ACS_ERR_ARG, err);
     *out = new acs_problem{std::move(p)};
   });
 }

@@ -177,6 +177,35 @@ def _finish(rng, m, n, row_ptr, col_idx, val, x0, z0, n_orth, soc_sizes, name) -
                         x0=x0, y0=y0, z0=z0, name=name)
 
 
+@dataclasses.dataclass
+class DenseProblem:
+    """Dense A (m x n, row-major float64 holding float32 values), b, c and a
+    cone list (orthant block first, then Lorentz cones); no planted optimum."""
+
+    m: int
+    n: int
+    A: np.ndarray
+    b: np.ndarray
+    c: np.ndarray
+    n_orth: int
+    soc_sizes: np.ndarray
+    x_feas: Optional[np.ndarray] = None  # the cone point b was built from
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return self.m * self.n
+
+    @property
+    def is_socp(self) -> bool:
+        return len(self.soc_sizes) > 0
+
+    def scipy_csr(self):
+        import scipy.sparse as sp
+
+        return sp.csr_matrix(self.A)
+
+
 # ----------------------------------------------------------------------------
 # generators
 # ----------------------------------------------------------------------------
@@ -325,3 +354,43 @@ def config4_trace(count: int = 2000, rate_per_s: float = 200.0, m_lo: float = 1e
 def iter_batch(count: int) -> Iterator[ConicProblem]:
     for i in range(count):
         yield config3(i)
+
+
+# ----------------------------------------------------------------------------
+# the paper's dense instances (Sec. V-B linear programs, Sec. V-D SOCPs)
+# ----------------------------------------------------------------------------
+
+def e3_lp(n: int, index: int = 0) -> DenseProblem:
+    """Dense LP of the paper's LP study: m = floor(0.8 n), A ~ U[-1, 1], b = A x
+    with x half-normal (absolute values of N(0,1) draws), c ~ N(0,1),
+    K = R_+^n.  Values rounded to float32."""
+    rng = np.random.default_rng(instance_seed(5, index) + n)
+    m = int(0.8 * n)
+    A = _f32(rng.uniform(-1.0, 1.0, size=(m, n)))
+    x = np.abs(rng.standard_normal(n))
+    c = _f32(rng.standard_normal(n))
+    return DenseProblem(m=m, n=n, A=A, b=A @ x, c=c, n_orth=n, soc_sizes=np.zeros(0, np.int32), x_feas=x,
+                        name=f"e3_lp_{m}x{n}")
+
+
+def e6_socp(n: int, h: int, index: int = 0) -> DenseProblem:
+    """Dense SOCP of the paper's SOCP study: m = floor(0.8 n), A ~ U[-1, 1],
+    c ~ U[0, 1], K = Lorentz cones of size h (an orthant block takes n mod h
+    coordinates).  b = A x with x drawn strictly inside K: per cone the tail
+    u ~ U[0,1]^(h-1) and the head ||u|| + U(0,1); orthant coordinates U(0,1).
+    Values rounded to float32."""
+    rng = np.random.default_rng(instance_seed(6, index) + 100 * n + h)
+    m = int(0.8 * n)
+    n_orth = n % h
+    sizes = np.full((n - n_orth) // h, h, dtype=np.int32)
+    A = _f32(rng.uniform(-1.0, 1.0, size=(m, n)))
+    x = np.empty(n)
+    x[:n_orth] = rng.random(n_orth)
+    for k in range(len(sizes)):
+        off = n_orth + k * h
+        u = rng.random(h - 1)
+        x[off + 1:off + h] = u
+        x[off] = np.sqrt(u @ u) + rng.random()
+    c = _f32(rng.random(n))
+    return DenseProblem(m=m, n=n, A=A, b=A @ x, c=c, n_orth=n_orth, soc_sizes=sizes, x_feas=x,
+                        name=f"e6_socp_h{h}_{m}x{n}")
