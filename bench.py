@@ -37,10 +37,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy", "gather"], default="lp2m",
+    ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy", "gather", "dense"], default="lp2m",
                     help="lp2m: iterations/s on the 2M-variable LP (default); batch: 4096 small LPs in one "
                          "persistent launch; serve: Poisson request stream through the serving loop")
     ap.add_argument("--count", type=int, default=4096, help="batch: number of instances")
+    ap.add_argument("--dense-n", type=int, default=30000, help="dense: n of the paper's random LP (m = 0.8 n)")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (requests/s)")
     return ap.parse_args()
@@ -64,6 +65,16 @@ def cpu_child(args):
                 20000, eps=1e-4, check_every=10)
         dt = time.perf_counter() - t0
         print(json.dumps({"iters": len(idx), "seconds": dt, "pcg_iters": 0, "what": "solves"}), flush=True)
+        return
+    if args.workload == "dense":  # the same recipe at n = 3000 (the full size takes minutes per iteration)
+        q = synth.e3_lp(3000)
+        t, L = default_parameters(q.soc_sizes)
+        t0 = time.perf_counter()
+        alg = Algorithm2(q.scipy_csr(), q.b, q.c, q.n_orth, q.soc_sizes, mu=1.0, t=t, schedule=L)
+        for _ in range(10):
+            alg.step()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"iters": 10, "seconds": dt, "pcg_iters": 0, "what": "dense"}), flush=True)
         return
     p = synth.config1(scale=args.scale)
     t, L = default_parameters(p.soc_sizes)
@@ -92,6 +103,11 @@ def finish_cpu_baseline(proc, timeout_s=600):
         sys.stderr.write(err[-2000:])
         return None
     r = json.loads(out.strip().splitlines()[-1])
+    if r.get("what") == "dense":
+        return {"value": r["iters"] / r["seconds"], "unit": "iters/s", "cores": 1, "kind": "oracle",
+                "sample": f"first {r['iters']} iterations of the FP64 oracle on the same recipe at n = 3000, "
+                          f"m = 2400 (dense Cholesky projections, l = 1 conditioning included), "
+                          f"{r['seconds']:.1f} s; the oracle needs minutes per iteration at n = 30000"}
     if r.get("what") == "solves":
         return {"value": r["iters"] / r["seconds"], "unit": "solves/s", "cores": 1, "kind": "oracle",
                 "sample": f"{r['iters']} seeded instances of the batch recipe solved one at a time to 1e-4 KKT by "
@@ -122,10 +138,10 @@ def kernel_bytes(m, n, nnz, vt=4, slices=8):
     return {"cg_a": cg_a, "cg_t": cg_t, "cg_comb": comb}
 
 
-def traffic_record(kernel):
+def traffic_record(kernel, workload="lp2m"):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lp2m.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -143,7 +159,8 @@ def main():
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
-    cpu_proc = None if (args.no_cpu_baseline or args.workload == "serve") else start_cpu_baseline(args)
+    cpu_proc = (None if (args.no_cpu_baseline or args.workload in ("serve", "copy", "gather"))
+                else start_cpu_baseline(args))
     if args.workload == "batch":
         return bench_batch(args, cpu_proc)
     if args.workload == "serve":
@@ -152,6 +169,8 @@ def main():
         return bench_copy()
     if args.workload == "gather":
         return bench_gather()
+    if args.workload == "dense":
+        return bench_dense(args, cpu_proc)
 
     from paper_2103_00736_amd import acs, synth
 
@@ -302,6 +321,73 @@ def bench_gather():
                       "what": "acs_state_spmv with 50 back-to-back launches timed by HIP events; A x includes "
                               "the slice-combine kernel, A^T x the row-order permutation of its input",
                       "cases": out}), flush=True)
+    return 0
+
+
+def dense_kernel_bytes(m, n, vt=4):
+    """Algorithmic bytes of the dense CG launches: A once (FP32) plus the vectors."""
+    rows = 4 * m * n + vt * n + (3 * vt + 16) * m  # A_s t and the CG update of r, q, w
+    cols = 4 * m * n + vt * m + 8 * m + 3 * vt * n  # A_s^T r (+ beta t_old, O t written)
+    return {"cg_a": rows, "cg_t": cols}
+
+
+def bench_dense(args, cpu_proc):
+    """Iterations/s on the paper's random dense LP (Sec. V-B recipe) at n =
+    30000, m = 24000: A is 2.9 GB of FP32 streamed twice per CG step."""
+    from paper_2103_00736_amd import acs, synth
+
+    t0 = time.perf_counter()
+    p = synth.e3_lp(args.dense_n)
+    gen_s = time.perf_counter() - t0
+    rc = acs.lib().acs_init(0)
+    if rc != 0:
+        raise RuntimeError(acs.lib().acs_last_error().decode())
+    prob = acs.Problem.from_synth(p)
+    del p.A
+    st = acs.State(prob, precision=acs.PREC_MIXED)
+    warmup = min(args.warmup, 10)
+    steps = min(args.steps, 20)
+    _progress(f"dense LP {p.m}x{p.n}: warmup {warmup}")
+    st.step(warmup)
+    cls = {"update": acs.KC_UPDATE, "resid": acs.KC_RESID, "cg_t": acs.KC_CG_T, "cg_a": acs.KC_CG_A,
+           "check": acs.KC_CHECK, "cond": acs.KC_COND, "fin": acs.KC_FIN}
+    _progress(f"timed region: {steps} iterations")
+    cg0 = st.info().cg_steps
+    st.profile([acs.KC_CG_A])
+    t1 = time.perf_counter()
+    st.step(steps)
+    t2 = time.perf_counter()
+    st.profile(False)
+    info = st.info()
+    cg = info.cg_steps - cg0
+    count, total_ms = st.timing(acs.KC_CG_A)
+    kb = dense_kernel_bytes(p.m, p.n)
+    avg_ms = total_ms / max(cg, 1)
+    achieved = kb["cg_a"] / (avg_ms * 1e-3) / 1e9
+    # breakdown of every class over a few more iterations
+    st.profile(list(cls.values()))
+    st.step(3)
+    st.profile(False)
+    prof = {k: st.timing(v) for k, v in cls.items()}
+    cpu = finish_cpu_baseline(cpu_proc) if cpu_proc else None
+    elapsed = t2 - t1
+    print(json.dumps({
+        "metric": "iters/sec on the paper's dense random LP (Sec. V-B recipe)", "value": steps / elapsed,
+        "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"dense LP m={p.m} n={p.n}, A~U[-1,1] (FP32, {4 * p.m * p.n / 1e9:.2f} GB), "
+                               f"b=A|x|, c~N(0,1), t=9.2, L={{300,400,...}}",
+                   "precision": "FP32 A and CG vectors, FP64 CG solution, residual sweeps and reductions"},
+        "roofline": {"bound": "hbm", "kernel": "k_dense_rows (CG)", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_record("cg_a", "dense_lp"),
+                     "avg_launch_ms": avg_ms,
+                     "launches": count, "working_launches": cg, "algorithmic_bytes_per_launch": kb["cg_a"]},
+        "cpu_baseline": cpu,
+        "detail": {"cg_steps_per_iter": cg / steps, "gen_s": gen_s,
+                   "kernel_ms": {k: {"count": v[0], "total_ms": round(v[1], 3)} for k, v in prof.items()},
+                   "kernel_ms_what": "every kernel class timed in 3 further iterations",
+                   "cg_t_bytes_per_launch": kb["cg_t"]},
+    }), flush=True)
     return 0
 
 
