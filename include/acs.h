@@ -69,6 +69,12 @@ extern "C" {
  * l_every = 0 means L = {l_first}.  Iteration 1 always conditions.
  * With `auto_params` = 1 the library picks the paper's per-class values:
  * LP: t = 9.2, L = {300, 400, ...}; SOCP: t = 1.7, L = {200, 300, ...}; mu = 1.
+ * Projection (Alg. 2 step 17) by warm-started CG, defaults cg_reduce = 0.1,
+ * cg_max = 500.  The iteration just before a conditioning event (its x, z set
+ * O) runs its CG to a 1e-6 reduction with up to 8 cg_max steps.  A cap that
+ * stops the CG short of cg_reduce leaves an error the outer iteration may not
+ * recover from once O is spread; smaller cg_reduce trades CG steps for outer
+ * iterations (0.03 solves the 2M-variable LP fastest).
  */
 typedef struct acs_settings {
   double mu;            /* proximal parameter mu > 0                            */

@@ -399,11 +399,15 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh) {
       bsweep<double>(I, 0, prod, epi, sh);
     }
     double rho = bsum(acc, sh.red);
-    const double tol2 = fmax(I.cg_red2 * rho, I.cg_abs2);
+    // x, z of this iteration set O at l + 1: project accurately
+    const bool feeds_event = in_sched(I, l + 1);
+    const double red2 = feeds_event ? fmin(I.cg_red2, kEventCgReduce * kEventCgReduce) : I.cg_red2;
+    const int cg_max = feeds_event ? I.cg_max * kEventCgMaxFactor : I.cg_max;
+    const double tol2 = fmax(red2 * rho, I.cg_abs2);
     double beta = 0.0;
     int k = 0;
     bool bad = !(rho == rho) || isinf(rho);
-    while (!bad && k < I.cg_max && rho > tol2) {
+    while (!bad && k < cg_max && rho > tol2) {
       acc = 0;
       {
         const float* __restrict__ tv = I.t_val;

@@ -23,6 +23,14 @@ struct RowBlock {
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kStageNnz = 2048;   // products staged in LDS per multi-row block
 constexpr int kSlices = 8;        // column slices of A, one per XCD
+// The iteration whose x, z feed a conditioning event (Alg. 2 steps 5-10 read
+// the x, z of the previous iteration) projects accurately: its CG runs to a
+// relative residual reduction of kEventCgReduce, with up to kEventCgMaxFactor
+// times the usual step cap.  The ratios o = x/z of complementary pairs are
+// taken between numbers that go to zero, so a loose projection there sets O
+// from noise; the paper's projection is exact.
+constexpr double kEventCgReduce = 1e-6;
+constexpr int kEventCgMaxFactor = 8;
 constexpr int kSellChunk = 64;    // rows per SELL chunk (one per lane of a wave64)
 constexpr int kSellMaxLen = 64;   // longest row packed into a chunk
 constexpr int kWaveRowMax = 2048; // longest row given to one wave; longer rows get a workgroup

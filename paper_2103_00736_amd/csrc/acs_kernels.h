@@ -160,7 +160,8 @@ template <typename VT> void launch_cone(const Dev<VT>& d, const VT* s, bool chec
                                         hipStream_t st);
 // residual sweep and its finalizer (rho_0, threshold, zero-step exit)
 template <typename VT> void launch_resid(const Dev<VT>& d, hipStream_t st);
-template <typename VT> void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st);
+template <typename VT> void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, int cg_max,
+                                             hipStream_t st);
 // the two CG sweeps and their finalizers (alpha; beta, stop test, host progress record)
 template <typename VT> void launch_cg_t(const Dev<VT>& d, hipStream_t st);
 template <typename VT> void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st);

@@ -861,12 +861,14 @@ __global__ __launch_bounds__(kBlock) void k_fin_cone(Dev<VT> d, int nb) {
 
 // CG start: rho_0, the stop threshold, zero-step exit
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_fin_resid(Dev<VT> d, int nb, int iter, double red2, double abs2) {
+__global__ __launch_bounds__(kBlock) void k_fin_resid(Dev<VT> d, int nb, int iter, double red2, double abs2,
+                                                      int cg_max) {
   double t[1];
   sum_partials<1>(d.partials, nb, t);
   if (threadIdx.x == 0) {
     Ctl* c = d.ctl;
     const double rho = t[0];
+    c->cg_max = cg_max;
     c->rho = rho;
     c->rho0 = rho;
     c->tol2 = fmax(red2 * rho, abs2);
@@ -1313,9 +1315,9 @@ void launch_resid(const Dev<VT>& d, hipStream_t st) {
 }
 
 template <typename VT>
-void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, hipStream_t st) {
+void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, int cg_max, hipStream_t st) {
   const int nb = d.dense ? dense_row_blocks(d.m) : comb_blocks(d.m);
-  ACS_LAUNCH((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, iter, red2, abs2);
+  ACS_LAUNCH((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, iter, red2, abs2, cg_max);
 }
 
 template <typename VT>
@@ -1438,7 +1440,7 @@ void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
   template void launch_update<VT>(const Dev<VT>&, const VT*, VT*, int, bool, hipStream_t);            \
   template void launch_cone<VT>(const Dev<VT>&, const VT*, bool, bool, int, hipStream_t);            \
   template void launch_resid<VT>(const Dev<VT>&, hipStream_t);                                        \
-  template void launch_fin_resid<VT>(const Dev<VT>&, int, double, double, hipStream_t);               \
+  template void launch_fin_resid<VT>(const Dev<VT>&, int, double, double, int, hipStream_t);               \
   template void launch_cg_t<VT>(const Dev<VT>&, hipStream_t);                                         \
   template void launch_fin_cg_t<VT>(const Dev<VT>&, hipStream_t);                                     \
   template void launch_cg_a<VT>(const Dev<VT>&, hipStream_t);                                         \

@@ -676,11 +676,11 @@ class Instance final : public InstanceBase {
   int hs_check() { return __atomic_load_n(&hs_->check_iter, __ATOMIC_ACQUIRE); }
 
   // CG for outer iteration `it`: chunks of launches, at most one chunk ahead
-  void run_cg(int it) {
+  void run_cg(int it, int cg_max) {
     const int chunk = 2;
     int launched = 0;
-    while (launched < S.cg_max) {
-      const int c = std::min(chunk, S.cg_max - launched);
+    while (launched < cg_max) {
+      const int c = std::min(chunk, cg_max - launched);
       for (int i = 0; i < c; ++i) {
         timed(KC_CG_T, [&] { launch_cg_t(d_, st_); });
         timed(KC_CG_A, [&] { launch_cg_a(d_, st_); });
@@ -689,7 +689,7 @@ class Instance final : public InstanceBase {
         timed(KC_FIN, [&] { launch_fin_cg_a(d_, id, st_); });
       }
       launched += c;
-      if (launched >= S.cg_max) break;
+      if (launched >= cg_max) break;
       const long long target = launch_id_ - c;
       wait_for([&] { return hs_cg_done() >= it || hs_launch_seq() >= target; });
       if (hs_cg_done() >= it) return;
@@ -738,10 +738,13 @@ class Instance final : public InstanceBase {
       }
       const int l = l_ + 1;
       if (sched_.contains(l)) condition();
-      timed(KC_RESID, [&] { launch_resid(d_, st_); });
-      timed(KC_FIN, [&] { launch_fin_resid(d_, l, red2, abs2, st_); });
-      run_cg(l);
       const bool next_event = sched_.contains(l + 1);
+      // x, z of this iteration set O at l + 1: project accurately
+      const double r2 = next_event ? std::min(red2, kEventCgReduce * kEventCgReduce) : red2;
+      const int cg_max = next_event ? S.cg_max * kEventCgMaxFactor : S.cg_max;
+      timed(KC_RESID, [&] { launch_resid(d_, st_); });
+      timed(KC_FIN, [&] { launch_fin_resid(d_, l, r2, abs2, cg_max, st_); });
+      run_cg(l, cg_max);
       bool check = (l % S.check_every == 0) || it == iters - 1;
       if (check && pending >= 0) {  // one check in flight at a time
         wait_for([&] { return hs_check() >= pending; });
@@ -941,7 +944,7 @@ void acs_settings_default(acs_settings* s) {
   s->check_every = 10;
   s->eps_kkt = 1e-4;
   s->precision = ACS_PREC_MIXED;
-  s->cg_max = 50;
+  s->cg_max = 500;
   s->cg_reduce = 0.1;
   s->cg_abs = 0.0;
   s->verbose = 0;

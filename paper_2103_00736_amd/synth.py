@@ -394,3 +394,15 @@ def e6_socp(n: int, h: int, index: int = 0) -> DenseProblem:
     c = _f32(rng.random(n))
     return DenseProblem(m=m, n=n, A=A, b=A @ x, c=c, n_orth=n_orth, soc_sizes=sizes, x_feas=x,
                         name=f"e6_socp_h{h}_{m}x{n}")
+
+
+def e2_lp(index: int) -> DenseProblem:
+    """One of the 10 random LPs of the paper's conditioning-schedule example
+    (Sec. IV): A in R^{80x100} with N(0,1) entries, b = A x with x ~ U[0,1]^100,
+    c ~ N(0,1), K = R_+^100.  Values rounded to float32."""
+    rng = np.random.default_rng(instance_seed(7, index))
+    A = _f32(rng.standard_normal((80, 100)))
+    x = rng.random(100)
+    c = _f32(rng.standard_normal(100))
+    return DenseProblem(m=80, n=100, A=A, b=A @ x, c=c, n_orth=100, soc_sizes=np.zeros(0, np.int32), x_feas=x,
+                        name=f"e2_lp_{index}")
