@@ -91,17 +91,22 @@ void init_instance_state(BInst& I, char* d_arena, const InstLayout& o, const Pro
                          Sched sa, Sched st_sched, hipStream_t st);
 // Lanes per row: next power of two of the mean row length, in [1, 64].
 int default_lanes(double mean_row);
-// Default schedules of an instance (staged, 2048-nonzero blocks).
+// Default schedules of an instance (staged, 1024-nonzero blocks).
 Sched default_sched_a(const Problem& p);
 Sched default_sched_t(const Problem& p);
 
 // Launch the persistent kernel over `count` descriptors; `order` lists
 // descriptor indices in the order workgroups take them; every instance runs
 // until solved or until `iter_budget` more iterations (resumable).
+// lds_floats: LDS (in floats) per workgroup for the CG's gathered vectors r
+// and t; an instance with m + n <= lds_floats keeps them there, a larger one
+// in global memory.
 void launch_batch(BInst* inst, const int32_t* order, int32_t count, unsigned int* queue, int32_t grid,
-                  int32_t block, int32_t iter_budget, hipStream_t st);
+                  int32_t lds_floats, int32_t iter_budget, hipStream_t st);
 void launch_queue_reset(unsigned int* queue, hipStream_t st);
-// Resident workgroups of the batch kernel per compute unit.
-int batch_blocks_per_cu();
+// Resident workgroups of the batch kernel per compute unit with that LDS.
+int batch_blocks_per_cu(int32_t lds_floats);
+// Most LDS floats a batch gives the gathered vectors (32 KB).
+constexpr int32_t kBatchLdsMax = 8192;
 
 }  // namespace acs

@@ -103,7 +103,7 @@ __device__ __forceinline__ void lproj(double v0, double nv, double& a0, double& 
   }
 }
 
-constexpr int kStageMax = 2048;  // LDS stage of the staged schedule (nonzeros)
+constexpr int kStageMax = 1024;  // LDS stage of the staged schedule (nonzeros)
 
 struct Shared {
   double red[kBB / 64];
@@ -363,7 +363,88 @@ __device__ void condition(BInst& I, Shared& sh) {
   }
 }
 
-__device__ void solve_one(BInst* gI, int budget, Shared& sh) {
+// Steps 17-18 projection of iteration l: residual r = A_s v - b_s (FP64
+// accumulation), then warm-started CG on (A_s A_s^T) dw = r.  With LDS the two
+// gathered vectors r (m) and t (n) live in the workgroup's LDS, so the CG's
+// random reads cost an LDS access instead of an L2 request; q and w stay in
+// global memory.  Returns the CG steps taken; `bad` reports a NaN/Inf.
+template <bool LDS>
+__device__ __forceinline__ int project(BInst& I, Shared& sh, float* __restrict__ lds, int l, bool& bad_out) {
+  float* __restrict__ rv = LDS ? lds : I.r;
+  float* __restrict__ tvec = LDS ? lds + I.m : I.t;
+  // r = A_s v - b_s (FP64 accumulation)
+  double acc = 0;
+  {
+    const double* __restrict__ av = I.a_val64;
+    const int32_t* __restrict__ ac = I.a_col;
+    const float* __restrict__ v = I.v;
+    auto prod = [&](int k) -> double { return av[k] * double(v[ac[k]]); };
+    auto epi = [&](int i, double s) {
+      const float ri = float(s - I.bs[i]);
+      rv[i] = ri;
+      acc += double(ri) * double(ri);
+    };
+    bsweep<double>(I, 0, prod, epi, sh);
+  }
+  double rho = bsum(acc, sh.red);
+  // x, z of this iteration set O at l + 1: project accurately
+  const bool feeds_event = in_sched(I, l + 1);
+  const double red2 = feeds_event ? fmin(I.cg_red2, kEventCgReduce * kEventCgReduce) : I.cg_red2;
+  const int cg_max = feeds_event ? I.cg_max * kEventCgMaxFactor : I.cg_max;
+  const double tol2 = fmax(red2 * rho, I.cg_abs2);
+  double beta = 0.0;
+  int k = 0;
+  bool bad = !(rho == rho) || isinf(rho);
+  while (!bad && k < cg_max && rho > tol2) {
+    acc = 0;
+    {
+      const float* __restrict__ tv = I.t_val;
+      const int32_t* __restrict__ tc = I.t_col;
+      const float* __restrict__ r = rv;
+      const float vb = float(beta);
+      auto prod = [&](int kk) -> float { return tv[kk] * r[tc[kk]]; };
+      auto epi = [&](int j, float s) {
+        const float tj = (beta != 0.0) ? s + vb * tvec[j] : s;
+        tvec[j] = tj;
+        acc += double(tj) * double(tj);
+      };
+      bsweep<float>(I, 1, prod, epi, sh);
+    }
+    const double tt = bsum(acc, sh.red);
+    if (!(tt > 0.0) || isinf(tt)) {
+      bad = !(tt == tt);
+      break;
+    }
+    const double alpha = rho / tt;
+    acc = 0;
+    {
+      const float* __restrict__ av = I.a_val;
+      const int32_t* __restrict__ ac = I.a_col;
+      const float* __restrict__ t = tvec;
+      const float va = float(alpha), vb = float(beta);
+      auto prod = [&](int kk) -> float { return av[kk] * t[ac[kk]]; };
+      auto epi = [&](int i, float mq) {
+        const float ri = rv[i];
+        const float qi = (beta != 0.0) ? ri + vb * I.q[i] : ri;
+        I.q[i] = qi;
+        I.w[i] += alpha * double(qi);
+        const float rn = ri - va * mq;
+        rv[i] = rn;
+        acc += double(rn) * double(rn);
+      };
+      bsweep<float>(I, 0, prod, epi, sh);
+    }
+    const double rn = bsum(acc, sh.red);
+    bad = !(rn == rn) || isinf(rn);
+    beta = bad ? 0.0 : rn / rho;
+    rho = rn;
+    ++k;
+  }
+  bad_out = bad;
+  return k;
+}
+
+__device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__ lds, int lds_floats) {
   BInst& I = sh.inst;
   {
     const int words = int(sizeof(BInst) / sizeof(int));
@@ -384,74 +465,8 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh) {
       double dummy[9];
       sweep_update(I, 0, false, dummy, sh);
     }
-    // r = A_s v - b_s (FP64 accumulation)
-    double acc = 0;
-    {
-      const double* __restrict__ av = I.a_val64;
-      const int32_t* __restrict__ ac = I.a_col;
-      const float* __restrict__ v = I.v;
-      auto prod = [&](int k) -> double { return av[k] * double(v[ac[k]]); };
-      auto epi = [&](int i, double s) {
-        const float ri = float(s - I.bs[i]);
-        I.r[i] = ri;
-        acc += double(ri) * double(ri);
-      };
-      bsweep<double>(I, 0, prod, epi, sh);
-    }
-    double rho = bsum(acc, sh.red);
-    // x, z of this iteration set O at l + 1: project accurately
-    const bool feeds_event = in_sched(I, l + 1);
-    const double red2 = feeds_event ? fmin(I.cg_red2, kEventCgReduce * kEventCgReduce) : I.cg_red2;
-    const int cg_max = feeds_event ? I.cg_max * kEventCgMaxFactor : I.cg_max;
-    const double tol2 = fmax(red2 * rho, I.cg_abs2);
-    double beta = 0.0;
-    int k = 0;
-    bool bad = !(rho == rho) || isinf(rho);
-    while (!bad && k < cg_max && rho > tol2) {
-      acc = 0;
-      {
-        const float* __restrict__ tv = I.t_val;
-        const int32_t* __restrict__ tc = I.t_col;
-        const float* __restrict__ r = I.r;
-        const float vb = float(beta);
-        auto prod = [&](int kk) -> float { return tv[kk] * r[tc[kk]]; };
-        auto epi = [&](int j, float s) {
-          const float tj = (beta != 0.0) ? s + vb * I.t[j] : s;
-          I.t[j] = tj;
-          acc += double(tj) * double(tj);
-        };
-        bsweep<float>(I, 1, prod, epi, sh);
-      }
-      const double tt = bsum(acc, sh.red);
-      if (!(tt > 0.0) || isinf(tt)) {
-        bad = !(tt == tt);
-        break;
-      }
-      const double alpha = rho / tt;
-      acc = 0;
-      {
-        const float* __restrict__ av = I.a_val;
-        const int32_t* __restrict__ ac = I.a_col;
-        const float* __restrict__ t = I.t;
-        const float va = float(alpha), vb = float(beta);
-        auto prod = [&](int kk) -> float { return av[kk] * t[ac[kk]]; };
-        auto epi = [&](int i, float mq) {
-          const float ri = I.r[i];
-          const float qi = (beta != 0.0) ? ri + vb * I.q[i] : ri;
-          I.q[i] = qi;
-          I.w[i] += alpha * double(qi);
-          const float rn = ri - va * mq;
-          I.r[i] = rn;
-          acc += double(rn) * double(rn);
-        };
-        bsweep<float>(I, 0, prod, epi, sh);
-      }
-      const double rn = bsum(acc, sh.red);
-      bad = !(rn == rn) || isinf(rn);
-      beta = bad ? 0.0 : rn / rho;
-      rho = rn;
-      ++k;
-    }
+    bool bad = false;
+    const int k = (I.m + I.n <= lds_floats) ? project<true>(I, sh, lds, l, bad) : project<false>(I, sh, lds, l, bad);
     cgt += k;
     __syncthreads();
     const bool next_event = in_sched(I, l + 1);
@@ -527,17 +542,23 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kBB) void k_batch(BInst* inst, const int32_t* order, int count, unsigned int* queue,
-                                               int budget) {
+// 4 waves per SIMD (16 per CU, 4 workgroups): 128 registers, a few spilled to
+// scratch.  Unconstrained the kernel takes 169 registers, 2 workgroups per CU;
+// measured on the 4096-LP batch, 3 workgroups (168 registers) gave +23% and 4
+// a further +23% on the same box, with the stage at 1024 nonzeros so that 4
+// workgroups and the CG vectors fit the 160 KB of LDS.
+__global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(
+    BInst* inst, const int32_t* order, int count, unsigned int* queue, int budget, int lds_floats) {
   __shared__ Shared sh;
   __shared__ int idx;
+  extern __shared__ float vec_lds[];  // lds_floats: r and t of instances with m + n <= lds_floats
   for (;;) {
     if (threadIdx.x == 0) idx = int(atomicAdd(queue, 1u));
     __syncthreads();
     const int i = idx;
     __syncthreads();
     if (i >= count) return;
-    solve_one(&inst[order[i]], budget, sh);
+    solve_one(&inst[order[i]], budget, sh, vec_lds, lds_floats);
   }
 }
 
@@ -545,15 +566,16 @@ __global__ void k_queue_reset(unsigned int* queue) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
 }
 
-void launch_batch(BInst* inst, const int32_t* order, int32_t count, unsigned int* queue, int32_t grid, int32_t block,
-                  int32_t iter_budget, hipStream_t st) {
-  (void)block;
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBB), 0, st, inst, order, count, queue, iter_budget);
+void launch_batch(BInst* inst, const int32_t* order, int32_t count, unsigned int* queue, int32_t grid,
+                  int32_t lds_floats, int32_t iter_budget, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBB), size_t(lds_floats) * sizeof(float), st, inst, order, count, queue,
+                     iter_budget, lds_floats);
 }
 
-int batch_blocks_per_cu() {
+int batch_blocks_per_cu(int32_t lds_floats) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBB, 0) != hipSuccess) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBB, size_t(lds_floats) * sizeof(float)) != hipSuccess)
+    nb = 1;
   return nb > 0 ? nb : 1;
 }
 

@@ -16,6 +16,8 @@
 #include <sstream>
 #include <string>
 #include <vector>
+#include <cstdlib>
+#include <cstdio>
 
 #include "acs_batch.h"
 #include "acs_internal.h"
@@ -45,8 +47,8 @@ static int size_class(const Problem& p) {
 
 
 int default_lanes(double mean_row) { return pow2_at_least(mean_row, 1, 64); }
-Sched default_sched_a(const Problem&) { return Sched{1, 2048}; }
-Sched default_sched_t(const Problem&) { return Sched{1, 2048}; }
+Sched default_sched_a(const Problem&) { return Sched{1, 1024}; }
+Sched default_sched_t(const Problem&) { return Sched{1, 1024}; }
 
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -228,7 +230,7 @@ class Batch {
     settings_.resize(count);
     for (int i = 0; i < count; ++i) settings_[i] = resolve_settings(s, *probs_[i]);
     layout_and_upload();
-    // default schedules: LDS-staged row blocks of 2048 nonzeros
+    // default schedules: LDS-staged row blocks of 1024 nonzeros
     g_.resize(count);
     for (int i = 0; i < count; ++i) {
       g_[i].first = default_sched_a(*probs_[i]);
@@ -243,7 +245,12 @@ class Batch {
     hipDeviceProp_t prop;
     BHIP(hipGetDeviceProperties(&prop, 0));
     cus_ = prop.multiProcessorCount;
-    per_cu_ = batch_blocks_per_cu();
+    // LDS for the gathered CG vectors: enough for the largest instance that fits
+    for (const auto& p : probs_) {
+      const int64_t need = int64_t(p->m) + p->n;
+      if (need <= kBatchLdsMax) lds_floats_ = std::max<int32_t>(lds_floats_, int32_t(need));
+    }
+    per_cu_ = batch_blocks_per_cu(lds_floats_);
     reset_all();
   }
 
@@ -273,7 +280,7 @@ class Batch {
     } else {
       const int grid = std::max(1, std::min(count(), cus_ * per_cu_));
       launch_queue_reset(d_queue_, st_);
-      launch_batch(d_inst_, d_order_, count(), d_queue_, grid, 256, budget, st_);
+      launch_batch(d_inst_, d_order_, count(), d_queue_, grid, lds_floats_, budget, st_);
       BHIP(hipGetLastError());
     }
     BHIP(hipEventRecord(b, st_));
@@ -333,7 +340,7 @@ class Batch {
         const Problem& p0 = *probs_[pick[0]];
         auto candidates = [&](double mean_row) {
           const int g0 = default_lanes(mean_row);
-          std::vector<Sched> c = {Sched{1, 512}, Sched{1, 1024}, Sched{1, 2048}};
+          std::vector<Sched> c = {Sched{1, 512}, Sched{1, 1024}};
           for (int g : {std::max(1, g0 / 2), g0, std::min(64, g0 * 2)}) c.push_back(Sched{0, g});
           return c;
         };
@@ -403,7 +410,7 @@ class Batch {
     BHIP(hipEventCreate(&b));
     launch_queue_reset(d_queue_, st_);
     BHIP(hipEventRecord(a, st_));
-    launch_batch(d_inst_, d_ord, int(ord.size()), d_queue_, grid, 256, iters, st_);
+    launch_batch(d_inst_, d_ord, int(ord.size()), d_queue_, grid, lds_floats_, iters, st_);
     BHIP(hipGetLastError());
     BHIP(hipEventRecord(b, st_));
     BHIP(hipEventSynchronize(b));
@@ -483,7 +490,7 @@ class Batch {
     const int grid = std::max(1, std::min(count(), cus_ * per_cu_));
     BHIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     launch_queue_reset(d_queue_, st_);
-    launch_batch(d_inst_, d_order_, count(), d_queue_, grid, 256, budget, st_);
+    launch_batch(d_inst_, d_order_, count(), d_queue_, grid, lds_floats_, budget, st_);
     BHIP(hipStreamEndCapture(st_, &graph_));
     BHIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
     graph_budget_ = budget;
@@ -507,6 +514,7 @@ class Batch {
   hipGraphExec_t exec_ = nullptr;
   int graph_budget_ = -1;
   int cus_ = 256, per_cu_ = 1;
+  int32_t lds_floats_ = 0;
 
  public:
   double last_ms_ = 0;

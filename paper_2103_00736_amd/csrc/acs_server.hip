@@ -72,7 +72,7 @@ class Server {
     pool_.resize(max_slots_);
     hipDeviceProp_t prop;
     SHIP(hipGetDeviceProperties(&prop, 0));
-    grid_cap_ = prop.multiProcessorCount * batch_blocks_per_cu();
+    grid_cap_ = prop.multiProcessorCount * batch_blocks_per_cu(0);
     for (int w = 0; w < workers; ++w) {
       hipStream_t st;
       SHIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -273,7 +273,7 @@ class Server {
                         pool_stream_));
     const int grid = std::max(1, std::min(int(order.size()), grid_cap_));
     launch_queue_reset(d_queue_, pool_stream_);
-    launch_batch(d_inst_, d_order_, int(order.size()), d_queue_, grid, 256, tick_iters_, pool_stream_);
+    launch_batch(d_inst_, d_order_, int(order.size()), d_queue_, grid, 0, tick_iters_, pool_stream_);
     SHIP(hipGetLastError());
     SHIP(hipStreamSynchronize(pool_stream_));
     {

@@ -81,7 +81,7 @@ def test_autotune_and_cache(tmp_path):
     b = acs.Batch(handles, max_iter=5000)
     b.autotune(sample=2, iters=10, cache_path=cache)
     lanes = [b.lanes(i) for i in range(len(probs))]
-    assert all(g in (1, 2, 4, 8, 16, 32, 64, -512, -1024, -2048) for pair in lanes for g in pair)
+    assert all(g in (1, 2, 4, 8, 16, 32, 64, -512, -1024) for pair in lanes for g in pair)
     text = open(cache).read()
     assert text.startswith("gfx950")
     b.run(5000)
