@@ -92,6 +92,21 @@ class RangeProjector:
             raise RuntimeError(f"oracle PCG did not reach rtol={self.rtol} (info={info})")
         return w
 
+    def normal_pinv(self) -> np.ndarray:
+        """The m x m matrix (B B^T)^+ written out: on the rows of B that are not
+        all zero the inverse of their Gram matrix, zero on the empty rows (they
+        add nothing to range(B^T)).  Dense; for the exact method only."""
+        if self.method != "exact":
+            raise ValueError("normal_pinv needs the exact method")
+        X = np.zeros((self.m, self.m))
+        k = len(self.live)
+        if self._chol is not None:
+            inner = sla.cho_solve(self._chol, np.eye(k))
+        else:
+            inner = self._pinv
+        X[np.ix_(self.live, self.live)] = inner
+        return X
+
     def project(self, v: np.ndarray) -> np.ndarray:
         """proj_{range B^T}(v) = B^T (B B^T)^+ B v."""
         v = np.asarray(v, dtype=np.float64)

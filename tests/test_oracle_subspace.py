@@ -80,3 +80,38 @@ def test_paper_example_condition_numbers():
     # D A E with the printed Sinkhorn-Knopp factors (given to 3 significant figures)
     M = np.diag(g["D_SK"]) @ A.toarray() @ np.diag(g["E_SK"])
     assert abs(cond(M) - g["cond_A_SK"]) / g["cond_A_SK"] < 1e-3
+
+
+@pytest.mark.parametrize("empty_rows", [0, 4])
+def test_normal_pinv_penrose(empty_rows):
+    """(B B^T)^+ satisfies the four Penrose conditions for G = B B^T and is
+    zero on empty rows; on live rows it inverts G."""
+    A = _rand_sparse(25, 60, 0.2, 31, empty_rows)
+    O = np.exp(np.random.default_rng(7).uniform(-2, 2, 60))
+    P = RangeProjector(A, O, method="exact")
+    B = A.toarray() * O
+    G = B @ B.T
+    X = P.normal_pinv()
+    sc = np.abs(X).max() * np.abs(G).max()
+    assert np.abs(G @ X @ G - G).max() <= 1e-10 * np.abs(G).max()
+    assert np.abs(X @ G @ X - X).max() <= 1e-10 * np.abs(X).max() * sc
+    assert np.abs(X - X.T).max() <= 1e-12 * np.abs(X).max()
+    assert np.abs(G @ X - (G @ X).T).max() <= 1e-10 * sc
+    live = np.abs(B).sum(axis=1) > 0
+    assert not X[~live].any() and not X[:, ~live].any()
+    assert np.abs((G @ X)[np.ix_(live, live)] - np.eye(live.sum())).max() <= 1e-10 * sc
+
+
+def test_normal_pinv_closed_forms():
+    # rows with disjoint supports: G is diagonal, G_ii = sum_j a_ij^2 O_j^2
+    A = sp.csr_matrix(np.array([[1.0, 2.0, 0, 0], [0, 0, 3.0, 0], [0, 0, 0, 0]]))
+    O = np.array([0.5, 2.0, 1.0, 7.0])
+    X = RangeProjector(A, O, method="exact").normal_pinv()
+    assert np.allclose(X, np.diag([1 / (0.25 + 16.0), 1 / 9.0, 0.0]), rtol=1e-14, atol=0)
+    # two rows: the 2 x 2 inverse by its cofactor formula
+    A = sp.csr_matrix(np.array([[1.0, 1.0, 0.0], [1.0, -1.0, 2.0]]))
+    O = np.array([1.0, 3.0, 0.5])
+    g11, g12, g22 = 1 + 9, 1 - 9, 1 + 9 + 1
+    det = g11 * g22 - g12 * g12
+    want = np.array([[g22, -g12], [-g12, g11]]) / det
+    assert np.allclose(RangeProjector(A, O, method="exact").normal_pinv(), want, rtol=1e-13, atol=0)
