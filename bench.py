@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6  # MI355X dense FP64 (vector and MFMA)
 
 
 def parse():
@@ -43,6 +44,8 @@ def parse():
                          "persistent launch; serve: Poisson request stream through the serving loop")
     ap.add_argument("--count", type=int, default=4096, help="batch: number of instances")
     ap.add_argument("--dense-n", type=int, default=30000, help="dense: n of the paper's random LP (m = 0.8 n)")
+    ap.add_argument("--projection", choices=["cg", "factor"], default="cg",
+                    help="dense: projection by warm-started CG or by the inverse of A_s A_s^T (formed at events)")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (requests/s)")
     return ap.parse_args()
@@ -139,14 +142,14 @@ def kernel_bytes(m, n, nnz, vt=4, slices=8):
     return {"cg_a": cg_a, "cg_t": cg_t, "cg_comb": comb}
 
 
-def traffic_record(kernel, workload="lp2m"):
+def traffic_record(kernel, workload="lp2m", source="acs_kernels.hip"):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2103_00736_amd", "csrc", "acs_kernels.hip"), "rb").read()
+    src = open(os.path.join(ROOT, "paper_2103_00736_amd", "csrc", source), "rb").read()
     if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
@@ -170,6 +173,8 @@ def main():
         return bench_copy()
     if args.workload == "gather":
         return bench_gather()
+    if args.workload == "dense" and args.projection == "factor":
+        return bench_dense_factor(args, cpu_proc)
     if args.workload == "dense":
         return bench_dense(args, cpu_proc)
     if args.workload == "ablation":
@@ -390,6 +395,94 @@ def bench_dense(args, cpu_proc):
                    "kernel_ms": {k: {"count": v[0], "total_ms": round(v[1], 3)} for k, v in prof.items()},
                    "kernel_ms_what": "every kernel class timed in 3 further iterations",
                    "cg_t_bytes_per_launch": kb["cg_t"]},
+    }), flush=True)
+    return 0
+
+
+def bench_dense_factor(args, cpu_proc):
+    """Iterations/s on the dense LP at n = 30000 with the direct projection,
+    over iterations 251-350: one conditioning event (l = 300), so the window
+    carries one formation and inversion of A_s A_s^T (m = 24000) and 100
+    applications of its inverse, the schedule's share of factorization work.
+    The CG projection is timed over the same window for comparison."""
+    from paper_2103_00736_amd import acs, synth
+
+    t0 = time.perf_counter()
+    p = synth.e3_lp(args.dense_n)
+    gen_s = time.perf_counter() - t0
+    rc = acs.lib().acs_init(0)
+    if rc != 0:
+        raise RuntimeError(acs.lib().acs_last_error().decode())
+    prob = acs.Problem.from_synth(p)
+    del p.A
+    m, n = p.m, p.n
+    warmup, steps = 250, 100
+    fac_cls = {"syrk": acs.KC_FAC_SYRK, "sweep": acs.KC_FAC_SWEEP, "apply": acs.KC_FAC_APPLY}
+    rates = {}
+    for proj in ("factor", "cg"):
+        st = acs.State(prob, precision=acs.PREC_MIXED,
+                       projection=acs.PROJ_FACTOR if proj == "factor" else acs.PROJ_CG)
+        _progress(f"dense LP {m}x{n}, {proj} projection: warmup {warmup}")
+        st.step(warmup)
+        _progress(f"timed region: {steps} iterations (event at l = 300 inside)")
+        if proj == "factor":
+            st.profile(list(fac_cls.values()))
+        t1 = time.perf_counter()
+        st.step(steps)
+        t2 = time.perf_counter()
+        rates[proj] = steps / (t2 - t1)
+        if proj == "factor":
+            st.profile(False)
+            prof = {k: st.timing(v) for k, v in fac_cls.items()}
+            elapsed = t2 - t1
+            info = st.info()
+        st.close()
+    # algorithmic flops: the lower triangle of B B^T (m (m + 1) / 2 dot
+    # products of length n), the inversion of an m x m SPD matrix by the
+    # symmetric sweep (m rank-1 updates of a half matrix: m^3 flops); bytes
+    # of the apply: M^{-1} once (FP64) and the vectors
+    syrk_flops = m * (m + 1) * n
+    sweep_flops = m ** 3
+    apply_bytes = 8 * m * m + 8 * 3 * m
+    cnt_s, ms_s = prof["syrk"]
+    cnt_w, ms_w = prof["sweep"]
+    cnt_a, ms_a = prof["apply"]
+    syrk_tf = syrk_flops * cnt_s / (ms_s * 1e-3) / 1e12 if ms_s > 0 else 0.0
+    sweep_tf = sweep_flops * cnt_w / (ms_w * 1e-3) / 1e12 if ms_w > 0 else 0.0
+    apply_gbs = apply_bytes * cnt_a / (ms_a * 1e-3) / 1e9 if ms_a > 0 else 0.0
+    dom = max(("syrk", ms_s), ("sweep", ms_w), ("apply", ms_a), key=lambda kv: kv[1])[0]
+    if dom == "apply":
+        roof = {"bound": "hbm", "kernel": "k_fac_apply", "achieved": apply_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": apply_gbs / HBM_PEAK_GBS, "traffic": traffic_record("fac_apply", "dense_lp", "acs_factor.hip"),
+                "avg_launch_ms": ms_a / max(cnt_a, 1), "launches": cnt_a, "algorithmic_bytes_per_launch": apply_bytes}
+    elif dom == "syrk":
+        roof = {"bound": "mfma", "kernel": "k_fac_syrk (FP64 MFMA)", "achieved": syrk_tf, "peak": FP64_PEAK_TFS,
+                "unit": "TFLOP/s", "frac": syrk_tf / FP64_PEAK_TFS,
+                "traffic": traffic_record("fac_syrk", "dense_lp", "acs_factor.hip"),
+                "avg_launch_ms": ms_s / max(cnt_s, 1), "launches": cnt_s, "algorithmic_flops_per_launch": syrk_flops}
+    else:
+        roof = {"bound": "mfma", "kernel": "inversion sweep (k_fac_pivot, k_fac_panel, k_fac_update)",
+                "achieved": sweep_tf, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": sweep_tf / FP64_PEAK_TFS,
+                "traffic": None, "avg_launch_ms": ms_w / max(cnt_w, 1), "launches": cnt_w,
+                "algorithmic_flops_per_launch": sweep_flops}
+    cpu = finish_cpu_baseline(cpu_proc) if cpu_proc else None
+    print(json.dumps({
+        "metric": "iters/sec on the paper's dense random LP (Sec. V-B recipe), direct projection",
+        "value": steps / elapsed, "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"dense LP m={m} n={n}, A~U[-1,1] (FP32 storage), b=A|x|, c~N(0,1), t=9.2, "
+                               f"L={{300,400,...}}; iterations {warmup + 1}-{warmup + steps}",
+                   "precision": "A_s A_s^T and its inverse in FP64 (MFMA), FP64 residual and apply; "
+                                "FP32 iterate"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "detail": {"gen_s": gen_s, "cg_iters_per_s_same_window": rates["cg"],
+                   "speedup_vs_cg_same_window": rates["factor"] / rates["cg"],
+                   "syrk": {"count": cnt_s, "total_ms": ms_s, "tflops": syrk_tf},
+                   "sweep": {"count": cnt_w, "total_ms": ms_w, "tflops": sweep_tf},
+                   "apply": {"count": cnt_a, "total_ms": ms_a, "gbs": apply_gbs},
+                   "factor_info": {"iterations": info.iterations, "conditionings": info.conditionings}},
     }), flush=True)
     return 0
 

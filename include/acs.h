@@ -62,6 +62,16 @@ extern "C" {
                              reductions, scaling factors                   */
 #define ACS_PREC_FP64 1   /* everything in FP64                            */
 
+/* ---- projection of Alg. 2 step 17 (the paper does not say how (A O)^+ is
+ * applied; Sec. II defines it as a pseudo-inverse) ------------------------ */
+#define ACS_PROJ_CG 0      /* warm-started CG on (A_s A_s^T) w = rhs each iteration */
+#define ACS_PROJ_FACTOR 1  /* M = A_s A_s^T formed and inverted in FP64 at every
+                              conditioning event (M is fixed between events);
+                              each iteration then sets w += M^{-1} r, exact up to
+                              rounding.  Needs m <= 32768 and m * n <= 2^31;
+                              extra device memory: acs_problem_factor_bytes.
+                              Single-instance paths only (not the batch kernel). */
+
 /*
  * Settings (Alg. 2 Require line and Sec. V).  Call acs_settings_default()
  * first.  Conditioning set L = {l_first, l_first + l_every, ...} up to l_last
@@ -91,7 +101,8 @@ typedef struct acs_settings {
   double cg_reduce;     /* stop CG once ||r|| <= cg_reduce * ||r_0|| (warm)     */
   double cg_abs;        /* ... or once ||r|| <= cg_abs (scaled system)          */
   int32_t verbose;      /* 0 quiet, 1 one line per check on stderr              */
-  int32_t reserved[7];
+  int32_t projection;   /* ACS_PROJ_CG (default) or ACS_PROJ_FACTOR              */
+  int32_t reserved[6];
 } acs_settings;
 
 /* Per-solve report.  KKT errors follow the oracle's definition:
@@ -153,6 +164,10 @@ void acs_problem_destroy(acs_problem* p);
 /* Device bytes a one-instance solve of `p` in `precision` allocates (for
  * budgeting; includes the SELL layouts of the CG products).  Host code. */
 int64_t acs_problem_device_bytes(const acs_problem* p, int32_t precision);
+/* Device bytes the direct projection (ACS_PROJ_FACTOR) adds to that: M and
+ * the FP64 copy of A_s (padded to mp = m rounded up to 128 rows), the sweep
+ * panels.  -1 for a null problem.  Host code. */
+int64_t acs_problem_factor_bytes(const acs_problem* p);
 /* Device bytes `p` takes as one instance of a batch arena or a server pool
  * slot (the persistent kernel's layout); -1 for a dense problem, which the
  * batch does not take.  Host code. */
@@ -211,9 +226,20 @@ int acs_state_spmv(acs_state* st, int32_t which, const void* x, void* y, int32_t
  * (0 = update sweep k_update, 1 = residual sweep k_resid_part +
  * k_resid_comb, 2 = CG sweep k_cg_t, 3 = CG sliced sweep k_cg_a_part, 4 =
  * cone k_cone, 5 = check k_pres, 6 = conditioning, 7 = one-workgroup
- * finalizers, 8 = CG combine k_cg_a_comb). */
-#define ACS_PROF_ALL 0x1ff
+ * finalizers, 8 = CG combine k_cg_a_comb, 9 = direct projection: M = A_s A_s^T
+ * (k_fac_syrk), 10 = direct projection: inversion sweep (k_fac_pivot,
+ * k_fac_panel, k_fac_update, k_fac_mirror), 11 = direct projection:
+ * w += M^{-1} r (k_fac_apply)).  The direct projection's FP64 copy of A_s
+ * counts as conditioning (6). */
+#define ACS_PROF_ALL 0xfff
 int acs_state_profile(acs_state* st, int32_t enable);
+/* Direct projection only (ACS_PROJ_FACTOR): copies (A O^2 A^T)^+ as computed
+ * by the last factorization (for the state's current O) into `out`, a
+ * caller-owned host array of m * m doubles, row-major in the caller's row
+ * order; rows and columns of dependent (e.g. empty) rows of A are zero.
+ * ACS_ERR_STATE on a CG state or before the first factorization.  A test
+ * entry point: it copies m rows one by one. */
+int acs_state_normal_inverse(acs_state* st, double* out);
 int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_ms);
 
 /*

@@ -24,16 +24,18 @@ ACS_ERR_STATE = -5
 
 SOLVED, MAX_ITER, NUMERIC, CANCELLED = 0, 1, 2, 3
 PREC_MIXED, PREC_FP64 = 0, 1
+PROJ_CG, PROJ_FACTOR = 0, 1
 
 # timing classes of acs_state_timing
-KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG_COMB = range(9)
-PROF_ALL = (1 << 9) - 1  # ACS_PROF_ALL
+(KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG_COMB, KC_FAC_SYRK, KC_FAC_SWEEP,
+ KC_FAC_APPLY) = range(12)
+PROF_ALL = (1 << 12) - 1  # ACS_PROF_ALL
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
-    "acs_problem_destroy", "acs_problem_create_dense", "acs_problem_device_bytes", "acs_batch_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
+    "acs_problem_destroy", "acs_problem_create_dense", "acs_problem_device_bytes", "acs_problem_factor_bytes", "acs_batch_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
     "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
-    "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_batch_create", "acs_batch_destroy",
+    "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_state_normal_inverse", "acs_batch_create", "acs_batch_destroy",
     "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_lanes", "acs_batch_solve",
     "acs_server_create", "acs_server_destroy", "acs_server_submit", "acs_server_poll", "acs_server_wait",
     "acs_server_cancel", "acs_server_stats",
@@ -53,7 +55,7 @@ class Settings(ctypes.Structure):
         ("auto_params", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("eps_kkt", ctypes.c_double), ("precision", ctypes.c_int32), ("cg_max", ctypes.c_int32),
         ("cg_reduce", ctypes.c_double), ("cg_abs", ctypes.c_double), ("verbose", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("projection", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -112,6 +114,7 @@ def lib() -> ctypes.CDLL:
         "acs_problem_create_dense": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, DP, DP, DP, ctypes.c_int32,
                                                     ctypes.c_int32, I32P, ctypes.POINTER(P)]),
         "acs_problem_device_bytes": (ctypes.c_int64, [P, ctypes.c_int32]),
+        "acs_problem_factor_bytes": (ctypes.c_int64, [P]),
         "acs_batch_device_bytes": (ctypes.c_int64, [P]),
         "acs_solve": (ctypes.c_int, [P, ctypes.POINTER(Settings), DP, DP, DP, ctypes.POINTER(Info), P]),
         "acs_state_create": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, ctypes.POINTER(P)]),
@@ -125,6 +128,7 @@ def lib() -> ctypes.CDLL:
         "acs_state_spmv": (ctypes.c_int, [P, ctypes.c_int32, P, P, ctypes.c_int32, DP]),
         "acs_state_profile": (ctypes.c_int, [P, ctypes.c_int32]),
         "acs_state_timing": (ctypes.c_int, [P, ctypes.c_int32, I64P, DP]),
+        "acs_state_normal_inverse": (ctypes.c_int, [P, DP]),
         "acs_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(Settings), P,
                                             ctypes.POINTER(P)]),
         "acs_batch_destroy": (None, [P]),
@@ -234,6 +238,9 @@ class Problem:
     def device_bytes(self, precision: int = PREC_MIXED) -> int:
         return int(lib().acs_problem_device_bytes(self.handle, precision))
 
+    def factor_bytes(self) -> int:
+        return int(lib().acs_problem_factor_bytes(self.handle))
+
     def batch_device_bytes(self) -> int:
         return int(lib().acs_batch_device_bytes(self.handle))
 
@@ -308,6 +315,13 @@ class State:
             for k in classes:
                 mask |= 1 << int(k)
         _check(lib().acs_state_profile(self.handle, mask))
+
+    def normal_inverse(self) -> np.ndarray:
+        """(A O^2 A^T)^+ of the last factorization (direct projection only)."""
+        m = self.problem.m
+        out = np.empty((m, m))
+        _check(lib().acs_state_normal_inverse(self.handle, _dptr(out)))
+        return out
 
     def timing(self, cls: int) -> Tuple[int, float]:
         cnt = ctypes.c_int64()

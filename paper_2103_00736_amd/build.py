@@ -10,8 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libacs.so")
-SOURCES = ["acs_problem.cpp", "acs_kernels.hip", "acs_solver.hip", "acs_batch.hip", "acs_batch_host.hip",
-           "acs_server.hip"]
+SOURCES = ["acs_problem.cpp", "acs_kernels.hip", "acs_factor.hip", "acs_solver.hip", "acs_batch.hip",
+           "acs_batch_host.hip", "acs_server.hip"]
 ARCH = os.environ.get("ACS_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed FP32 instructions (see the design notes on gfx950 codegen)

@@ -131,6 +131,7 @@ __device__ __forceinline__ void bsweep(const BInst& I, int which, Prod& prod, Ep
       Acc s = 0;
       for (int k = k0 + tid; k < k1; k += kBB) s += prod(k);
       s = wsum(s);
+      __syncthreads();  // a preceding bsum may still be reading sh.red
       if ((tid & 63) == 0) sh.red[tid >> 6] = double(s);
       __syncthreads();
       if (tid == 0) {

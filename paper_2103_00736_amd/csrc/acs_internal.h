@@ -192,7 +192,7 @@ struct SolveOut {
 };
 SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream,
                             const InstanceResources& res = InstanceResources());
-int64_t instance_device_bytes(const Problem& p, int precision);
+int64_t instance_device_bytes(const Problem& p, int precision, int projection);
 
 template <class F>
 int guarded(F&& f) {

@@ -34,6 +34,19 @@ struct LaunchEvents {
 };
 LaunchEvents*& launch_events();  // thread-local slot, nullptr when not timing
 
+// hipLaunchKernelGGL, or the timed launch while a LaunchEvents slot is set
+#define ACS_LAUNCH(kernel, grid, block, shmem, stream, ...)                                          \
+  do {                                                                                                \
+    LaunchEvents* ev_ = launch_events();                                                              \
+    if (ev_) {                                                                                        \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_->launches == 0 ? ev_->start : nullptr, \
+                            ev_->stop, 0u, __VA_ARGS__);                                               \
+      ++ev_->launches;                                                                                \
+    } else {                                                                                          \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                            \
+    }                                                                                                 \
+  } while (0)
+
 // Device control block of one instance (CG scalars, reductions, flags).
 struct Ctl {
   double rho;     // ||r||^2 of the current CG residual
@@ -136,6 +149,7 @@ struct Dev {
   double* zt;  // chat + A_s^T w on SOC coordinates
   double* w;
   VT* r;
+  double* r64;  // FP64 copy of the residual for the direct projection, else nullptr
   VT* q;
   VT* t;
   // outputs
@@ -149,6 +163,25 @@ struct Dev {
   Ctl* ctl;
   double* partials;
   HostStatus* hs;
+};
+
+// Direct projection: the normal matrix M = A_s A_s^T of the current scaling,
+// formed and inverted in FP64 at each conditioning event; each iteration
+// then corrects w by M^{-1} r instead of running the CG.
+constexpr int kFacTile = 64;        // pivot block and tile of the inversion sweep
+constexpr int kFacPad = 128;        // the order of M is padded to a multiple of this
+constexpr int kFacMaxOrder = 32768; // largest padded order (8 GiB of FP64)
+constexpr double kFacPivotTol = 1e-11;  // pivots at or below it (unit-diagonal M) count as dependent rows
+
+struct FacDev {
+  int32_t m;    // rows of A
+  int32_t mp;   // padded order of M (multiple of kFacPad)
+  int32_t ldb;  // leading dimension of B (multiple of 64)
+  int32_t nb;   // pivot blocks swept: ceil(m / kFacTile)
+  double* S;    // mp x mp: M, then -M^{-1} (lower tiles) during the sweep, then M^{-1} (full)
+  double* B;    // mp x ldb: A_s in FP64, zero outside m x n
+  double* C;    // mp x kFacTile: W = Op L^{-T} of the current sweep step (Op the pivot-column panel)
+  double* P;    // kFacTile x kFacTile: L^{-1}, L the Cholesky factor of the current pivot block
 };
 
 enum UpdMode { UPD_PROLOGUE = 0, UPD_UPDATE = 1, UPD_UPDATE_ONLY = 2 };
@@ -178,5 +211,10 @@ template <typename VT> void launch_rescale(const Dev<VT>& d, int wmode, hipStrea
 // in the caller's row order
 template <typename VT> void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st);
 template <typename VT> void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st);
+// direct projection: B = A_s (copy), M = B B^T (syrk), M -> M^{-1} (sweep), w += M^{-1} r64 (apply)
+template <typename VT> void launch_fac_copy(const Dev<VT>& d, const FacDev& f, hipStream_t st);
+void launch_fac_syrk(const FacDev& f, hipStream_t st);
+void launch_fac_sweep(const FacDev& f, hipStream_t st);
+template <typename VT> void launch_fac_apply(const Dev<VT>& d, const FacDev& f, hipStream_t st);
 
 }  // namespace acs

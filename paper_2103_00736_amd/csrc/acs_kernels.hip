@@ -24,19 +24,6 @@ LaunchEvents*& launch_events() {
   return slot;
 }
 
-// hipLaunchKernelGGL, or the timed launch while a LaunchEvents slot is set
-#define ACS_LAUNCH(kernel, grid, block, shmem, stream, ...)                                          \
-  do {                                                                                                \
-    LaunchEvents* ev_ = launch_events();                                                              \
-    if (ev_) {                                                                                        \
-      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_->launches == 0 ? ev_->start : nullptr, \
-                            ev_->stop, 0u, __VA_ARGS__);                                               \
-      ++ev_->launches;                                                                                \
-    } else {                                                                                          \
-      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                            \
-    }                                                                                                 \
-  } while (0)
-
 // ----------------------------------------------------------------------------
 // helpers
 // ----------------------------------------------------------------------------
@@ -465,8 +452,10 @@ __global__ __launch_bounds__(kBlock) void k_resid_comb(Dev<VT> d) {
     double sum = d.part64[i];
 #pragma unroll
     for (int x = 1; x < kSlices; ++x) sum += d.part64[size_t(x) * m + i];
-    const VT ri = VT(sum - d.bs[i]);
+    const double r64 = sum - d.bs[i];
+    const VT ri = VT(r64);
     d.r[i] = ri;
+    if (d.r64) d.r64[i] = r64;
     acc[0] += double(ri) * double(ri);
   }
   block_store_partials<1>(acc, d.partials, blockIdx.x);
@@ -1121,8 +1110,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(Dev<VT> d, int aux, VT* _
         const int i = i0 + r;
         if (i >= d.m) break;
         if (KIND == DK_RESID) {
-          const VT ri = VT(d.dinv[i] * s[r] - d.bs[i]);
+          const double r64 = d.dinv[i] * s[r] - d.bs[i];
+          const VT ri = VT(r64);
           d.r[i] = ri;
+          if (d.r64) d.r64[i] = r64;
           acc[0] += double(ri) * double(ri);
         } else if (KIND == DK_PRES) {
           pres_row(d, i, d.dinv[i] * s[r], d.mu, acc);

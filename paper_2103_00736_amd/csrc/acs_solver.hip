@@ -75,6 +75,7 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
   if (!(s.mu > 0) || !(s.t > 0)) throw AcsError(ACS_ERR_ARG, "settings: mu and t must be > 0");
   if (s.max_iter < 0 || s.check_every < 1 || s.cg_max < 0) throw AcsError(ACS_ERR_ARG, "settings: bad counts");
   if (s.precision != ACS_PREC_MIXED && s.precision != ACS_PREC_FP64) throw AcsError(ACS_ERR_ARG, "settings: precision");
+  if (s.projection != ACS_PROJ_CG && s.projection != ACS_PROJ_FACTOR) throw AcsError(ACS_ERR_ARG, "settings: projection");
   return s;
 }
 
@@ -229,6 +230,28 @@ static void dense_chunks(const Problem& p, int32_t* rows, int32_t* chunks) {
   *chunks = int32_t((int64_t(p.m) + r - 1) / r);
 }
 
+// Direct projection sizes: padded order of M and leading dimension of B
+static void factor_shape(const Problem& p, int32_t* mp, int32_t* ldb) {
+  *mp = int32_t((int64_t(p.m) + kFacPad - 1) / kFacPad * kFacPad);
+  *ldb = p.dense ? p.ld : int32_t((int64_t(p.n) + 63) / 64 * 64);
+}
+
+static int64_t factor_bytes(const Problem& p) {
+  int32_t mp, ldb;
+  factor_shape(p, &mp, &ldb);
+  return 8 * (int64_t(mp) * mp + int64_t(mp) * ldb + int64_t(mp) * kFacTile + kFacTile * kFacTile + mp) + 5 * 256;
+}
+
+static void check_factor_fits(const Problem& p) {
+  int32_t mp, ldb;
+  factor_shape(p, &mp, &ldb);
+  if (int64_t(p.m) > kFacMaxOrder || mp > kFacMaxOrder)
+    throw AcsError(ACS_ERR_ARG, "direct projection: m = " + std::to_string(p.m) + " exceeds " +
+                                    std::to_string(kFacMaxOrder));
+  if (int64_t(mp) * ldb > (int64_t(1) << 31))
+    throw AcsError(ACS_ERR_ARG, "direct projection: the dense copy of A (m x n) exceeds 2^31 entries");
+}
+
 static int64_t estimate_bytes(const Problem& p, int precision) {
   const int64_t vt = precision == ACS_PREC_FP64 ? 8 : 4;
   const int64_t nnz = p.nnz, m = p.m, n = p.n;
@@ -270,11 +293,15 @@ class InstanceBase {
   virtual void profile(uint32_t mask) = 0;
   virtual void timing(int cls, int64_t* count, double* total_ms) = 0;
   virtual int current_l() const = 0;
+  virtual void normal_inverse(double* out) = 0;
   acs_info info{};
   acs_settings S{};
 };
 
-enum KClass { KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_FIN = 7, KC_CG_COMB = 8, KC_N = 9 };
+enum KClass {
+  KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_FIN = 7,
+  KC_CG_COMB = 8, KC_FAC_SYRK = 9, KC_FAC_SWEEP = 10, KC_FAC_APPLY = 11, KC_N = 12
+};
 
 template <typename VT>
 class Instance final : public InstanceBase {
@@ -407,6 +434,32 @@ class Instance final : public InstanceBase {
     HIP_CHECK(hipMemsetAsync(d.dx64, 0, sizeof(double) * p.ld, st_));
   }
 
+  // direct projection: M (mp x mp), the FP64 copy of A_s, the sweep panels
+  void setup_factor() {
+    const Problem& p = *P_;
+    check_factor_fits(p);
+    fac_ = true;
+    FacDev& f = f_;
+    f.m = p.m;
+    factor_shape(p, &f.mp, &f.ldb);
+    f.nb = (p.m + kFacTile - 1) / kFacTile;
+    f.S = arena_.alloc<double>(size_t(f.mp) * f.mp);
+    f.B = arena_.alloc<double>(size_t(f.mp) * f.ldb);
+    f.C = arena_.alloc<double>(size_t(f.mp) * kFacTile);
+    f.P = arena_.alloc<double>(kFacTile * kFacTile);
+    d_.r64 = arena_.alloc<double>(f.mp);
+    // entries of the residual beyond m stay zero
+    HIP_CHECK(hipMemsetAsync(d_.r64, 0, sizeof(double) * f.mp, st_));
+  }
+
+  // M = A_s A_s^T of the current scaling and its inverse
+  void factorize() {
+    timed(KC_COND, [&] { launch_fac_copy(d_, f_, st_); });
+    timed(KC_FAC_SYRK, [&] { launch_fac_syrk(f_, st_); });
+    timed(KC_FAC_SWEEP, [&] { launch_fac_sweep(f_, st_); });
+    factored_ = true;
+  }
+
   void setup_device() {
     const Problem& p = *P_;
     Dev<VT>& d = d_;
@@ -435,6 +488,7 @@ class Instance final : public InstanceBase {
       setup_dense(up);
     else
       setup_sparse(up);
+    if (S.projection == ACS_PROJ_FACTOR) setup_factor();
     d.soc_off = soc_off;
     d.b = b;
     d.c = c;
@@ -548,11 +602,13 @@ class Instance final : public InstanceBase {
     launch_rescale(d_, 2, st_);  // A_s, b_s, chat for O; w -> scaled
     check_launch();
     l_ = l;
+    factored_ = false;
     if (sched_.contains(l + 1)) {
       // the conditioning of iteration l+1 reads abs_K(s_prev) on the cones
       launch_cone(d_, s_prev_dev(), false, true, cone_group_, st_);
     } else {
       prologue();
+      if (fac_) factorize();
     }
     check_launch();
     HIP_CHECK(hipStreamSynchronize(st_));
@@ -579,6 +635,7 @@ class Instance final : public InstanceBase {
     });
     info.conditionings += 1;
     prologue();
+    if (fac_) factorize();
   }
 
   // ----------------------------------------------------------- profiling
@@ -743,8 +800,13 @@ class Instance final : public InstanceBase {
       const double r2 = next_event ? std::min(red2, kEventCgReduce * kEventCgReduce) : red2;
       const int cg_max = next_event ? S.cg_max * kEventCgMaxFactor : S.cg_max;
       timed(KC_RESID, [&] { launch_resid(d_, st_); });
-      timed(KC_FIN, [&] { launch_fin_resid(d_, l, r2, abs2, cg_max, st_); });
-      run_cg(l, cg_max);
+      if (fac_) {  // w += M^{-1} r
+        timed(KC_FIN, [&] { launch_fin_resid(d_, l, r2, abs2, 0, st_); });
+        timed(KC_FAC_APPLY, [&] { launch_fac_apply(d_, f_, st_); });
+      } else {
+        timed(KC_FIN, [&] { launch_fin_resid(d_, l, r2, abs2, cg_max, st_); });
+        run_cg(l, cg_max);
+      }
       bool check = (l % S.check_every == 0) || it == iters - 1;
       if (check && pending >= 0) {  // one check in flight at a time
         wait_for([&] { return hs_check() >= pending; });
@@ -785,6 +847,22 @@ class Instance final : public InstanceBase {
   }
 
   int current_l() const override { return l_; }
+
+  // (A O^2 A^T)^{-1} of the last factorization, m x m in the caller's row
+  // order: M^{-1} = diag(d)^{-1} (A O^2 A^T)^{-1} diag(d)^{-1}
+  void normal_inverse(double* out) override {
+    const Problem& p = *P_;
+    if (!fac_) throw AcsError(ACS_ERR_STATE, "the state does not use the direct projection");
+    if (!factored_) throw AcsError(ACS_ERR_STATE, "no factorization since the state was set");
+    HIP_CHECK(hipStreamSynchronize(st_));
+    std::vector<double> di(p.m), row(p.m);
+    HIP_CHECK(hipMemcpy(di.data(), d_.dinv, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+    for (int i = 0; i < p.m; ++i) {
+      HIP_CHECK(hipMemcpy(row.data(), f_.S + size_t(i) * f_.mp, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+      double* o = out + size_t(p.row_perm[i]) * p.m;
+      for (int j = 0; j < p.m; ++j) o[p.row_perm[j]] = (di[i] * di[j]) * row[j];  // symmetric rounding
+    }
+  }
 
   void check_now() override {
     if (!have_xyz_) throw AcsError(ACS_ERR_STATE, "no iteration has been run since the state was set");
@@ -855,6 +933,9 @@ class Instance final : public InstanceBase {
   bool have_xyz_ = false;
   int cone_group_ = 4;
   size_t nparts_ = 1;
+  bool fac_ = false;       // direct projection
+  bool factored_ = false;  // M^{-1} matches the current scaling
+  FacDev f_{};
   HostStatus* hs_ = nullptr;
   uint32_t prof_mask_ = 0;  // kernel classes timed with events
   std::vector<ProfEv> prof_pending_, prof_free_;
@@ -882,7 +963,9 @@ SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings
   return o;
 }
 
-int64_t instance_device_bytes(const Problem& p, int precision) { return estimate_bytes(p, precision); }
+int64_t instance_device_bytes(const Problem& p, int precision, int projection) {
+  return estimate_bytes(p, precision) + (projection == ACS_PROJ_FACTOR ? factor_bytes(p) : 0);
+}
 
 static int g_device = -1;
 static std::mutex g_init_mu;
@@ -1058,6 +1141,18 @@ int acs_state_profile(acs_state* st, int32_t enable) {
     if (!st) throw AcsError(ACS_ERR_ARG, "null state");
     st->inst->profile(uint32_t(enable));
   });
+}
+
+int acs_state_normal_inverse(acs_state* st, double* out) {
+  return guarded([&] {
+    if (!st || !out) throw AcsError(ACS_ERR_ARG, "null argument");
+    st->inst->normal_inverse(out);
+  });
+}
+
+int64_t acs_problem_factor_bytes(const acs_problem* p) {
+  if (!p) return -1;
+  return factor_bytes(*p->p);
 }
 
 int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_ms) {

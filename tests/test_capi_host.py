@@ -34,8 +34,9 @@ def test_library_exports_every_declared_symbol():
 def test_settings_defaults_and_layout():
     s = acs.default_settings()
     assert s.mu == 1.0 and s.t == 9.2 and s.l_first == 300 and s.l_every == 100 and s.auto_params == 1
-    assert s.eps_kkt == 1e-4 and s.precision == acs.PREC_MIXED
+    assert s.eps_kkt == 1e-4 and s.precision == acs.PREC_MIXED and s.projection == acs.PROJ_CG
     assert ctypes.sizeof(acs.Settings) == 104
+    assert acs.Settings.projection.offset == 76 and acs.Settings.reserved.offset == 80
     assert acs.version().startswith("acs")
 
 
@@ -102,3 +103,20 @@ def test_device_byte_estimates_are_host_code():
     # at least the matrix's indices and values in the SELL layouts of both products
     assert one >= 24 * p.nnz and fp64 >= 16 * p.nnz and pool >= 8 * p.nnz
     h.close()
+
+
+def test_factor_bytes():
+    """The direct projection's extra memory: M (mp x mp) and the FP64 copy of A
+    (mp x ldb) with mp = m rounded up to 128 and ldb = n rounded up to 64."""
+    p = synth.lp_uniform(200, 500, 2000, 4)
+    h = acs.Problem.from_synth(p)
+    mp, ldb = 256, 512
+    want = 8 * (mp * mp + mp * ldb + mp * 64 + 64 * 64 + mp)
+    assert want <= h.factor_bytes() <= want + 4096
+    h.close()
+    d = synth.e3_lp(300)  # dense: m = 240, leading dimension 320
+    hd = acs.Problem.from_synth(d)
+    mp, ldb = 256, 320
+    want = 8 * (mp * mp + mp * ldb + mp * 64 + 64 * 64 + mp)
+    assert want <= hd.factor_bytes() <= want + 4096
+    hd.close()

@@ -92,3 +92,41 @@ def test_autotune_and_cache(tmp_path):
     b2 = acs.Batch(handles, max_iter=5000)
     b2.autotune(sample=2, iters=10, cache_path=cache)  # served from the cache
     assert [b2.lanes(i) for i in range(len(probs))] == lanes
+
+
+def _long_row_lp():
+    """A planted LP whose row 0 and column 0 are longer than the batch kernel's
+    LDS stage (1024 nonzeros), so both sweeps take the whole-workgroup row path
+    right after a workgroup reduction."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(17)
+    m, n = 1200, 3000
+    A = np.where(rng.random((m, n)) < 0.004, rng.standard_normal((m, n)), 0.0)
+    A[0, :] = rng.standard_normal(n)
+    A[:, 0] = rng.standard_normal(m)
+    A = A.astype(np.float32).astype(np.float64)
+    x0 = np.where(rng.random(n) < 0.3, rng.random(n) + 0.1, 0.0)
+    z0 = np.where(x0 > 0, 0.0, rng.random(n) + 0.1)
+    y0 = rng.standard_normal(m)
+    C = sp.csr_matrix(A)
+    return C, A @ x0, A.T @ y0 + z0, float((A.T @ y0 + z0) @ x0)
+
+
+def test_batch_long_rows_after_reductions():
+    C, b, c, p_star = _long_row_lp()
+    m, n = C.shape
+    h = acs.Problem(m, n, C.indptr, C.indices, C.data, b, c, n)
+    small = [synth.config3(i, m=int(mm)) for i, mm in enumerate([80, 120])]
+    handles = [h] + [acs.Problem.from_synth(p) for p in small]
+    bt = acs.Batch(handles, eps_kkt=1e-4, max_iter=20000)
+    bt.run(20000)
+    x, y, z, info = bt.result(0)
+    rec = kkt_errors(C, b, c, n, np.zeros(0, np.int32), x, y, z)
+    print(f"long rows: status={info.status} it={info.iterations} oracle_kkt={rec['kkt']:.2e} pobj={rec['pobj']:.6f} "
+          f"p*={p_star:.6f}")
+    assert info.status == acs.SOLVED
+    assert rec["kkt"] <= 1.05e-4
+    assert abs(rec["pobj"] - p_star) <= 1e-3 * (1 + abs(p_star))
+    _, _, _, one = acs.solve(h, eps_kkt=1e-4)
+    assert abs(one.pobj - info.pobj) <= 1e-3 * (1 + abs(p_star))
