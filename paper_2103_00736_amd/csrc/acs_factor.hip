@@ -23,9 +23,10 @@
 //          empty) row and is skipped, which leaves zeros in its row and
 //          column: the result is then the inverse on the other rows, with
 //          the oracle's pseudo-inverse's projection.  The trailing update is
-//          a rank-64 FP64 MFMA product on the lower tiles.
+//          a rank-64 FP64 MFMA product on the lower 64 x 64 tiles.
 //   mirror S <- -S, both triangles.
 //   apply  w += S r64 (FP64 rows, HBM-bound).
+#include <algorithm>
 #include <cmath>
 
 #include "acs_kernels.h"
@@ -38,8 +39,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = kFacTile;     // 64
 constexpr int kSyrkTile = 128;   // output tile of the product B B^T
-constexpr int kSyrkK = 16;       // k-depth of one LDS stage
-constexpr int kSyrkLd = kSyrkK + 4;  // LDS row stride (doubles)
+constexpr int kSyrkK = 32;       // k-depth of one LDS stage
+constexpr int kSyrkLd = kSyrkK + 2;  // LDS row stride (doubles)
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -96,37 +97,45 @@ __global__ __launch_bounds__(kBlock) void k_fac_sparse_b(Dev<VT> d, FacDev f) {
   for (int k = d.a_rp[i] + threadIdx.x; k < d.a_rp[i + 1]; k += kBlock) row[d.a_col[k]] = d.a_val64[k];
 }
 
-// Lower 128 x 128 tiles of S = B B^T.  Four waves in 2 x 2, each owning a
-// 64 x 64 block as 4 x 4 MFMA tiles.  Stages of 16 columns of B go through
-// LDS, the next stage's loads in flight during the current one's MFMAs.  The
-// contraction index inside a stage is permuted (lane slot q of MFMA step s is
-// column 4 q + s) so that each lane reads 4 consecutive doubles per tile.
-__global__ __launch_bounds__(kBlock) void k_fac_syrk(FacDev f) {
+// Lower 128 x 128 tiles of S = B B^T (k = ldb columns of B).  Eight waves
+// in 2 x 4, each owning a 64 x 32 block as 4 x 2 MFMA tiles; stages of 32
+// columns go through LDS, the next stage's loads held in registers during
+// the current one's MFMAs.  At 128 registers a wave and 68 KB of LDS a
+// workgroup, two workgroups (4 waves a SIMD) share a CU; a 4-wave layout
+// with 64 x 64 blocks needs more than 256 registers a wave and runs one wave
+// a SIMD at 55% of this rate.  The contraction index inside each half stage
+// is permuted (lane slot q of MFMA step s is column 4 q + s) so that a lane
+// reads 4 consecutive doubles per tile; both operands use the same order.
+constexpr int kSyrkThreads = 512;
+
+__global__ __launch_bounds__(kSyrkThreads) void k_fac_syrk(FacDev f) {
+  const double* __restrict__ A = f.B;
+  const int lda = f.ldb, kdim = f.ldb;
   __shared__ double As[kSyrkTile * kSyrkLd];
   __shared__ double Bs[kSyrkTile * kSyrkLd];
-  int I, J;
-  tri_index(blockIdx.x, I, J);
+  const int tile = f.syrk_order[blockIdx.x];
+  if (tile < 0) return;
+  const int I = tile >> 16, J = tile & 0xffff;
   const int r0 = I * kSyrkTile, c0 = J * kSyrkTile;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
-  const double* __restrict__ Ag = f.B + size_t(r0) * f.ldb;
-  const double* __restrict__ Bg = f.B + size_t(c0) * f.ldb;
-  const int sr = tid >> 3, sc = (tid & 7) * 2;  // staging: rows sr + 32 q, columns sc, sc + 1
-  d4 acc[4][4];
+  const int wr = wave >> 2, wc = wave & 3, li = lane & 15, kq = lane >> 4;
+  const double* __restrict__ Ag = A + size_t(r0) * lda;
+  const double* __restrict__ Bg = A + size_t(c0) * lda;
+  const int sr = tid >> 4, sc = (tid & 15) * 2;  // staging: rows sr + 32 q, columns sc, sc + 1
+  d4 acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  // the next stage's loads, issued unconditionally (the last stage reloads
+  // its own columns) so that they stay in registers
   double2 pa[4], pb[4];
-  auto gload = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      pa[q] = *reinterpret_cast<const double2*>(Ag + size_t(sr + 32 * q) * f.ldb + k0 + sc);
-      pb[q] = *reinterpret_cast<const double2*>(Bg + size_t(sr + 32 * q) * f.ldb + k0 + sc);
-    }
-  };
-  gload(0);
-  for (int k0 = 0; k0 < f.ldb; k0 += kSyrkK) {
+  for (int q = 0; q < 4; ++q) {
+    pa[q] = *reinterpret_cast<const double2*>(Ag + size_t(sr + 32 * q) * lda + sc);
+    pb[q] = *reinterpret_cast<const double2*>(Bg + size_t(sr + 32 * q) * lda + sc);
+  }
+  for (int k0 = 0; k0 < kdim; k0 += kSyrkK) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -134,37 +143,48 @@ __global__ __launch_bounds__(kBlock) void k_fac_syrk(FacDev f) {
       *reinterpret_cast<double2*>(Bs + (sr + 32 * q) * kSyrkLd + sc) = pb[q];
     }
     __syncthreads();
-    if (k0 + kSyrkK < f.ldb) gload(k0 + kSyrkK);
-    double av[4][4], bv[4][4];
+    const int kn = (k0 + kSyrkK < kdim) ? k0 + kSyrkK : k0;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double* pa_ = As + (wr * 64 + t * 16 + li) * kSyrkLd + kq * 4;
-      const double* pb_ = Bs + (wc * 64 + t * 16 + li) * kSyrkLd + kq * 4;
-      const double2 a0 = *reinterpret_cast<const double2*>(pa_), a1 = *reinterpret_cast<const double2*>(pa_ + 2);
-      const double2 b0 = *reinterpret_cast<const double2*>(pb_), b1 = *reinterpret_cast<const double2*>(pb_ + 2);
-      av[t][0] = a0.x;
-      av[t][1] = a0.y;
-      av[t][2] = a1.x;
-      av[t][3] = a1.y;
-      bv[t][0] = b0.x;
-      bv[t][1] = b0.y;
-      bv[t][2] = b1.x;
-      bv[t][3] = b1.y;
+    for (int q = 0; q < 4; ++q) {
+      pa[q] = *reinterpret_cast<const double2*>(Ag + size_t(sr + 32 * q) * lda + kn + sc);
+      pb[q] = *reinterpret_cast<const double2*>(Bg + size_t(sr + 32 * q) * lda + kn + sc);
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int h = 0; h < kSyrkK / 16; ++h) {
+      double av[4][4], bv[2][4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int t = 0; t < 4; ++t) {
+        const double* pa_ = As + (wr * 64 + t * 16 + li) * kSyrkLd + h * 16 + kq * 4;
+        const double2 a0 = *reinterpret_cast<const double2*>(pa_), a1 = *reinterpret_cast<const double2*>(pa_ + 2);
+        av[t][0] = a0.x;
+        av[t][1] = a0.y;
+        av[t][2] = a1.x;
+        av[t][3] = a1.y;
+      }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mfma64(av[a][s], bv[b][s], acc[a][b]);
+      for (int t = 0; t < 2; ++t) {
+        const double* pb_ = Bs + (wc * 32 + t * 16 + li) * kSyrkLd + h * 16 + kq * 4;
+        const double2 b0 = *reinterpret_cast<const double2*>(pb_), b1 = *reinterpret_cast<const double2*>(pb_ + 2);
+        bv[t][0] = b0.x;
+        bv[t][1] = b0.y;
+        bv[t][2] = b1.x;
+        bv[t][3] = b1.y;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
+    }
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = r0 + wr * 64 + a * 16 + kq + 4 * v, col = c0 + wc * 64 + b * 16 + li;
+        const int row = r0 + wr * 64 + a * 16 + kq + 4 * v, col = c0 + wc * 32 + b * 16 + li;
         f.S[size_t(row) * f.mp + col] = acc[a][b][v];
       }
 }
@@ -173,19 +193,24 @@ __global__ __launch_bounds__(kBlock) void k_fac_syrk(FacDev f) {
 // sweep
 // ----------------------------------------------------------------------------
 // Pivot block K, P = S_KK (the Schur complement of the rows not yet swept,
-// positive semidefinite): Cholesky P = L L^T in LDS (a pivot at or below
-// kFacPivotTol is skipped: its column of L is zero), then L^{-1} by forward
-// substitution (zero rows and columns for skipped pivots).  Writes L^{-1} to
-// f.P and S_KK <- -P^{-1} = -L^{-T} L^{-1}.
+// positive semidefinite): right-looking Cholesky P = L L^T in LDS (a pivot at
+// or below kFacPivotTol is skipped: its column of L is zero), with the
+// forward substitution L X = I carried along in the same sweep (step j
+// finishes row j of X = L^{-1}; skipped pivots leave zero rows and columns).
+// Writes L^{-1} to f.P and S_KK <- -P^{-1} = -L^{-T} L^{-1}.
 __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
   __shared__ double P[kT][kT + 1];  // L in the lower triangle
-  __shared__ double X[kT][kT + 1];  // L^{-1}
+  __shared__ double X[kT][kT + 1];  // L^{-1}: forward substitution of L X = I, row by row with L
   __shared__ double rd[kT];         // 1 / L_jj, 0 for a skipped pivot
   const int tid = threadIdx.x;
   double* __restrict__ Skk = f.S + size_t(K) * kT * f.mp + size_t(K) * kT;
-  for (int e = tid; e < kT * kT; e += kBlock) P[e / kT][e % kT] = Skk[size_t(e / kT) * f.mp + e % kT];
+  for (int e = tid; e < kT * kT; e += kBlock) {
+    const int i = e / kT, k = e % kT;
+    P[i][k] = Skk[size_t(i) * f.mp + k];
+    X[i][k] = (i == k) ? 1.0 : 0.0;
+  }
   __syncthreads();
-  for (int j = 0; j < kT; ++j) {  // right-looking, lower triangle
+  for (int j = 0; j < kT; ++j) {
     if (tid == 0) {
       const double d = P[j][j];
       const bool ok = d > kFacPivotTol;
@@ -194,34 +219,44 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
       rd[j] = ok ? 1.0 / l : 0.0;
     }
     __syncthreads();
-    if (tid > j && tid < kT) P[tid][j] *= rd[j];
+    const double r = rd[j];
+    if (tid > j && tid < kT) P[tid][j] *= r;  // column j of L
+    if (tid < kT) X[j][tid] *= r;             // row j of L^{-1} is final
     __syncthreads();
-    for (int e = tid; e < kT * kT; e += kBlock) {
-      const int i = e / kT, k = e % kT;
-      if (k > j && i >= k) P[i][k] -= P[i][j] * P[k][j];
-    }
-    __syncthreads();
-  }
-  if (tid < kT) {  // column j of L^{-1}
-    const int j = tid;
-    for (int i = 0; i < kT; ++i) {
-      double x = 0.0;
-      if (i >= j && rd[i] != 0.0 && rd[j] != 0.0) {
-        double acc = (i == j) ? 1.0 : 0.0;
-        for (int t = j; t < i; ++t) acc -= P[i][t] * X[t][j];
-        x = acc * rd[i];
+    // rows i > j, one wave per row, a lane per column k <= i: X (nonzero for
+    // k <= j) and the trailing lower part of P (j < k <= i)
+    {
+      const int k = tid & 63;
+      for (int i = j + 1 + (tid >> 6); i < kT; i += kBlock / 64) {
+        const double lij = P[i][j];
+        if (k <= j)
+          X[i][k] -= lij * X[j][k];
+        else if (k <= i)
+          P[i][k] -= lij * P[k][j];
       }
-      X[i][j] = x;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < kT * kT; e += kBlock) {
-    const int a = e / kT, b = e % kT;
-    double acc = 0.0;
-    for (int t = a > b ? a : b; t < kT; ++t) acc += X[t][a] * X[t][b];
-    f.P[e] = X[a][b];
-    Skk[size_t(a) * f.mp + b] = -acc;
+  // S_KK = -L^{-T} L^{-1}, 4 x 4 blocks per thread; L^{-1} is lower triangular
+  const int a0 = (tid >> 4) * 4, b0 = (tid & 15) * 4;
+  double acc[4][4] = {};
+  for (int t = 0; t < kT; ++t) {
+    double xa[4], xb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xa[q] = X[t][a0 + q];
+      xb[q] = X[t][b0 + q];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] += xa[p] * xb[q];
   }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Skk[size_t(a0 + p) * f.mp + b0 + q] = -acc[p][q];
+  for (int e = tid; e < kT * kT; e += kBlock) f.P[e] = X[e / kT][e % kT];
 }
 
 // Panel of block K, one workgroup per other row block I: Op = S_IK (read
@@ -290,12 +325,20 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
   }
 }
 
-// Trailing update of block K on the lower tile (I, J), I, J != K:
-// S_IJ -= W_I W_J^T (= Op_I P^{-1} Op_J^T), rank 64.  Four waves in 2 x 2, each 32 x 32 (2 x 2
-// MFMA tiles); lane slot q of MFMA step (h, s) is column 16 q + 8 h + s.
+// Trailing update of block K on the lower 64 x 64 tile (I, J), I, J != K:
+// S_IJ -= W_I W_J^T (= Op_I P^{-1} Op_J^T), rank 64.  The step streams the
+// whole lower triangle of S once, so the tile's S values are loaded first
+// (their latency overlaps the staging of W_I and W_J in LDS and the MFMAs);
+// four waves in 2 x 2, each 32 x 32 (2 x 2 MFMA tiles); lane slot q of MFMA
+// step s in quarter h is column 16 h + 4 q + s.
+constexpr int kWLd = kT + 2;  // LDS row stride of the staged W blocks (doubles)
+
 __global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
-  int I, J;
-  tri_index(blockIdx.x, I, J);
+  __shared__ double Wi[kT * kWLd];
+  __shared__ double Wj[kT * kWLd];
+  const int tile = f.upd_order[blockIdx.x];
+  if (tile < 0) return;
+  const int I = tile >> 16, J = tile & 0xffff;
   if (I == K || J == K) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
@@ -306,38 +349,53 @@ __global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        sv[a][b][v] = St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li];
-  const double* __restrict__ Cg = f.C + size_t(I) * kT * kT;
-  const double* __restrict__ Og = f.C + size_t(J) * kT * kT;
+      for (int v = 0; v < 4; ++v) sv[a][b][v] = St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li];
+  const double* __restrict__ Wig = f.C + size_t(I) * kT * kT;
+  const double* __restrict__ Wjg = f.C + size_t(J) * kT * kT;
+  {
+    const int r = tid >> 5, c = (tid & 31) * 2;  // rows r + 8 q, columns c, c + 1
+    double2 xi[8], xj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      xi[q] = *reinterpret_cast<const double2*>(Wig + (r + 8 * q) * kT + c);
+      xj[q] = *reinterpret_cast<const double2*>(Wjg + (r + 8 * q) * kT + c);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      *reinterpret_cast<double2*>(Wi + (r + 8 * q) * kWLd + c) = xi[q];
+      *reinterpret_cast<double2*>(Wj + (r + 8 * q) * kWLd + c) = xj[q];
+    }
+  }
+  __syncthreads();
   d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    double av[2][8], bv[2][8];
+  for (int h = 0; h < 4; ++h) {
+    double av[2][4], bv[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      const double* pa = Cg + (wr * 32 + t * 16 + li) * kT + kq * 16 + h * 8;
-      const double* pb = Og + (wc * 32 + t * 16 + li) * kT + kq * 16 + h * 8;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double2 x = *reinterpret_cast<const double2*>(pa + 2 * u);
-        const double2 y = *reinterpret_cast<const double2*>(pb + 2 * u);
-        av[t][2 * u] = x.x;
-        av[t][2 * u + 1] = x.y;
-        bv[t][2 * u] = y.x;
-        bv[t][2 * u + 1] = y.y;
-      }
+      const double* pa = Wi + (wr * 32 + t * 16 + li) * kWLd + h * 16 + kq * 4;
+      const double* pb = Wj + (wc * 32 + t * 16 + li) * kWLd + h * 16 + kq * 4;
+      const double2 a0 = *reinterpret_cast<const double2*>(pa), a1 = *reinterpret_cast<const double2*>(pa + 2);
+      const double2 b0 = *reinterpret_cast<const double2*>(pb), b1 = *reinterpret_cast<const double2*>(pb + 2);
+      av[t][0] = a0.x;
+      av[t][1] = a0.y;
+      av[t][2] = a1.x;
+      av[t][3] = a1.y;
+      bv[t][0] = b0.x;
+      bv[t][1] = b0.y;
+      bv[t][2] = b1.x;
+      bv[t][3] = b1.y;
     }
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
+    for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s], bv[b][s], acc[a][b]);
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -427,18 +485,35 @@ void launch_fac_copy(const Dev<VT>& d, const FacDev& f, hipStream_t st) {
   }
 }
 
+std::vector<int32_t> fac_tile_order(int tiles) {
+  constexpr int kXcds = 8;
+  const int G = std::max(1, std::min(8, tiles / 8));  // small orders: squares small enough to spread
+  std::vector<std::vector<int32_t>> lists(kXcds);
+  int sq = 0;
+  for (int P = 0; P * G < tiles; ++P)
+    for (int Q = 0; Q <= P; ++Q, ++sq) {
+      std::vector<int32_t>& L = lists[sq % kXcds];
+      for (int I = P * G; I < std::min(tiles, P * G + G); ++I)
+        for (int J = Q * G; J < std::min(I + 1, Q * G + G); ++J) L.push_back((I << 16) | J);
+    }
+  size_t len = 0;
+  for (const auto& L : lists) len = std::max(len, L.size());
+  std::vector<int32_t> out(len * kXcds, -1);
+  for (int x = 0; x < kXcds; ++x)
+    for (size_t k = 0; k < lists[x].size(); ++k) out[k * kXcds + x] = lists[x][k];
+  return out;
+}
+
 void launch_fac_syrk(const FacDev& f, hipStream_t st) {
-  const int t = f.mp / kSyrkTile;
-  ACS_LAUNCH(k_fac_syrk, dim3(t * (t + 1) / 2), dim3(kBlock), 0, st, f);
+  ACS_LAUNCH(k_fac_syrk, dim3(f.syrk_blocks), dim3(kSyrkThreads), 0, st, f);
 }
 
 void launch_fac_sweep(const FacDev& f, hipStream_t st) {
-  const int tiles = f.nb * (f.nb + 1) / 2;
   for (int K = 0; K < f.nb; ++K) {
     ACS_LAUNCH(k_fac_pivot, dim3(1), dim3(kBlock), 0, st, f, K);
     if (f.nb > 1) {
       ACS_LAUNCH(k_fac_panel, dim3(f.nb - 1), dim3(kBlock), 0, st, f, K);
-      ACS_LAUNCH(k_fac_update, dim3(tiles), dim3(kBlock), 0, st, f, K);
+      ACS_LAUNCH(k_fac_update, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
     }
   }
   const int all = f.mp / kT;

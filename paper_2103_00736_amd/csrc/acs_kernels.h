@@ -17,6 +17,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "acs_internal.h"
 
 namespace acs {
@@ -182,7 +184,18 @@ struct FacDev {
   double* B;    // mp x ldb: A_s in FP64, zero outside m x n
   double* C;    // mp x kFacTile: W = Op L^{-T} of the current sweep step (Op the pivot-column panel)
   double* P;    // kFacTile x kFacTile: L^{-1}, L the Cholesky factor of the current pivot block
+  // workgroup -> tile tables (fac_tile_order) of the form step (128 x 128
+  // tiles of mp) and of the sweep's update (64 x 64 tiles of nb blocks)
+  const int32_t* syrk_order;
+  const int32_t* upd_order;
+  int32_t syrk_blocks, upd_blocks;
 };
+
+// Workgroup order over the lower-triangular tiles (I, J), J <= I < tiles:
+// squares of up to 8 x 8 tiles, each handed whole to one XCD (workgroup b runs on
+// XCD b % 8), so the 64 workgroups an XCD runs at once share 8 row and 8
+// column panels in its L2.  Entry (I << 16) | J, or -1 for an idle workgroup.
+std::vector<int32_t> fac_tile_order(int tiles);
 
 enum UpdMode { UPD_PROLOGUE = 0, UPD_UPDATE = 1, UPD_UPDATE_ONLY = 2 };
 

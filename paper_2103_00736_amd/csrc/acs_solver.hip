@@ -239,7 +239,9 @@ static void factor_shape(const Problem& p, int32_t* mp, int32_t* ldb) {
 static int64_t factor_bytes(const Problem& p) {
   int32_t mp, ldb;
   factor_shape(p, &mp, &ldb);
-  return 8 * (int64_t(mp) * mp + int64_t(mp) * ldb + int64_t(mp) * kFacTile + kFacTile * kFacTile + mp) + 5 * 256;
+  const int64_t orders = 4 * int64_t(fac_tile_order(mp / 128).size() + fac_tile_order((p.m + kFacTile - 1) / kFacTile).size());
+  return 8 * (int64_t(mp) * mp + int64_t(mp) * ldb + int64_t(mp) * kFacTile + kFacTile * kFacTile + mp) + orders +
+         7 * 256;
 }
 
 static void check_factor_fits(const Problem& p) {
@@ -447,6 +449,18 @@ class Instance final : public InstanceBase {
     f.B = arena_.alloc<double>(size_t(f.mp) * f.ldb);
     f.C = arena_.alloc<double>(size_t(f.mp) * kFacTile);
     f.P = arena_.alloc<double>(kFacTile * kFacTile);
+    {
+      const std::vector<int32_t> so = fac_tile_order(f.mp / 128), uo = fac_tile_order(f.nb);
+      int32_t* a = arena_.alloc<int32_t>(so.size());
+      int32_t* b = arena_.alloc<int32_t>(uo.size());
+      HIP_CHECK(hipMemcpyAsync(a, so.data(), 4 * so.size(), hipMemcpyHostToDevice, st_));
+      HIP_CHECK(hipMemcpyAsync(b, uo.data(), 4 * uo.size(), hipMemcpyHostToDevice, st_));
+      HIP_CHECK(hipStreamSynchronize(st_));
+      f.syrk_order = a;
+      f.upd_order = b;
+      f.syrk_blocks = int32_t(so.size());
+      f.upd_blocks = int32_t(uo.size());
+    }
     d_.r64 = arena_.alloc<double>(f.mp);
     // entries of the residual beyond m stay zero
     HIP_CHECK(hipMemsetAsync(d_.r64, 0, sizeof(double) * f.mp, st_));
