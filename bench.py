@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--dense-n", type=int, default=30000, help="dense: n of the paper's random LP (m = 0.8 n)")
     ap.add_argument("--projection", choices=["cg", "factor"], default="cg",
                     help="dense: projection by warm-started CG or by the inverse of A_s A_s^T (formed at events)")
+    ap.add_argument("--skip-cg-compare", action="store_true",
+                    help="dense --projection factor: do not also time the CG projection over the same window")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (requests/s)")
     return ap.parse_args()
@@ -417,9 +419,10 @@ def bench_dense_factor(args, cpu_proc):
     del p.A
     m, n = p.m, p.n
     warmup, steps = 250, 100
-    fac_cls = {"syrk": acs.KC_FAC_SYRK, "sweep": acs.KC_FAC_SWEEP, "apply": acs.KC_FAC_APPLY}
-    rates = {}
-    for proj in ("factor", "cg"):
+    fac_cls = {"syrk": acs.KC_FAC_SYRK, "update": acs.KC_FAC_UPDATE, "apply": acs.KC_FAC_APPLY,
+               "panel": acs.KC_FAC_PANEL}
+    rates = {"cg": None}
+    for proj in (("factor",) if args.skip_cg_compare else ("factor", "cg")):
         st = acs.State(prob, precision=acs.PREC_MIXED,
                        projection=acs.PROJ_FACTOR if proj == "factor" else acs.PROJ_CG)
         _progress(f"dense LP {m}x{n}, {proj} projection: warmup {warmup}")
@@ -437,20 +440,29 @@ def bench_dense_factor(args, cpu_proc):
             elapsed = t2 - t1
             info = st.info()
         st.close()
-    # algorithmic flops: the lower triangle of B B^T (m (m + 1) / 2 dot
-    # products of length n), the inversion of an m x m SPD matrix by the
-    # symmetric sweep (m rank-1 updates of a half matrix: m^3 flops); bytes
-    # of the apply: M^{-1} once (FP64) and the vectors
+    # Algorithmic work per launch:
+    #   k_fac_syrk: the lower triangle of B B^T, m (m + 1) / 2 dot products of
+    #     length n: m (m + 1) n flops;
+    #   k_fac_update (one sweep step, rank 64): every lower 64 x 64 tile of S
+    #     outside the pivot block's row and column read and written once
+    #     (16 bytes an entry) and the 64-column panel W read once; 2 * 64
+    #     flops an entry;
+    #   k_fac_apply: M^{-1} once (FP64) and three m-vectors.
+    nb = (m + 63) // 64
+    upd_tiles = nb * (nb + 1) // 2 - nb
+    upd_bytes = 16 * 64 * 64 * upd_tiles + 8 * 64 * 64 * nb
+    upd_flops = 2 * 64 * 64 * 64 * upd_tiles
     syrk_flops = m * (m + 1) * n
-    sweep_flops = m ** 3
     apply_bytes = 8 * m * m + 8 * 3 * m
     cnt_s, ms_s = prof["syrk"]
-    cnt_w, ms_w = prof["sweep"]
+    cnt_u, ms_u = prof["update"]
     cnt_a, ms_a = prof["apply"]
+    cnt_p, ms_p = prof["panel"]
     syrk_tf = syrk_flops * cnt_s / (ms_s * 1e-3) / 1e12 if ms_s > 0 else 0.0
-    sweep_tf = sweep_flops * cnt_w / (ms_w * 1e-3) / 1e12 if ms_w > 0 else 0.0
+    upd_gbs = upd_bytes * cnt_u / (ms_u * 1e-3) / 1e9 if ms_u > 0 else 0.0
+    upd_tf = upd_flops * cnt_u / (ms_u * 1e-3) / 1e12 if ms_u > 0 else 0.0
     apply_gbs = apply_bytes * cnt_a / (ms_a * 1e-3) / 1e9 if ms_a > 0 else 0.0
-    dom = max(("syrk", ms_s), ("sweep", ms_w), ("apply", ms_a), key=lambda kv: kv[1])[0]
+    dom = max(("syrk", ms_s), ("update", ms_u), ("apply", ms_a), key=lambda kv: kv[1])[0]
     if dom == "apply":
         roof = {"bound": "hbm", "kernel": "k_fac_apply", "achieved": apply_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": apply_gbs / HBM_PEAK_GBS, "traffic": traffic_record("fac_apply", "dense_lp", "acs_factor.hip"),
@@ -460,11 +472,12 @@ def bench_dense_factor(args, cpu_proc):
                 "unit": "TFLOP/s", "frac": syrk_tf / FP64_PEAK_TFS,
                 "traffic": traffic_record("fac_syrk", "dense_lp", "acs_factor.hip"),
                 "avg_launch_ms": ms_s / max(cnt_s, 1), "launches": cnt_s, "algorithmic_flops_per_launch": syrk_flops}
-    else:
-        roof = {"bound": "mfma", "kernel": "inversion sweep (k_fac_pivot, k_fac_panel, k_fac_update)",
-                "achieved": sweep_tf, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": sweep_tf / FP64_PEAK_TFS,
-                "traffic": None, "avg_launch_ms": ms_w / max(cnt_w, 1), "launches": cnt_w,
-                "algorithmic_flops_per_launch": sweep_flops}
+    else:  # the rank-64 step streams S once: HBM-bound (its flops would take 0.8x as long at the MFMA peak)
+        roof = {"bound": "hbm", "kernel": "k_fac_update (rank-64 sweep step)", "achieved": upd_gbs,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": upd_gbs / HBM_PEAK_GBS,
+                "traffic": traffic_record("fac_update", "dense_lp", "acs_factor.hip"),
+                "avg_launch_ms": ms_u / max(cnt_u, 1), "launches": cnt_u, "algorithmic_bytes_per_launch": upd_bytes,
+                "fp64_tflops": upd_tf}
     cpu = finish_cpu_baseline(cpu_proc) if cpu_proc else None
     print(json.dumps({
         "metric": "iters/sec on the paper's dense random LP (Sec. V-B recipe), direct projection",
@@ -478,10 +491,12 @@ def bench_dense_factor(args, cpu_proc):
         "roofline": roof,
         "cpu_baseline": cpu,
         "detail": {"gen_s": gen_s, "cg_iters_per_s_same_window": rates["cg"],
-                   "speedup_vs_cg_same_window": rates["factor"] / rates["cg"],
+                   "speedup_vs_cg_same_window": rates["factor"] / rates["cg"] if rates["cg"] else None,
                    "syrk": {"count": cnt_s, "total_ms": ms_s, "tflops": syrk_tf},
-                   "sweep": {"count": cnt_w, "total_ms": ms_w, "tflops": sweep_tf},
+                   "update": {"count": cnt_u, "total_ms": ms_u, "gbs": upd_gbs, "tflops": upd_tf},
+                   "pivot_panel_mirror": {"count": cnt_p, "total_ms": ms_p},
                    "apply": {"count": cnt_a, "total_ms": ms_a, "gbs": apply_gbs},
+                   "event_ms": ms_s + ms_u + ms_p,
                    "factor_info": {"iterations": info.iterations, "conditionings": info.conditionings}},
     }), flush=True)
     return 0

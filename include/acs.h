@@ -226,12 +226,12 @@ int acs_state_spmv(acs_state* st, int32_t which, const void* x, void* y, int32_t
  * (0 = update sweep k_update, 1 = residual sweep k_resid_part +
  * k_resid_comb, 2 = CG sweep k_cg_t, 3 = CG sliced sweep k_cg_a_part, 4 =
  * cone k_cone, 5 = check k_pres, 6 = conditioning, 7 = one-workgroup
- * finalizers, 8 = CG combine k_cg_a_comb, 9 = direct projection: M = A_s A_s^T
- * (k_fac_syrk), 10 = direct projection: inversion sweep (k_fac_pivot,
- * k_fac_panel, k_fac_update, k_fac_mirror), 11 = direct projection:
- * w += M^{-1} r (k_fac_apply)).  The direct projection's FP64 copy of A_s
- * counts as conditioning (6). */
-#define ACS_PROF_ALL 0xfff
+ * finalizers, 8 = CG combine k_cg_a_comb; direct projection: 9 = M = A_s A_s^T
+ * (k_fac_syrk), 10 = the inversion sweep's rank-64 updates (k_fac_update),
+ * 11 = w += M^{-1} r (k_fac_apply), 12 = the sweep's pivot blocks and panels
+ * (k_fac_pivot, k_fac_panel, k_fac_mirror)).  The direct projection's FP64
+ * copy of A_s counts as conditioning (6). */
+#define ACS_PROF_ALL 0x1fff
 int acs_state_profile(acs_state* st, int32_t enable);
 /* Direct projection only (ACS_PROJ_FACTOR): copies (A O^2 A^T)^+ as computed
  * by the last factorization (for the state's current O) into `out`, a

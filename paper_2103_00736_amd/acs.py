@@ -27,9 +27,9 @@ PREC_MIXED, PREC_FP64 = 0, 1
 PROJ_CG, PROJ_FACTOR = 0, 1
 
 # timing classes of acs_state_timing
-(KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG_COMB, KC_FAC_SYRK, KC_FAC_SWEEP,
- KC_FAC_APPLY) = range(12)
-PROF_ALL = (1 << 12) - 1  # ACS_PROF_ALL
+(KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG_COMB, KC_FAC_SYRK, KC_FAC_UPDATE,
+ KC_FAC_APPLY, KC_FAC_PANEL) = range(13)
+PROF_ALL = (1 << 13) - 1  # ACS_PROF_ALL
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",

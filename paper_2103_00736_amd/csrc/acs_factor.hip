@@ -100,15 +100,18 @@ __global__ __launch_bounds__(kBlock) void k_fac_sparse_b(Dev<VT> d, FacDev f) {
 // Lower 128 x 128 tiles of S = B B^T (k = ldb columns of B).  Eight waves
 // in 2 x 4, each owning a 64 x 32 block as 4 x 2 MFMA tiles; stages of 32
 // columns go through LDS, the next stage's loads held in registers during
-// the current one's MFMAs.  At 128 registers a wave and 68 KB of LDS a
-// workgroup, two workgroups (4 waves a SIMD) share a CU; a 4-wave layout
-// with 64 x 64 blocks needs more than 256 registers a wave and runs one wave
-// a SIMD at 55% of this rate.  The contraction index inside each half stage
-// is permuted (lane slot q of MFMA step s is column 4 q + s) so that a lane
-// reads 4 consecutive doubles per tile; both operands use the same order.
+// the current one's MFMAs.  Register budget: 128 a wave, so that two
+// workgroups (4 waves a SIMD, with 68 KB of LDS each) share a CU with the
+// prefetch in registers.  That is why each MFMA step reads its six operands
+// from LDS just before use instead of holding a half stage of them (that
+// layout needs about 150 registers: at 4 waves a SIMD the compiler moves
+// the prefetch to scratch memory, at 2 waves a SIMD it runs 15% slower; the
+// 4-wave, 64 x 64-block layout runs 55% slower).  The contraction index is
+// permuted (lane slot q of MFMA step s is column 16 (s / 4) + 4 q + s % 4);
+// both operands use the same order.
 constexpr int kSyrkThreads = 512;
 
-__global__ __launch_bounds__(kSyrkThreads) void k_fac_syrk(FacDev f) {
+__global__ __launch_bounds__(kSyrkThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_fac_syrk(FacDev f) {
   const double* __restrict__ A = f.B;
   const int lda = f.ldb, kdim = f.ldb;
   __shared__ double As[kSyrkTile * kSyrkLd];
@@ -128,54 +131,46 @@ __global__ __launch_bounds__(kSyrkThreads) void k_fac_syrk(FacDev f) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   // the next stage's loads, issued unconditionally (the last stage reloads
-  // its own columns) so that they stay in registers
-  double2 pa[4], pb[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    pa[q] = *reinterpret_cast<const double2*>(Ag + size_t(sr + 32 * q) * lda + sc);
-    pb[q] = *reinterpret_cast<const double2*>(Bg + size_t(sr + 32 * q) * lda + sc);
-  }
+  // its own columns).  Eight named registers: written as arrays, the
+  // compiler keeps them in scratch memory.
+  auto ld = [&](const double* g, int row, int k) {
+    return *reinterpret_cast<const double2*>(g + size_t(row) * lda + k + sc);
+  };
+  auto st = [&](double* l, int row, double2 v) { *reinterpret_cast<double2*>(l + row * kSyrkLd + sc) = v; };
+  double2 pa0 = ld(Ag, sr, 0), pa1 = ld(Ag, sr + 32, 0), pa2 = ld(Ag, sr + 64, 0), pa3 = ld(Ag, sr + 96, 0);
+  double2 pb0 = ld(Bg, sr, 0), pb1 = ld(Bg, sr + 32, 0), pb2 = ld(Bg, sr + 64, 0), pb3 = ld(Bg, sr + 96, 0);
   for (int k0 = 0; k0 < kdim; k0 += kSyrkK) {
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<double2*>(As + (sr + 32 * q) * kSyrkLd + sc) = pa[q];
-      *reinterpret_cast<double2*>(Bs + (sr + 32 * q) * kSyrkLd + sc) = pb[q];
-    }
+    st(As, sr, pa0);
+    st(As, sr + 32, pa1);
+    st(As, sr + 64, pa2);
+    st(As, sr + 96, pa3);
+    st(Bs, sr, pb0);
+    st(Bs, sr + 32, pb1);
+    st(Bs, sr + 64, pb2);
+    st(Bs, sr + 96, pb3);
     __syncthreads();
     const int kn = (k0 + kSyrkK < kdim) ? k0 + kSyrkK : k0;
+    pa0 = ld(Ag, sr, kn);
+    pa1 = ld(Ag, sr + 32, kn);
+    pa2 = ld(Ag, sr + 64, kn);
+    pa3 = ld(Ag, sr + 96, kn);
+    pb0 = ld(Bg, sr, kn);
+    pb1 = ld(Bg, sr + 32, kn);
+    pb2 = ld(Bg, sr + 64, kn);
+    pb3 = ld(Bg, sr + 96, kn);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      pa[q] = *reinterpret_cast<const double2*>(Ag + size_t(sr + 32 * q) * lda + kn + sc);
-      pb[q] = *reinterpret_cast<const double2*>(Bg + size_t(sr + 32 * q) * lda + kn + sc);
-    }
+    for (int s = 0; s < kSyrkK / 4; ++s) {
+      const int col = 16 * (s >> 2) + 4 * kq + (s & 3);
+      double av[4], bv[2];
 #pragma unroll
-    for (int h = 0; h < kSyrkK / 16; ++h) {
-      double av[4][4], bv[2][4];
+      for (int t = 0; t < 4; ++t) av[t] = As[(wr * 64 + t * 16 + li) * kSyrkLd + col];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const double* pa_ = As + (wr * 64 + t * 16 + li) * kSyrkLd + h * 16 + kq * 4;
-        const double2 a0 = *reinterpret_cast<const double2*>(pa_), a1 = *reinterpret_cast<const double2*>(pa_ + 2);
-        av[t][0] = a0.x;
-        av[t][1] = a0.y;
-        av[t][2] = a1.x;
-        av[t][3] = a1.y;
-      }
+      for (int t = 0; t < 2; ++t) bv[t] = Bs[(wc * 32 + t * 16 + li) * kSyrkLd + col];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const double* pb_ = Bs + (wc * 32 + t * 16 + li) * kSyrkLd + h * 16 + kq * 4;
-        const double2 b0 = *reinterpret_cast<const double2*>(pb_), b1 = *reinterpret_cast<const double2*>(pb_ + 2);
-        bv[t][0] = b0.x;
-        bv[t][1] = b0.y;
-        bv[t][2] = b1.x;
-        bv[t][3] = b1.y;
-      }
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
     }
   }
 #pragma unroll
@@ -508,14 +503,16 @@ void launch_fac_syrk(const FacDev& f, hipStream_t st) {
   ACS_LAUNCH(k_fac_syrk, dim3(f.syrk_blocks), dim3(kSyrkThreads), 0, st, f);
 }
 
-void launch_fac_sweep(const FacDev& f, hipStream_t st) {
-  for (int K = 0; K < f.nb; ++K) {
-    ACS_LAUNCH(k_fac_pivot, dim3(1), dim3(kBlock), 0, st, f, K);
-    if (f.nb > 1) {
-      ACS_LAUNCH(k_fac_panel, dim3(f.nb - 1), dim3(kBlock), 0, st, f, K);
-      ACS_LAUNCH(k_fac_update, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
-    }
-  }
+void launch_fac_pivot_panel(const FacDev& f, int K, hipStream_t st) {
+  ACS_LAUNCH(k_fac_pivot, dim3(1), dim3(kBlock), 0, st, f, K);
+  if (f.nb > 1) ACS_LAUNCH(k_fac_panel, dim3(f.nb - 1), dim3(kBlock), 0, st, f, K);
+}
+
+void launch_fac_update(const FacDev& f, int K, hipStream_t st) {
+  if (f.nb > 1) ACS_LAUNCH(k_fac_update, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
+}
+
+void launch_fac_mirror(const FacDev& f, hipStream_t st) {
   const int all = f.mp / kT;
   ACS_LAUNCH(k_fac_mirror, dim3(all * (all + 1) / 2), dim3(kBlock), 0, st, f);
 }

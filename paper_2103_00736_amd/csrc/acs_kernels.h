@@ -224,10 +224,14 @@ template <typename VT> void launch_rescale(const Dev<VT>& d, int wmode, hipStrea
 // in the caller's row order
 template <typename VT> void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st);
 template <typename VT> void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st);
-// direct projection: B = A_s (copy), M = B B^T (syrk), M -> M^{-1} (sweep), w += M^{-1} r64 (apply)
+// direct projection: B = A_s (copy), M = B B^T (syrk), M -> M^{-1} (the
+// sweep: for K = 0..nb-1 pivot_panel(K) then update(K); then mirror),
+// w += M^{-1} r64 (apply)
 template <typename VT> void launch_fac_copy(const Dev<VT>& d, const FacDev& f, hipStream_t st);
 void launch_fac_syrk(const FacDev& f, hipStream_t st);
-void launch_fac_sweep(const FacDev& f, hipStream_t st);
+void launch_fac_pivot_panel(const FacDev& f, int K, hipStream_t st);
+void launch_fac_update(const FacDev& f, int K, hipStream_t st);
+void launch_fac_mirror(const FacDev& f, hipStream_t st);
 template <typename VT> void launch_fac_apply(const Dev<VT>& d, const FacDev& f, hipStream_t st);
 
 }  // namespace acs

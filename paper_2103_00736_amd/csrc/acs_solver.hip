@@ -302,7 +302,7 @@ class InstanceBase {
 
 enum KClass {
   KC_UPDATE = 0, KC_RESID = 1, KC_CG_T = 2, KC_CG_A = 3, KC_CONE = 4, KC_CHECK = 5, KC_COND = 6, KC_FIN = 7,
-  KC_CG_COMB = 8, KC_FAC_SYRK = 9, KC_FAC_SWEEP = 10, KC_FAC_APPLY = 11, KC_N = 12
+  KC_CG_COMB = 8, KC_FAC_SYRK = 9, KC_FAC_UPDATE = 10, KC_FAC_APPLY = 11, KC_FAC_PANEL = 12, KC_N = 13
 };
 
 template <typename VT>
@@ -470,7 +470,11 @@ class Instance final : public InstanceBase {
   void factorize() {
     timed(KC_COND, [&] { launch_fac_copy(d_, f_, st_); });
     timed(KC_FAC_SYRK, [&] { launch_fac_syrk(f_, st_); });
-    timed(KC_FAC_SWEEP, [&] { launch_fac_sweep(f_, st_); });
+    for (int K = 0; K < f_.nb; ++K) {
+      timed(KC_FAC_PANEL, [&] { launch_fac_pivot_panel(f_, K, st_); });
+      timed(KC_FAC_UPDATE, [&] { launch_fac_update(f_, K, st_); });
+    }
+    timed(KC_FAC_PANEL, [&] { launch_fac_mirror(f_, st_); });
     factored_ = true;
   }
 
