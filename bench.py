@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy", "gather", "dense", "ablation"],
+    ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy", "gather", "dense", "dense_solve",
+                                           "ablation"],
                     default="lp2m",
                     help="lp2m: iterations/s on the 2M-variable LP (default); batch: 4096 small LPs in one "
                          "persistent launch; serve: Poisson request stream through the serving loop")
@@ -175,6 +176,8 @@ def main():
         return bench_copy()
     if args.workload == "gather":
         return bench_gather()
+    if args.workload == "dense_solve":
+        return bench_dense_solve(args)
     if args.workload == "dense" and args.projection == "factor":
         return bench_dense_factor(args, cpu_proc)
     if args.workload == "dense":
@@ -499,6 +502,36 @@ def bench_dense_factor(args, cpu_proc):
                    "event_ms": ms_s + ms_u + ms_p,
                    "factor_info": {"iterations": info.iterations, "conditionings": info.conditionings}},
     }), flush=True)
+    return 0
+
+
+def bench_dense_solve(args):
+    """Whole solves of the dense LP (n = 30000, m = 24000) to 1e-4 KKT in mixed
+    precision, with the direct projection and with the CG projection: wall
+    time of the iteration loop, iterations, conditioning events, KKT."""
+    from paper_2103_00736_amd import acs, synth
+
+    p = synth.e3_lp(args.dense_n)
+    assert acs.lib().acs_init(0) == 0
+    prob = acs.Problem.from_synth(p)
+    del p.A
+    out = {}
+    for name, proj in (("factor", acs.PROJ_FACTOR), ("cg", acs.PROJ_CG)):
+        _progress(f"dense LP {p.m}x{p.n}: full solve, {name} projection")
+        st = acs.State(prob, precision=acs.PREC_MIXED, projection=proj, eps_kkt=1e-4, max_iter=20000)
+        t0 = time.perf_counter()
+        info = st.solve()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": dt, "status": info.status, "iterations": info.iterations,
+                     "conditionings": info.conditionings, "kkt": info.kkt, "pobj": info.pobj,
+                     "cg_steps": info.cg_steps}
+        st.close()
+    print(json.dumps({"metric": "time to 1e-4 KKT on the paper's dense random LP (Sec. V-B recipe)",
+                      "value": out["factor"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+                      "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"dense LP m={p.m} n={p.n}, mixed precision, t=9.2, L={{300,400,...}}"},
+                      "solves": out, "speedup_factor_vs_cg": out["cg"]["seconds"] / out["factor"]["seconds"]}),
+          flush=True)
     return 0
 
 
