@@ -446,15 +446,19 @@ def bench_dense_factor(args, cpu_proc):
     # Algorithmic work per launch:
     #   k_fac_syrk: the lower triangle of B B^T, m (m + 1) / 2 dot products of
     #     length n: m (m + 1) n flops;
-    #   k_fac_update (one sweep step, rank 64): every lower 64 x 64 tile of S
-    #     outside the pivot block's row and column read and written once
-    #     (16 bytes an entry) and the 64-column panel W read once; 2 * 64
-    #     flops an entry;
+    #   k_fac_update (two sweep steps K, K + 1 a launch; the last step alone
+    #     when the block count is odd): every lower 64 x 64 tile of S outside
+    #     block row and column K + 1 read and written once (16 bytes an
+    #     entry) and the two 64-column panels W read once; 2 * 64 flops an
+    #     entry for each step's term (block row and column K take only step
+    #     K + 1's).  Per launch: the event's total over its launches;
     #   k_fac_apply: M^{-1} once (FP64) and three m-vectors.
     nb = (m + 63) // 64
-    upd_tiles = nb * (nb + 1) // 2 - nb
-    upd_bytes = 16 * 64 * 64 * upd_tiles + 8 * 64 * 64 * nb
-    upd_flops = 2 * 64 * 64 * 64 * upd_tiles
+    tiles = nb * (nb + 1) // 2
+    pairs, single = nb // 2, nb % 2
+    tile_flops = 2 * 64 * 64 * 64
+    upd_bytes = 16 * 64 * 64 * (tiles - nb) + (2 * pairs + single) * 8 * 64 * 64 * nb // (pairs + single)
+    upd_flops = tile_flops * (pairs * (2 * (tiles - 2 * nb + 1) + nb - 1) + single * (tiles - nb)) // (pairs + single)
     syrk_flops = m * (m + 1) * n
     apply_bytes = 8 * m * m + 8 * 3 * m
     cnt_s, ms_s = prof["syrk"]
@@ -475,8 +479,15 @@ def bench_dense_factor(args, cpu_proc):
                 "unit": "TFLOP/s", "frac": syrk_tf / FP64_PEAK_TFS,
                 "traffic": traffic_record("fac_syrk", "dense_lp", "acs_factor.hip"),
                 "avg_launch_ms": ms_s / max(cnt_s, 1), "launches": cnt_s, "algorithmic_flops_per_launch": syrk_flops}
-    else:  # the rank-64 step streams S once: HBM-bound (its flops would take 0.8x as long at the MFMA peak)
-        roof = {"bound": "hbm", "kernel": "k_fac_update (rank-64 sweep step)", "achieved": upd_gbs,
+    elif upd_flops / (FP64_PEAK_TFS * 1e12) >= upd_bytes / (HBM_PEAK_GBS * 1e9):
+        # two steps a pass over S: at the peaks its flops take longer than its bytes
+        roof = {"bound": "mfma", "kernel": "k_fac_update (two rank-64 sweep steps, FP64 MFMA)", "achieved": upd_tf,
+                "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": upd_tf / FP64_PEAK_TFS,
+                "traffic": traffic_record("fac_update", "dense_lp", "acs_factor.hip"),
+                "avg_launch_ms": ms_u / max(cnt_u, 1), "launches": cnt_u, "algorithmic_flops_per_launch": upd_flops,
+                "algorithmic_bytes_per_launch": upd_bytes, "hbm_gbs": upd_gbs}
+    else:
+        roof = {"bound": "hbm", "kernel": "k_fac_update (sweep steps)", "achieved": upd_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": upd_gbs / HBM_PEAK_GBS,
                 "traffic": traffic_record("fac_update", "dense_lp", "acs_factor.hip"),
                 "avg_launch_ms": ms_u / max(cnt_u, 1), "launches": cnt_u, "algorithmic_bytes_per_launch": upd_bytes,

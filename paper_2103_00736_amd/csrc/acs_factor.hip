@@ -23,7 +23,10 @@
 //          empty) row and is skipped, which leaves zeros in its row and
 //          column: the result is then the inverse on the other rows, with
 //          the oracle's pseudo-inverse's projection.  The trailing update is
-//          a rank-64 FP64 MFMA product on the lower 64 x 64 tiles.
+//          an FP64 MFMA product on the lower 64 x 64 tiles; steps are taken
+//          in pairs, so that one pass over S applies the rank-64 terms of
+//          two steps (the block row of the second step is brought up to date
+//          first, before its pivot).
 //   mirror S <- -S, both triangles.
 //   apply  w += S r64 (FP64 rows, HBM-bound).
 #include <algorithm>
@@ -192,7 +195,8 @@ __global__ __launch_bounds__(kSyrkThreads) __attribute__((amdgpu_waves_per_eu(4,
 // or below kFacPivotTol is skipped: its column of L is zero), with the
 // forward substitution L X = I carried along in the same sweep (step j
 // finishes row j of X = L^{-1}; skipped pivots leave zero rows and columns).
-// Writes L^{-1} to f.P and S_KK <- -P^{-1} = -L^{-T} L^{-1}.
+// Writes L^{-1} to f.P, S_KK <- -P^{-1} = -L^{-T} L^{-1} and a zero W block
+// for block K.
 __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
   __shared__ double P[kT][kT + 1];  // L in the lower triangle
   __shared__ double X[kT][kT + 1];  // L^{-1}: forward substitution of L X = I, row by row with L
@@ -252,11 +256,16 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) Skk[size_t(a0 + p) * f.mp + b0 + q] = -acc[p][q];
   for (int e = tid; e < kT * kT; e += kBlock) f.P[e] = X[e / kT][e % kT];
+  // W of this step on block K itself is zero: the paired update then adds
+  // nothing from this step to block row and column K
+  double* __restrict__ Wk = f.C + size_t(K & 1) * f.mp * kT + size_t(K) * kT * kT;
+  for (int e = tid; e < kT * kT; e += kBlock) Wk[e] = 0.0;
 }
 
 // Panel of block K, one workgroup per other row block I: Op = S_IK (read
 // from the lower tile S_KI^T when I < K), W = Op L^{-T} (kept for the
-// update), C = W L^{-1} = Op P^{-1} written back to S_IK (S_KI^T).
+// update, in slot K mod 2), C = W L^{-1} = Op P^{-1} written back to S_IK
+// (S_KI^T).
 __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
   __shared__ double T[kT][kT + 1];
   __shared__ double Li[kT][kT + 1];
@@ -291,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) T[i0 + r][c0 + q] = w[r][q];
   __syncthreads();
-  double* __restrict__ Wg = f.C + size_t(I) * kT * kT;
+  double* __restrict__ Wg = f.C + size_t(K & 1) * f.mp * kT + size_t(I) * kT * kT;
   for (int e = tid; e < kT * kT; e += kBlock) Wg[e] = T[e / kT][e % kT];
   double c[4][4] = {};
   for (int e = 0; e < kT; ++e) {  // C = W L^{-1}: C_ic = sum_e W_ie Li_ec
@@ -320,53 +329,55 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
   }
 }
 
-// Trailing update of block K on the lower 64 x 64 tile (I, J), I, J != K:
-// S_IJ -= W_I W_J^T (= Op_I P^{-1} Op_J^T), rank 64.  The step streams the
-// whole lower triangle of S once, so the tile's S values are loaded first
-// (their latency overlaps the staging of W_I and W_J in LDS and the MFMAs);
-// four waves in 2 x 2, each 32 x 32 (2 x 2 MFMA tiles); lane slot q of MFMA
-// step s in quarter h is column 16 h + 4 q + s.
+// Trailing update on the lower 64 x 64 tile (I, J).  Sweep steps are taken in
+// pairs (K, K + 1) so that one pass over S applies two of them:
+//   strip (after step K's panel): the tiles of block row and column K + 1
+//          get step K's term, S_IJ -= W_I W_J^T (W of step K), so that
+//          step K + 1's pivot and panel see the updated values;
+//   pair  (after step K + 1's panel): every other tile gets both terms,
+//          S_IJ -= W_I W_J^T (step K) + W'_I W'_J^T (step K + 1), a rank-128
+//          product; on block row or column K the first term is zero (step
+//          K wrote its final values there, and W of step K on block K is
+//          zero);
+//   one   a single step K (the last block when the count is odd).
+// The tile's S values are loaded first (their latency overlaps the staging
+// of the W blocks in LDS); the second term's W blocks are fetched into
+// registers while the first term's MFMAs run.  Four waves in 2 x 2, each
+// 32 x 32 (2 x 2 MFMA tiles); lane slot q of MFMA step s in quarter h is
+// column 16 h + 4 q + s.
 constexpr int kWLd = kT + 2;  // LDS row stride of the staged W blocks (doubles)
+enum UpdMode { kUpdOne = 0, kUpdStrip = 1, kUpdPair = 2 };
 
-__global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
-  __shared__ double Wi[kT * kWLd];
-  __shared__ double Wj[kT * kWLd];
-  const int tile = f.upd_order[blockIdx.x];
-  if (tile < 0) return;
-  const int I = tile >> 16, J = tile & 0xffff;
-  if (I == K || J == K) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
-  double* __restrict__ St = f.S + size_t(I) * kT * f.mp + size_t(J) * kT;
-  double sv[2][2][4];
+// W = Op L^{-T} of sweep step K for row block I: two slots of mp x 64, so
+// that steps K and K + 1 are both available to the paired update
+__device__ __forceinline__ const double* w_block(const FacDev& f, int K, int I) {
+  return f.C + size_t(K & 1) * f.mp * kT + size_t(I) * kT * kT;
+}
+
+// rows r + 8 q, columns c, c + 1 of a W block, as one vector value (an
+// array held across the first term's MFMAs is kept in scratch memory by the
+// compiler; a vector stays in registers)
+typedef double d16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ d16 w_fetch(const double* __restrict__ w, int r, int c) {
+  d16 x;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sv[a][b][v] = St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li];
-  const double* __restrict__ Wig = f.C + size_t(I) * kT * kT;
-  const double* __restrict__ Wjg = f.C + size_t(J) * kT * kT;
-  {
-    const int r = tid >> 5, c = (tid & 31) * 2;  // rows r + 8 q, columns c, c + 1
-    double2 xi[8], xj[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      xi[q] = *reinterpret_cast<const double2*>(Wig + (r + 8 * q) * kT + c);
-      xj[q] = *reinterpret_cast<const double2*>(Wjg + (r + 8 * q) * kT + c);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      *reinterpret_cast<double2*>(Wi + (r + 8 * q) * kWLd + c) = xi[q];
-      *reinterpret_cast<double2*>(Wj + (r + 8 * q) * kWLd + c) = xj[q];
-    }
+  for (int q = 0; q < 8; ++q) {
+    const double2 v = *reinterpret_cast<const double2*>(w + (r + 8 * q) * kT + c);
+    x[2 * q] = v.x;
+    x[2 * q + 1] = v.y;
   }
-  __syncthreads();
-  d4 acc[2][2];
+  return x;
+}
+
+__device__ __forceinline__ void w_stage(double* Ws, int r, int c, d16 x) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < 8; ++q) *reinterpret_cast<double2*>(Ws + (r + 8 * q) * kWLd + c) = double2{x[2 * q], x[2 * q + 1]};
+}
+
+// acc += Wi Wj^T on this wave's 32 x 32 block
+__device__ __forceinline__ void w_product(const double* Wi, const double* Wj, int wr, int wc, int li, int kq,
+                                          d4 (&acc)[2][2]) {
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     double av[2][4], bv[2][4];
@@ -392,6 +403,46 @@ __global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
   }
+}
+
+// S_IJ -= W_I W_J^T of step K0 (and of step K0 + 1 when kTwo)
+template <bool kTwo>
+__device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K0, double* Wi, double* Wj) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
+  double* __restrict__ St = f.S + size_t(I) * kT * f.mp + size_t(J) * kT;
+  double sv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sv[a][b][v] = St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li];
+  const int r = tid >> 5, c = (tid & 31) * 2;  // staging: rows r + 8 q, columns c, c + 1
+  {
+    const d16 xi = w_fetch(w_block(f, K0, I), r, c), xj = w_fetch(w_block(f, K0, J), r, c);
+    w_stage(Wi, r, c, xi);
+    w_stage(Wj, r, c, xj);
+  }
+  __syncthreads();
+  d16 yi, yj;
+  if (kTwo) {
+    yi = w_fetch(w_block(f, K0 + 1, I), r, c);
+    yj = w_fetch(w_block(f, K0 + 1, J), r, c);
+  }
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  w_product(Wi, Wj, wr, wc, li, kq, acc);
+  if (kTwo) {
+    __syncthreads();
+    w_stage(Wi, r, c, yi);
+    w_stage(Wj, r, c, yj);
+    __syncthreads();
+    w_product(Wi, Wj, wr, wc, li, kq, acc);
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -399,6 +450,29 @@ __global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li] = sv[a][b][v] - acc[a][b][v];
+}
+
+template <int kMode>
+__global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
+  __shared__ double Wi[kT * kWLd];
+  __shared__ double Wj[kT * kWLd];
+  int I, J;
+  if (kMode == kUpdStrip) {  // block row and column K + 1, all blocks but K
+    const int t = blockIdx.x, K1 = K + 1;
+    if (t == K) return;
+    I = t < K1 ? K1 : t;
+    J = t < K1 ? t : K1;
+  } else {
+    const int tile = f.upd_order[blockIdx.x];
+    if (tile < 0) return;
+    I = tile >> 16;
+    J = tile & 0xffff;
+    const int last = kMode == kUpdPair ? K + 1 : K;
+    if (I == last || J == last) return;
+  }
+  // in a pair, tiles on block row or column K take step K's term as zero:
+  // W of step K on block K is zero (written by the pivot)
+  update_tile<kMode == kUpdPair>(f, I, J, K, Wi, Wj);
 }
 
 // S <- -S on both triangles from the lower tiles (diagonal tiles from their
@@ -509,7 +583,15 @@ void launch_fac_pivot_panel(const FacDev& f, int K, hipStream_t st) {
 }
 
 void launch_fac_update(const FacDev& f, int K, hipStream_t st) {
-  if (f.nb > 1) ACS_LAUNCH(k_fac_update, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
+  if (f.nb > 1) ACS_LAUNCH(k_fac_update<kUpdOne>, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
+}
+
+void launch_fac_strip(const FacDev& f, int K, hipStream_t st) {
+  ACS_LAUNCH(k_fac_update<kUpdStrip>, dim3(f.nb), dim3(kBlock), 0, st, f, K);
+}
+
+void launch_fac_update_pair(const FacDev& f, int K, hipStream_t st) {
+  ACS_LAUNCH(k_fac_update<kUpdPair>, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
 }
 
 void launch_fac_mirror(const FacDev& f, hipStream_t st) {

@@ -182,7 +182,7 @@ struct FacDev {
   int32_t nb;   // pivot blocks swept: ceil(m / kFacTile)
   double* S;    // mp x mp: M, then -M^{-1} (lower tiles) during the sweep, then M^{-1} (full)
   double* B;    // mp x ldb: A_s in FP64, zero outside m x n
-  double* C;    // mp x kFacTile: W = Op L^{-T} of the current sweep step (Op the pivot-column panel)
+  double* C;    // 2 x mp x kFacTile: W = Op L^{-T} of sweep step K in slot K mod 2 (Op the pivot-column panel)
   double* P;    // kFacTile x kFacTile: L^{-1}, L the Cholesky factor of the current pivot block
   // workgroup -> tile tables (fac_tile_order) of the form step (128 x 128
   // tiles of mp) and of the sweep's update (64 x 64 tiles of nb blocks)
@@ -231,6 +231,10 @@ template <typename VT> void launch_fac_copy(const Dev<VT>& d, const FacDev& f, h
 void launch_fac_syrk(const FacDev& f, hipStream_t st);
 void launch_fac_pivot_panel(const FacDev& f, int K, hipStream_t st);
 void launch_fac_update(const FacDev& f, int K, hipStream_t st);
+// paired steps K, K + 1 (K even): launch_fac_strip after step K's panel,
+// launch_fac_update_pair after step K + 1's panel
+void launch_fac_strip(const FacDev& f, int K, hipStream_t st);
+void launch_fac_update_pair(const FacDev& f, int K, hipStream_t st);
 void launch_fac_mirror(const FacDev& f, hipStream_t st);
 template <typename VT> void launch_fac_apply(const Dev<VT>& d, const FacDev& f, hipStream_t st);
 

@@ -268,9 +268,10 @@ def test_factor_full_solve(make, prec):
         assert abs(rec["pobj"] - p.p_star) <= 1e-3 * (1 + abs(p.p_star))
 
 
-@pytest.mark.parametrize("m", [1, 63, 64, 65, 127, 128, 129, 200])
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 127, 128, 129, 200, 257])
 def test_factor_tile_boundaries(m):
-    """Orders around the 64-row pivot blocks and the 128-row padding."""
+    """Orders around the 64-row pivot blocks and the 128-row padding, with
+    odd and even block counts (steps are swept in pairs)."""
     n = max(2, int(m * 1.25) + 1)
     rng = np.random.default_rng(m)
     p = _Sparse(rng.uniform(-1, 1, (m, n)), m, f"dense_{m}x{n}")
