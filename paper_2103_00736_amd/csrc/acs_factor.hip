@@ -190,6 +190,80 @@ __global__ __launch_bounds__(kSyrkThreads) __attribute__((amdgpu_waves_per_eu(4,
 // ----------------------------------------------------------------------------
 // sweep
 // ----------------------------------------------------------------------------
+// Shared by the panel and the update: the W panels, and 64-row FP64 MFMA
+// products of blocks staged in LDS (four waves in 2 x 2, each 32 x 32 as
+// 2 x 2 MFMA tiles; lane slot q of MFMA step s in quarter h of the staged
+// columns is column 16 h + 4 q + s).
+constexpr int kWc = 32;         // columns of a W block staged in LDS at a time
+constexpr int kWcLd = kWc + 2;  // LDS row stride of a staged chunk (doubles)
+enum UpdMode { kUpdOne = 0, kUpdStrip = 1, kUpdPair = 2 };
+
+// W = Op L^{-T} of sweep step K for row block I: two slots of mp x 64, so
+// that steps K and K + 1 are both available to the paired update
+__device__ __forceinline__ const double* w_block(const FacDev& f, int K, int I) {
+  return f.C + size_t(K & 1) * f.mp * kT + size_t(I) * kT * kT;
+}
+
+// chunk q of the tile's W columns: term q / 2 (step K0 + q / 2), columns
+// 32 (q % 2) .. + 32 of row block B
+__device__ __forceinline__ const double* w_chunk(const FacDev& f, int K0, int q, int B) {
+  return w_block(f, K0 + q / 2, B) + kWc * (q % 2);
+}
+
+// rows r + 16 q, columns c, c + 1 of a chunk, as one vector value (an array
+// held across MFMAs is kept in scratch memory by the compiler; a vector
+// stays in registers)
+typedef double d8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ d8 w_fetch(const double* __restrict__ w, int r, int c) {
+  d8 x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double2 v = *reinterpret_cast<const double2*>(w + (r + 16 * q) * kT + c);
+    x[2 * q] = v.x;
+    x[2 * q + 1] = v.y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ void w_stage(double* Ws, int r, int c, d8 x) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    *reinterpret_cast<double2*>(Ws + (r + 16 * q) * kWcLd + c) = double2{x[2 * q], x[2 * q + 1]};
+}
+
+// acc += Wi Wj^T over kCols staged columns (LDS row stride kLd), on this
+// wave's 32 x 32 block: rows 32 wr .., columns 32 wc ..
+template <int kCols = kWc, int kLd = kWcLd>
+__device__ __forceinline__ void w_product(const double* Wi, const double* Wj, int wr, int wc, int li, int kq,
+                                          d4 (&acc)[2][2]) {
+#pragma unroll
+  for (int h = 0; h < kCols / 16; ++h) {
+    double av[2][4], bv[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const double* pa = Wi + (wr * 32 + t * 16 + li) * kLd + h * 16 + kq * 4;
+      const double* pb = Wj + (wc * 32 + t * 16 + li) * kLd + h * 16 + kq * 4;
+      const double2 a0 = *reinterpret_cast<const double2*>(pa), a1 = *reinterpret_cast<const double2*>(pa + 2);
+      const double2 b0 = *reinterpret_cast<const double2*>(pb), b1 = *reinterpret_cast<const double2*>(pb + 2);
+      av[t][0] = a0.x;
+      av[t][1] = a0.y;
+      av[t][2] = a1.x;
+      av[t][3] = a1.y;
+      bv[t][0] = b0.x;
+      bv[t][1] = b0.y;
+      bv[t][2] = b1.x;
+      bv[t][3] = b1.y;
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
+  }
+}
+
 // Pivot block K, P = S_KK (the Schur complement of the rows not yet swept,
 // positive semidefinite): right-looking Cholesky P = L L^T in LDS (a pivot at
 // or below kFacPivotTol is skipped: its column of L is zero), with the
@@ -198,9 +272,8 @@ __global__ __launch_bounds__(kSyrkThreads) __attribute__((amdgpu_waves_per_eu(4,
 // Writes L^{-1} to f.P, S_KK <- -P^{-1} = -L^{-T} L^{-1} and a zero W block
 // for block K.
 __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
-  __shared__ double P[kT][kT + 1];  // L in the lower triangle
+  __shared__ double P[kT][kT + 1];  // the trailing Schur complements; column j of L is P_:j / L_jj
   __shared__ double X[kT][kT + 1];  // L^{-1}: forward substitution of L X = I, row by row with L
-  __shared__ double rd[kT];         // 1 / L_jj, 0 for a skipped pivot
   const int tid = threadIdx.x;
   double* __restrict__ Skk = f.S + size_t(K) * kT * f.mp + size_t(K) * kT;
   for (int e = tid; e < kT * kT; e += kBlock) {
@@ -209,33 +282,36 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
     X[i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
+  // One barrier a column: every thread takes 1 / L_jj itself, scales the
+  // column-j values of L and row j of X it reads in registers, and row j of
+  // X is scaled in place one column later, when no thread reads it any more.
+  double rprev = 0.0;
+  const int k = tid & 63, w = tid >> 6;
+  constexpr int kRows = kT / (kBlock / 64);  // rows i > j a wave takes at most
   for (int j = 0; j < kT; ++j) {
-    if (tid == 0) {
-      const double d = P[j][j];
-      const bool ok = d > kFacPivotTol;
-      const double l = ok ? sqrt(d) : 0.0;
-      P[j][j] = l;
-      rd[j] = ok ? 1.0 / l : 0.0;
+    if (j > 0 && tid < kT) X[j - 1][tid] *= rprev;  // row j - 1 of L^{-1} is final
+    const double d = P[j][j];
+    const double r = d > kFacPivotTol ? 1.0 / sqrt(d) : 0.0;  // 0: skipped pivot
+    // rows i = j + 1 + w + 4 q > j, a wave per row, a lane per column k <= i:
+    // X (nonzero for k <= j) and the trailing lower part of P (j < k <= i).
+    // The lane's factor (row j of X or column j of P) is the same for every
+    // row; the rows' column-j entries are all read before any update, so
+    // the loads issue together.
+    const double src = (k <= j ? X[j][k] : P[k][j]) * r;
+    double* __restrict__ dst = k <= j ? &X[0][k] : &P[0][k];
+    double l[kRows];
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) l[q] = P[min(j + 1 + w + 4 * q, kT - 1)][j] * r;
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      const int i = j + 1 + w + 4 * q;
+      if (i < kT && k <= i) dst[i * (kT + 1)] -= l[q] * src;
     }
     __syncthreads();
-    const double r = rd[j];
-    if (tid > j && tid < kT) P[tid][j] *= r;  // column j of L
-    if (tid < kT) X[j][tid] *= r;             // row j of L^{-1} is final
-    __syncthreads();
-    // rows i > j, one wave per row, a lane per column k <= i: X (nonzero for
-    // k <= j) and the trailing lower part of P (j < k <= i)
-    {
-      const int k = tid & 63;
-      for (int i = j + 1 + (tid >> 6); i < kT; i += kBlock / 64) {
-        const double lij = P[i][j];
-        if (k <= j)
-          X[i][k] -= lij * X[j][k];
-        else if (k <= i)
-          P[i][k] -= lij * P[k][j];
-      }
-    }
-    __syncthreads();
+    rprev = r;
   }
+  if (tid < kT) X[kT - 1][tid] *= rprev;
+  __syncthreads();
   // S_KK = -L^{-T} L^{-1}, 4 x 4 blocks per thread; L^{-1} is lower triangular
   const int a0 = (tid >> 4) * 4, b0 = (tid & 15) * 4;
   double acc[4][4] = {};
@@ -266,66 +342,67 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
 // from the lower tile S_KI^T when I < K), W = Op L^{-T} (kept for the
 // update, in slot K mod 2), C = W L^{-1} = Op P^{-1} written back to S_IK
 // (S_KI^T).
+constexpr int kPLd = kT + 2;  // LDS row stride of the panel's 64 x 64 blocks
+
 __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
-  __shared__ double T[kT][kT + 1];
-  __shared__ double Li[kT][kT + 1];
+  __shared__ double T[kT * kPLd];    // Op, then W, then C
+  __shared__ double Li[kT * kPLd];   // L^{-1}
+  __shared__ double LiT[kT * kPLd];  // L^{-T}
   const int I = blockIdx.x < K ? blockIdx.x : blockIdx.x + 1;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
   const bool below = I > K;
-  for (int e = tid; e < kT * kT; e += kBlock) Li[e / kT][e % kT] = f.P[e];
+  for (int e = tid; e < kT * kT; e += kBlock) {
+    const int a = e / kT, b = e % kT;
+    const double x = f.P[e];
+    Li[a * kPLd + b] = x;
+    LiT[b * kPLd + a] = x;
+  }
   if (below) {
     const double* __restrict__ src = f.S + size_t(I) * kT * f.mp + size_t(K) * kT;
-    for (int e = tid; e < kT * kT; e += kBlock) T[e / kT][e % kT] = src[size_t(e / kT) * f.mp + e % kT];
+    for (int e = tid; e < kT * kT; e += kBlock) T[(e / kT) * kPLd + e % kT] = src[size_t(e / kT) * f.mp + e % kT];
   } else {
     const double* __restrict__ src = f.S + size_t(K) * kT * f.mp + size_t(I) * kT;
-    for (int e = tid; e < kT * kT; e += kBlock) T[e % kT][e / kT] = src[size_t(e / kT) * f.mp + e % kT];
+    for (int e = tid; e < kT * kT; e += kBlock) T[(e % kT) * kPLd + e / kT] = src[size_t(e / kT) * f.mp + e % kT];
   }
   __syncthreads();
-  const int i0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;  // this thread's 4 x 4 block
-  double w[4][4] = {};
-  for (int e = 0; e < kT; ++e) {  // W = Op L^{-T}: W_ic = sum_e Op_ie Li_ce
-    double a[4], l[4];
+  // W = Op L^{-T}: W_ic = sum_e Op_ie Li_ce (FP64 MFMA, 4 waves of 32 x 32)
+  d4 acc[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = T[i0 + r][e];
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) l[q] = Li[c0 + q][e];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) w[r][q] += a[r] * l[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) T[i0 + r][c0 + q] = w[r][q];
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  w_product<kT, kPLd>(T, Li, wr, wc, li, kq, acc);
   __syncthreads();
   double* __restrict__ Wg = f.C + size_t(K & 1) * f.mp * kT + size_t(I) * kT * kT;
-  for (int e = tid; e < kT * kT; e += kBlock) Wg[e] = T[e / kT][e % kT];
-  double c[4][4] = {};
-  for (int e = 0; e < kT; ++e) {  // C = W L^{-1}: C_ic = sum_e W_ie Li_ec
-    double a[4], l[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = T[i0 + r][e];
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) l[q] = Li[e][c0 + q];
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) c[r][q] += a[r] * l[q];
-  }
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 32 + a * 16 + kq + 4 * v, col = wc * 32 + b * 16 + li;
+        T[row * kPLd + col] = acc[a][b][v];
+        Wg[row * kT + col] = acc[a][b][v];
+        acc[a][b][v] = 0.0;
+      }
+  __syncthreads();
+  // C = W L^{-1}: C_ic = sum_e W_ie Li_ec
+  w_product<kT, kPLd>(T, LiT, wr, wc, li, kq, acc);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) T[i0 + r][c0 + q] = c[r][q];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[(wr * 32 + a * 16 + kq + 4 * v) * kPLd + wc * 32 + b * 16 + li] = acc[a][b][v];
   __syncthreads();
   if (below) {
     double* __restrict__ dst = f.S + size_t(I) * kT * f.mp + size_t(K) * kT;
-    for (int e = tid; e < kT * kT; e += kBlock) dst[size_t(e / kT) * f.mp + e % kT] = T[e / kT][e % kT];
+    for (int e = tid; e < kT * kT; e += kBlock) dst[size_t(e / kT) * f.mp + e % kT] = T[(e / kT) * kPLd + e % kT];
   } else {
     double* __restrict__ dst = f.S + size_t(K) * kT * f.mp + size_t(I) * kT;
-    for (int e = tid; e < kT * kT; e += kBlock) dst[size_t(e / kT) * f.mp + e % kT] = T[e % kT][e / kT];
+    for (int e = tid; e < kT * kT; e += kBlock) dst[size_t(e / kT) * f.mp + e % kT] = T[(e % kT) * kPLd + e / kT];
   }
 }
 
@@ -341,72 +418,13 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
 //          zero);
 //   one   a single step K (the last block when the count is odd).
 // The tile's S values are loaded first (their latency overlaps the staging
-// of the W blocks in LDS); the second term's W blocks are fetched into
-// registers while the first term's MFMAs run.  Four waves in 2 x 2, each
-// 32 x 32 (2 x 2 MFMA tiles); lane slot q of MFMA step s in quarter h is
-// column 16 h + 4 q + s.
-constexpr int kWLd = kT + 2;  // LDS row stride of the staged W blocks (doubles)
-enum UpdMode { kUpdOne = 0, kUpdStrip = 1, kUpdPair = 2 };
-
-// W = Op L^{-T} of sweep step K for row block I: two slots of mp x 64, so
-// that steps K and K + 1 are both available to the paired update
-__device__ __forceinline__ const double* w_block(const FacDev& f, int K, int I) {
-  return f.C + size_t(K & 1) * f.mp * kT + size_t(I) * kT * kT;
-}
-
-// rows r + 8 q, columns c, c + 1 of a W block, as one vector value (an
-// array held across the first term's MFMAs is kept in scratch memory by the
-// compiler; a vector stays in registers)
-typedef double d16 __attribute__((ext_vector_type(16)));
-
-__device__ __forceinline__ d16 w_fetch(const double* __restrict__ w, int r, int c) {
-  d16 x;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const double2 v = *reinterpret_cast<const double2*>(w + (r + 8 * q) * kT + c);
-    x[2 * q] = v.x;
-    x[2 * q + 1] = v.y;
-  }
-  return x;
-}
-
-__device__ __forceinline__ void w_stage(double* Ws, int r, int c, d16 x) {
-#pragma unroll
-  for (int q = 0; q < 8; ++q) *reinterpret_cast<double2*>(Ws + (r + 8 * q) * kWLd + c) = double2{x[2 * q], x[2 * q + 1]};
-}
-
-// acc += Wi Wj^T on this wave's 32 x 32 block
-__device__ __forceinline__ void w_product(const double* Wi, const double* Wj, int wr, int wc, int li, int kq,
-                                          d4 (&acc)[2][2]) {
-#pragma unroll
-  for (int h = 0; h < 4; ++h) {
-    double av[2][4], bv[2][4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const double* pa = Wi + (wr * 32 + t * 16 + li) * kWLd + h * 16 + kq * 4;
-      const double* pb = Wj + (wc * 32 + t * 16 + li) * kWLd + h * 16 + kq * 4;
-      const double2 a0 = *reinterpret_cast<const double2*>(pa), a1 = *reinterpret_cast<const double2*>(pa + 2);
-      const double2 b0 = *reinterpret_cast<const double2*>(pb), b1 = *reinterpret_cast<const double2*>(pb + 2);
-      av[t][0] = a0.x;
-      av[t][1] = a0.y;
-      av[t][2] = a1.x;
-      av[t][3] = a1.y;
-      bv[t][0] = b0.x;
-      bv[t][1] = b0.y;
-      bv[t][2] = b1.x;
-      bv[t][3] = b1.y;
-    }
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
-  }
-}
-
-// S_IJ -= W_I W_J^T of step K0 (and of step K0 + 1 when kTwo)
-template <bool kTwo>
+// of the W blocks in LDS).  W columns are staged 32 at a time (35 KB of LDS,
+// three workgroups a CU at 164 registers), the next chunk fetched into
+// registers while the current chunk's MFMAs run.
+// S_IJ -= sum over kTerms steps K0, K0 + 1, .. of W_I W_J^T, the W columns
+// staged 32 at a time, the next chunk fetched into registers during the
+// current chunk's MFMAs
+template <int kTerms>
 __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K0, double* Wi, double* Wj) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
@@ -418,30 +436,30 @@ __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) sv[a][b][v] = St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li];
-  const int r = tid >> 5, c = (tid & 31) * 2;  // staging: rows r + 8 q, columns c, c + 1
-  {
-    const d16 xi = w_fetch(w_block(f, K0, I), r, c), xj = w_fetch(w_block(f, K0, J), r, c);
-    w_stage(Wi, r, c, xi);
-    w_stage(Wj, r, c, xj);
-  }
+  const int r = tid >> 4, c = (tid & 15) * 2;  // staging: rows r + 16 q, columns c, c + 1
+  d8 xi = w_fetch(w_chunk(f, K0, 0, I), r, c), xj = w_fetch(w_chunk(f, K0, 0, J), r, c);
+  w_stage(Wi, r, c, xi);
+  w_stage(Wj, r, c, xj);
   __syncthreads();
-  d16 yi, yj;
-  if (kTwo) {
-    yi = w_fetch(w_block(f, K0 + 1, I), r, c);
-    yj = w_fetch(w_block(f, K0 + 1, J), r, c);
-  }
   d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  w_product(Wi, Wj, wr, wc, li, kq, acc);
-  if (kTwo) {
-    __syncthreads();
-    w_stage(Wi, r, c, yi);
-    w_stage(Wj, r, c, yj);
-    __syncthreads();
+  constexpr int kChunks = 2 * kTerms;
+#pragma unroll
+  for (int q = 0; q < kChunks; ++q) {
+    if (q + 1 < kChunks) {
+      xi = w_fetch(w_chunk(f, K0, q + 1, I), r, c);
+      xj = w_fetch(w_chunk(f, K0, q + 1, J), r, c);
+    }
     w_product(Wi, Wj, wr, wc, li, kq, acc);
+    if (q + 1 < kChunks) {
+      __syncthreads();
+      w_stage(Wi, r, c, xi);
+      w_stage(Wj, r, c, xj);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -453,9 +471,9 @@ __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K
 }
 
 template <int kMode>
-__global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
-  __shared__ double Wi[kT * kWLd];
-  __shared__ double Wj[kT * kWLd];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fac_update(FacDev f, int K) {
+  __shared__ double Wi[kT * kWcLd];
+  __shared__ double Wj[kT * kWcLd];
   int I, J;
   if (kMode == kUpdStrip) {  // block row and column K + 1, all blocks but K
     const int t = blockIdx.x, K1 = K + 1;
@@ -472,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_fac_update(FacDev f, int K) {
   }
   // in a pair, tiles on block row or column K take step K's term as zero:
   // W of step K on block K is zero (written by the pivot)
-  update_tile<kMode == kUpdPair>(f, I, J, K, Wi, Wj);
+  update_tile<kMode == kUpdPair ? 2 : 1>(f, I, J, K, Wi, Wj);
 }
 
 // S <- -S on both triangles from the lower tiles (diagonal tiles from their
