@@ -264,6 +264,48 @@ __device__ __forceinline__ void w_product(const double* Wi, const double* Wj, in
   }
 }
 
+// acc += A B over 64 staged columns, A row-major [row][k], B k-major
+// [k][column] (LDS row stride kPLd), on this wave's 32 x 32 block
+constexpr int kPLd = kT + 2;  // LDS row stride of the panel's 64 x 64 blocks
+
+__device__ __forceinline__ void kn_product(const double* A, const double* B, int wr, int wc, int li, int kq,
+                                           d4 (&acc)[2][2]) {
+#pragma unroll
+  for (int h = 0; h < kT / 16; ++h) {
+    double av[2][4], bv[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const double* pa = A + (wr * 32 + t * 16 + li) * kPLd + h * 16 + kq * 4;
+      const double2 a0 = *reinterpret_cast<const double2*>(pa), a1 = *reinterpret_cast<const double2*>(pa + 2);
+      av[t][0] = a0.x;
+      av[t][1] = a0.y;
+      av[t][2] = a1.x;
+      av[t][3] = a1.y;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) bv[t][s4] = B[(h * 16 + kq * 4 + s4) * kPLd + wc * 32 + t * 16 + li];
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a][s4], bv[b][s4], acc[a][b]);
+  }
+}
+
+// A 64 x 64 block, row stride ld, read by the workgroup: element e = tid +
+// 256 u in v[u].  The loads are all issued before any is used (a loop that
+// stores each element to LDS as it arrives waits for every load in turn).
+constexpr int kPer = kT * kT / kBlock;  // 16
+
+__device__ __forceinline__ void block_load(const double* __restrict__ src, size_t ld, double (&v)[kPer]) {
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = threadIdx.x + kBlock * u;
+    v[u] = src[size_t(e / kT) * ld + e % kT];
+  }
+}
+
 // Pivot block K, P = S_KK (the Schur complement of the rows not yet swept,
 // positive semidefinite): right-looking Cholesky P = L L^T in LDS (a pivot at
 // or below kFacPivotTol is skipped: its column of L is zero), with the
@@ -276,10 +318,15 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
   __shared__ double X[kT][kT + 1];  // L^{-1}: forward substitution of L X = I, row by row with L
   const int tid = threadIdx.x;
   double* __restrict__ Skk = f.S + size_t(K) * kT * f.mp + size_t(K) * kT;
-  for (int e = tid; e < kT * kT; e += kBlock) {
-    const int i = e / kT, k = e % kT;
-    P[i][k] = Skk[size_t(i) * f.mp + k];
-    X[i][k] = (i == k) ? 1.0 : 0.0;
+  {
+    double v[kPer];
+    block_load(Skk, f.mp, v);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + kBlock * u, i = e / kT, k = e % kT;
+      P[i][k] = v[u];
+      X[i][k] = (i == k) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   // One barrier a column: every thread takes 1 / L_jj itself, scales the
@@ -290,22 +337,29 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
   constexpr int kRows = kT / (kBlock / 64);  // rows i > j a wave takes at most
   for (int j = 0; j < kT; ++j) {
     if (j > 0 && tid < kT) X[j - 1][tid] *= rprev;  // row j - 1 of L^{-1} is final
-    const double d = P[j][j];
-    const double r = d > kFacPivotTol ? 1.0 / sqrt(d) : 0.0;  // 0: skipped pivot
     // rows i = j + 1 + w + 4 q > j, a wave per row, a lane per column k <= i:
     // X (nonzero for k <= j) and the trailing lower part of P (j < k <= i).
     // The lane's factor (row j of X or column j of P) is the same for every
-    // row; the rows' column-j entries are all read before any update, so
-    // the loads issue together.
-    const double src = (k <= j ? X[j][k] : P[k][j]) * r;
+    // row; the rows' column-j entries and the entries to update are all read
+    // (at clamped rows) before any update, so the loads issue together and
+    // only the stores are predicated.  The loads do not wait for 1 / L_jj,
+    // which is computed without a branch (a skipped pivot multiplies by 0).
+    const double d = P[j][j];
+    const double pk = k <= j ? X[j][k] : P[k][j];
     double* __restrict__ dst = k <= j ? &X[0][k] : &P[0][k];
-    double l[kRows];
+    double l[kRows], v[kRows];
 #pragma unroll
-    for (int q = 0; q < kRows; ++q) l[q] = P[min(j + 1 + w + 4 * q, kT - 1)][j] * r;
+    for (int q = 0; q < kRows; ++q) {
+      const int ic = min(j + 1 + w + 4 * q, kT - 1);
+      l[q] = P[ic][j];
+      v[q] = dst[ic * (kT + 1)];
+    }
+    const double r = (1.0 / sqrt(fmax(d, kFacPivotTol))) * double(d > kFacPivotTol);  // 0: skipped pivot
+    const double src = pk * r;
 #pragma unroll
     for (int q = 0; q < kRows; ++q) {
       const int i = j + 1 + w + 4 * q;
-      if (i < kT && k <= i) dst[i * (kT + 1)] -= l[q] * src;
+      if (i < kT && k <= i) dst[i * (kT + 1)] = v[q] - (l[q] * r) * src;
     }
     __syncthreads();
     rprev = r;
@@ -342,28 +396,27 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
 // from the lower tile S_KI^T when I < K), W = Op L^{-T} (kept for the
 // update, in slot K mod 2), C = W L^{-1} = Op P^{-1} written back to S_IK
 // (S_KI^T).
-constexpr int kPLd = kT + 2;  // LDS row stride of the panel's 64 x 64 blocks
-
 __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
-  __shared__ double T[kT * kPLd];    // Op, then W, then C
-  __shared__ double Li[kT * kPLd];   // L^{-1}
-  __shared__ double LiT[kT * kPLd];  // L^{-T}
+  __shared__ double T[kT * kPLd];   // Op, then W, then C
+  __shared__ double Li[kT * kPLd];  // L^{-1}
   const int I = blockIdx.x < K ? blockIdx.x : blockIdx.x + 1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
   const bool below = I > K;
-  for (int e = tid; e < kT * kT; e += kBlock) {
-    const int a = e / kT, b = e % kT;
-    const double x = f.P[e];
-    Li[a * kPLd + b] = x;
-    LiT[b * kPLd + a] = x;
-  }
-  if (below) {
-    const double* __restrict__ src = f.S + size_t(I) * kT * f.mp + size_t(K) * kT;
-    for (int e = tid; e < kT * kT; e += kBlock) T[(e / kT) * kPLd + e % kT] = src[size_t(e / kT) * f.mp + e % kT];
-  } else {
-    const double* __restrict__ src = f.S + size_t(K) * kT * f.mp + size_t(I) * kT;
-    for (int e = tid; e < kT * kT; e += kBlock) T[(e % kT) * kPLd + e / kT] = src[size_t(e / kT) * f.mp + e % kT];
+  {
+    double vl[kPer], vt[kPer];
+    block_load(f.P, kT, vl);
+    block_load(below ? f.S + size_t(I) * kT * f.mp + size_t(K) * kT : f.S + size_t(K) * kT * f.mp + size_t(I) * kT,
+               f.mp, vt);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + kBlock * u, a = e / kT, b = e % kT;
+      Li[a * kPLd + b] = vl[u];
+      if (below)
+        T[a * kPLd + b] = vt[u];
+      else
+        T[b * kPLd + a] = vt[u];
+    }
   }
   __syncthreads();
   // W = Op L^{-T}: W_ic = sum_e Op_ie Li_ce (FP64 MFMA, 4 waves of 32 x 32)
@@ -388,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
       }
   __syncthreads();
   // C = W L^{-1}: C_ic = sum_e W_ie Li_ec
-  w_product<kT, kPLd>(T, LiT, wr, wc, li, kq, acc);
+  kn_product(T, Li, wr, wc, li, kq, acc);
   __syncthreads();
 #pragma unroll
   for (int a = 0; a < 2; ++a)
