@@ -446,19 +446,32 @@ def bench_dense_factor(args, cpu_proc):
     # Algorithmic work per launch:
     #   k_fac_syrk: the lower triangle of B B^T, m (m + 1) / 2 dot products of
     #     length n: m (m + 1) n flops;
-    #   k_fac_update (two sweep steps K, K + 1 a launch; the last step alone
-    #     when the block count is odd): every lower 64 x 64 tile of S outside
-    #     block row and column K + 1 read and written once (16 bytes an
-    #     entry) and the two 64-column panels W read once; 2 * 64 flops an
-    #     entry for each step's term (block row and column K take only step
-    #     K + 1's).  Per launch: the event's total over its launches;
+    #   k_fac_update (one pass over S per group of up to 4 sweep steps
+    #     K0 .. K0 + cnt - 1): every lower 64 x 64 tile of S outside block row
+    #     and column K0 + cnt - 1 read and written once (16 bytes an entry)
+    #     and the cnt 64-column panels W read once; 2 * 64 flops an entry for
+    #     each step's term the tile takes (a tile on the row of group block
+    #     K0 + h takes only the steps after it).  Per launch: the event's
+    #     total over its launches;
     #   k_fac_apply: M^{-1} once (FP64) and three m-vectors.
     nb = (m + 63) // 64
-    tiles = nb * (nb + 1) // 2
-    pairs, single = nb // 2, nb % 2
-    tile_flops = 2 * 64 * 64 * 64
-    upd_bytes = 16 * 64 * 64 * (tiles - nb) + (2 * pairs + single) * 8 * 64 * 64 * nb // (pairs + single)
-    upd_flops = tile_flops * (pairs * (2 * (tiles - 2 * nb + 1) + nb - 1) + single * (tiles - nb)) // (pairs + single)
+    group = 4
+    upd_bytes_sum = upd_flops_sum = 0
+    upd_launches = 0
+    low = np.tril(np.ones((nb, nb), dtype=bool))
+    for k0 in range(0, nb, group):
+        cnt = min(group, nb - k0)
+        h = np.full(nb, -1)
+        h[k0:k0 + cnt] = np.arange(cnt)
+        terms = cnt - 1 - np.maximum(h[:, None], h[None, :])
+        mask = low.copy()
+        mask[k0 + cnt - 1, :] = False
+        mask[:, k0 + cnt - 1] = False
+        upd_flops_sum += 2 * 64 ** 3 * int(terms[mask].sum())
+        upd_bytes_sum += 16 * 64 * 64 * int(mask.sum()) + cnt * 8 * 64 * 64 * nb
+        upd_launches += 1
+    upd_bytes = upd_bytes_sum // upd_launches
+    upd_flops = upd_flops_sum // upd_launches
     syrk_flops = m * (m + 1) * n
     apply_bytes = 8 * m * m + 8 * 3 * m
     cnt_s, ms_s = prof["syrk"]
@@ -480,8 +493,8 @@ def bench_dense_factor(args, cpu_proc):
                 "traffic": traffic_record("fac_syrk", "dense_lp", "acs_factor.hip"),
                 "avg_launch_ms": ms_s / max(cnt_s, 1), "launches": cnt_s, "algorithmic_flops_per_launch": syrk_flops}
     elif upd_flops / (FP64_PEAK_TFS * 1e12) >= upd_bytes / (HBM_PEAK_GBS * 1e9):
-        # two steps a pass over S: at the peaks its flops take longer than its bytes
-        roof = {"bound": "mfma", "kernel": "k_fac_update (two rank-64 sweep steps, FP64 MFMA)", "achieved": upd_tf,
+        # four steps a pass over S: at the peaks its flops take longer than its bytes
+        roof = {"bound": "mfma", "kernel": "k_fac_update (pass of four rank-64 sweep steps, FP64 MFMA)", "achieved": upd_tf,
                 "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": upd_tf / FP64_PEAK_TFS,
                 "traffic": traffic_record("fac_update", "dense_lp", "acs_factor.hip"),
                 "avg_launch_ms": ms_u / max(cnt_u, 1), "launches": cnt_u, "algorithmic_flops_per_launch": upd_flops,

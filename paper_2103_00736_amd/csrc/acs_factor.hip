@@ -196,12 +196,12 @@ __global__ __launch_bounds__(kSyrkThreads) __attribute__((amdgpu_waves_per_eu(4,
 // columns is column 16 h + 4 q + s).
 constexpr int kWc = 32;         // columns of a W block staged in LDS at a time
 constexpr int kWcLd = kWc + 2;  // LDS row stride of a staged chunk (doubles)
-enum UpdMode { kUpdOne = 0, kUpdStrip = 1, kUpdPair = 2 };
+enum UpdMode { kUpdStrip = 0, kUpdPass = 1 };
 
-// W = Op L^{-T} of sweep step K for row block I: two slots of mp x 64, so
-// that steps K and K + 1 are both available to the paired update
-__device__ __forceinline__ const double* w_block(const FacDev& f, int K, int I) {
-  return f.C + size_t(K & 1) * f.mp * kT + size_t(I) * kT * kT;
+// W = Op L^{-T} of sweep step K for row block I: kFacGroup slots of mp x 64,
+// so that all steps of a group are available to its pass
+__device__ __forceinline__ double* w_block(const FacDev& f, int K, int I) {
+  return f.C + size_t(K % kFacGroup) * f.mp * kT + size_t(I) * kT * kT;
 }
 
 // chunk q of the tile's W columns: term q / 2 (step K0 + q / 2), columns
@@ -311,9 +311,9 @@ __device__ __forceinline__ void block_load(const double* __restrict__ src, size_
 // or below kFacPivotTol is skipped: its column of L is zero), with the
 // forward substitution L X = I carried along in the same sweep (step j
 // finishes row j of X = L^{-1}; skipped pivots leave zero rows and columns).
-// Writes L^{-1} to f.P, S_KK <- -P^{-1} = -L^{-T} L^{-1} and a zero W block
-// for block K.
-__global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
+// Writes L^{-1} to f.P, S_KK <- -P^{-1} = -L^{-T} L^{-1}, and zero W blocks
+// for block K of every step K0 .. K of its group (see the update).
+__global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K, int K0) {
   __shared__ double P[kT][kT + 1];  // the trailing Schur complements; column j of L is P_:j / L_jj
   __shared__ double X[kT][kT + 1];  // L^{-1}: forward substitution of L X = I, row by row with L
   const int tid = threadIdx.x;
@@ -388,8 +388,10 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K) {
   for (int e = tid; e < kT * kT; e += kBlock) f.P[e] = X[e / kT][e % kT];
   // W of this step on block K itself is zero: the paired update then adds
   // nothing from this step to block row and column K
-  double* __restrict__ Wk = f.C + size_t(K & 1) * f.mp * kT + size_t(K) * kT * kT;
-  for (int e = tid; e < kT * kT; e += kBlock) Wk[e] = 0.0;
+  for (int s = K0; s <= K; ++s) {
+    double* __restrict__ Wk = w_block(f, s, K);
+    for (int e = tid; e < kT * kT; e += kBlock) Wk[e] = 0.0;
+  }
 }
 
 // Panel of block K, one workgroup per other row block I: Op = S_IK (read
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   w_product<kT, kPLd>(T, Li, wr, wc, li, kq, acc);
   __syncthreads();
-  double* __restrict__ Wg = f.C + size_t(K & 1) * f.mp * kT + size_t(I) * kT * kT;
+  double* __restrict__ Wg = w_block(f, K, I);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -459,17 +461,21 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
   }
 }
 
-// Trailing update on the lower 64 x 64 tile (I, J).  Sweep steps are taken in
-// pairs (K, K + 1) so that one pass over S applies two of them:
-//   strip (after step K's panel): the tiles of block row and column K + 1
-//          get step K's term, S_IJ -= W_I W_J^T (W of step K), so that
-//          step K + 1's pivot and panel see the updated values;
-//   pair  (after step K + 1's panel): every other tile gets both terms,
-//          S_IJ -= W_I W_J^T (step K) + W'_I W'_J^T (step K + 1), a rank-128
-//          product; on block row or column K the first term is zero (step
-//          K wrote its final values there, and W of step K on block K is
-//          zero);
-//   one   a single step K (the last block when the count is odd).
+// Trailing update on the lower 64 x 64 tiles.  Sweep steps are taken in
+// groups K0 .. K0 + cnt - 1 (cnt <= kFacGroup), so that one pass over S
+// applies the rank-64 terms W_I W_J^T of all of them:
+//   strip (after step K0 + g's panel, g + 1 < cnt): every tile of block row
+//          and column B = K0 + g + 1 takes the terms of steps K0 .. K0 + g,
+//          so that step B's pivot and panel see up-to-date values;
+//   pass  (after the group's last panel): every tile outside block row and
+//          column K0 + cnt - 1 takes the terms of all cnt steps.
+// Each tile must take each step's term once, and none on the block row and
+// column that step writes in final form.  Both follow from zero W blocks:
+// W of step s on block K is zero for s = K (its own pivot) and for s < K in
+// the group (zeroed by step K's pivot, after the strip that applied them to
+// block row K).  So every tile takes every available term, with no case
+// analysis.  The order was checked against the one-step sweep in a CPU
+// emulation.
 // The tile's S values are loaded first (their latency overlaps the staging
 // of the W blocks in LDS).  W columns are staged 32 at a time (35 KB of LDS,
 // three workgroups a CU at 164 registers), the next chunk fetched into
@@ -523,27 +529,24 @@ __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K
         St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li] = sv[a][b][v] - acc[a][b][v];
 }
 
-template <int kMode>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fac_update(FacDev f, int K) {
+template <int kMode, int kTerms>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fac_update(FacDev f, int K0) {
   __shared__ double Wi[kT * kWcLd];
   __shared__ double Wj[kT * kWcLd];
   int I, J;
-  if (kMode == kUpdStrip) {  // block row and column K + 1, all blocks but K
-    const int t = blockIdx.x, K1 = K + 1;
-    if (t == K) return;
-    I = t < K1 ? K1 : t;
-    J = t < K1 ? t : K1;
+  if (kMode == kUpdStrip) {  // block row and column B = K0 + kTerms, lower tiles (B, t) or (t, B)
+    const int t = blockIdx.x, B = K0 + kTerms;
+    I = max(t, B);
+    J = min(t, B);
   } else {
     const int tile = f.upd_order[blockIdx.x];
     if (tile < 0) return;
     I = tile >> 16;
     J = tile & 0xffff;
-    const int last = kMode == kUpdPair ? K + 1 : K;
+    const int last = K0 + kTerms - 1;
     if (I == last || J == last) return;
   }
-  // in a pair, tiles on block row or column K take step K's term as zero:
-  // W of step K on block K is zero (written by the pivot)
-  update_tile<kMode == kUpdPair ? 2 : 1>(f, I, J, K, Wi, Wj);
+  update_tile<kTerms>(f, I, J, K0, Wi, Wj);
 }
 
 // S <- -S on both triangles from the lower tiles (diagonal tiles from their
@@ -648,21 +651,30 @@ void launch_fac_syrk(const FacDev& f, hipStream_t st) {
   ACS_LAUNCH(k_fac_syrk, dim3(f.syrk_blocks), dim3(kSyrkThreads), 0, st, f);
 }
 
-void launch_fac_pivot_panel(const FacDev& f, int K, hipStream_t st) {
-  ACS_LAUNCH(k_fac_pivot, dim3(1), dim3(kBlock), 0, st, f, K);
+void launch_fac_pivot_panel(const FacDev& f, int K, int K0, hipStream_t st) {
+  ACS_LAUNCH(k_fac_pivot, dim3(1), dim3(kBlock), 0, st, f, K, K0);
   if (f.nb > 1) ACS_LAUNCH(k_fac_panel, dim3(f.nb - 1), dim3(kBlock), 0, st, f, K);
 }
 
-void launch_fac_update(const FacDev& f, int K, hipStream_t st) {
-  if (f.nb > 1) ACS_LAUNCH(k_fac_update<kUpdOne>, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
+void launch_fac_strip(const FacDev& f, int K0, int terms, hipStream_t st) {
+  static_assert(kFacGroup == 4, "one strip instance per term count below the group size");
+  switch (terms) {
+    case 1: ACS_LAUNCH((k_fac_update<kUpdStrip, 1>), dim3(f.nb), dim3(kBlock), 0, st, f, K0); break;
+    case 2: ACS_LAUNCH((k_fac_update<kUpdStrip, 2>), dim3(f.nb), dim3(kBlock), 0, st, f, K0); break;
+    case 3: ACS_LAUNCH((k_fac_update<kUpdStrip, 3>), dim3(f.nb), dim3(kBlock), 0, st, f, K0); break;
+    default: throw AcsError(ACS_ERR_ARG, "sweep strip: term count out of range");
+  }
 }
 
-void launch_fac_strip(const FacDev& f, int K, hipStream_t st) {
-  ACS_LAUNCH(k_fac_update<kUpdStrip>, dim3(f.nb), dim3(kBlock), 0, st, f, K);
-}
-
-void launch_fac_update_pair(const FacDev& f, int K, hipStream_t st) {
-  ACS_LAUNCH(k_fac_update<kUpdPair>, dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K);
+void launch_fac_pass(const FacDev& f, int K0, int terms, hipStream_t st) {
+  if (f.nb <= 1) return;
+  switch (terms) {
+    case 1: ACS_LAUNCH((k_fac_update<kUpdPass, 1>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
+    case 2: ACS_LAUNCH((k_fac_update<kUpdPass, 2>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
+    case 3: ACS_LAUNCH((k_fac_update<kUpdPass, 3>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
+    case 4: ACS_LAUNCH((k_fac_update<kUpdPass, 4>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
+    default: throw AcsError(ACS_ERR_ARG, "sweep pass: term count out of range");
+  }
 }
 
 void launch_fac_mirror(const FacDev& f, hipStream_t st) {

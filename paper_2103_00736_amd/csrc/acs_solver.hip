@@ -240,7 +240,8 @@ static int64_t factor_bytes(const Problem& p) {
   int32_t mp, ldb;
   factor_shape(p, &mp, &ldb);
   const int64_t orders = 4 * int64_t(fac_tile_order(mp / 128).size() + fac_tile_order((p.m + kFacTile - 1) / kFacTile).size());
-  return 8 * (int64_t(mp) * mp + int64_t(mp) * ldb + 2 * int64_t(mp) * kFacTile + kFacTile * kFacTile + mp) + orders +
+  return 8 * (int64_t(mp) * mp + int64_t(mp) * ldb + kFacGroup * int64_t(mp) * kFacTile + kFacTile * kFacTile + mp) +
+         orders +
          7 * 256;
 }
 
@@ -447,7 +448,7 @@ class Instance final : public InstanceBase {
     f.nb = (p.m + kFacTile - 1) / kFacTile;
     f.S = arena_.alloc<double>(size_t(f.mp) * f.mp);
     f.B = arena_.alloc<double>(size_t(f.mp) * f.ldb);
-    f.C = arena_.alloc<double>(2 * size_t(f.mp) * kFacTile);
+    f.C = arena_.alloc<double>(size_t(kFacGroup) * f.mp * kFacTile);
     f.P = arena_.alloc<double>(kFacTile * kFacTile);
     {
       const std::vector<int32_t> so = fac_tile_order(f.mp / 128), uo = fac_tile_order(f.nb);
@@ -470,20 +471,17 @@ class Instance final : public InstanceBase {
   void factorize() {
     timed(KC_COND, [&] { launch_fac_copy(d_, f_, st_); });
     timed(KC_FAC_SYRK, [&] { launch_fac_syrk(f_, st_); });
-    // steps in pairs: one pass over S per pair (the strip brings block K + 1
-    // up to date with step K before its pivot); an odd last step alone
-    int K = 0;
-    for (; K + 1 < f_.nb; K += 2) {
+    // steps in groups of kFacGroup: one pass over S per group (each strip
+    // brings the next block of the group up to date before its pivot)
+    for (int K0 = 0; K0 < f_.nb; K0 += kFacGroup) {
+      const int cnt = std::min(kFacGroup, f_.nb - K0);
       timed(KC_FAC_PANEL, [&] {
-        launch_fac_pivot_panel(f_, K, st_);
-        launch_fac_strip(f_, K, st_);
-        launch_fac_pivot_panel(f_, K + 1, st_);
+        for (int g = 0; g < cnt; ++g) {
+          launch_fac_pivot_panel(f_, K0 + g, K0, st_);
+          if (g + 1 < cnt) launch_fac_strip(f_, K0, g + 1, st_);
+        }
       });
-      timed(KC_FAC_UPDATE, [&] { launch_fac_update_pair(f_, K, st_); });
-    }
-    if (K < f_.nb) {
-      timed(KC_FAC_PANEL, [&] { launch_fac_pivot_panel(f_, K, st_); });
-      timed(KC_FAC_UPDATE, [&] { launch_fac_update(f_, K, st_); });
+      timed(KC_FAC_UPDATE, [&] { launch_fac_pass(f_, K0, cnt, st_); });
     }
     timed(KC_FAC_PANEL, [&] { launch_fac_mirror(f_, st_); });
     factored_ = true;
