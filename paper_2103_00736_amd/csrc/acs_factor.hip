@@ -196,12 +196,13 @@ __global__ __launch_bounds__(kSyrkThreads) __attribute__((amdgpu_waves_per_eu(4,
 // columns is column 16 h + 4 q + s).
 constexpr int kWc = 32;         // columns of a W block staged in LDS at a time
 constexpr int kWcLd = kWc + 2;  // LDS row stride of a staged chunk (doubles)
-enum UpdMode { kUpdStrip = 0, kUpdPass = 1 };
+enum UpdMode { kUpdStrip = 0, kUpdPass = 1, kUpdPassNext = 2, kUpdPassRest = 3 };
 
-// W = Op L^{-T} of sweep step K for row block I: kFacGroup slots of mp x 64,
-// so that all steps of a group are available to its pass
+// W = Op L^{-T} of sweep step K for row block I: kFacSlots slots of mp x 64,
+// so that all steps of a group are available to its pass while the next
+// group's panels write theirs
 __device__ __forceinline__ double* w_block(const FacDev& f, int K, int I) {
-  return f.C + size_t(K % kFacGroup) * f.mp * kT + size_t(I) * kT * kT;
+  return f.C + size_t(K % kFacSlots) * f.mp * kT + size_t(I) * kT * kT;
 }
 
 // chunk q of the tile's W columns: term q / 2 (step K0 + q / 2), columns
@@ -530,21 +531,29 @@ __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K
 }
 
 template <int kMode, int kTerms>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fac_update(FacDev f, int K0) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fac_update(FacDev f, int K0,
+                                                                                                 int nxt, int cntn) {
   __shared__ double Wi[kT * kWcLd];
   __shared__ double Wj[kT * kWcLd];
   int I, J;
+  const int last = K0 + kTerms - 1;
   if (kMode == kUpdStrip) {  // block row and column B = K0 + kTerms, lower tiles (B, t) or (t, B)
     const int t = blockIdx.x, B = K0 + kTerms;
     I = max(t, B);
     J = min(t, B);
+  } else if (kMode == kUpdPassNext) {  // block rows and columns b = nxt .. nxt + cntn - 1
+    const int b = nxt + int(blockIdx.x) / f.nb, t = int(blockIdx.x) % f.nb;
+    if (t >= nxt && t < nxt + cntn && t > b) return;  // a tile of two such blocks once
+    I = max(t, b);
+    J = min(t, b);
+    if (I == last || J == last) return;
   } else {
     const int tile = f.upd_order[blockIdx.x];
     if (tile < 0) return;
     I = tile >> 16;
     J = tile & 0xffff;
-    const int last = K0 + kTerms - 1;
     if (I == last || J == last) return;
+    if (kMode == kUpdPassRest && ((I >= nxt && I < nxt + cntn) || (J >= nxt && J < nxt + cntn))) return;
   }
   update_tile<kTerms>(f, I, J, K0, Wi, Wj);
 }
@@ -658,23 +667,46 @@ void launch_fac_pivot_panel(const FacDev& f, int K, int K0, hipStream_t st) {
 
 void launch_fac_strip(const FacDev& f, int K0, int terms, hipStream_t st) {
   static_assert(kFacGroup == 4, "one strip instance per term count below the group size");
+  const dim3 g(f.nb), b(kBlock);
   switch (terms) {
-    case 1: ACS_LAUNCH((k_fac_update<kUpdStrip, 1>), dim3(f.nb), dim3(kBlock), 0, st, f, K0); break;
-    case 2: ACS_LAUNCH((k_fac_update<kUpdStrip, 2>), dim3(f.nb), dim3(kBlock), 0, st, f, K0); break;
-    case 3: ACS_LAUNCH((k_fac_update<kUpdStrip, 3>), dim3(f.nb), dim3(kBlock), 0, st, f, K0); break;
+    case 1: ACS_LAUNCH((k_fac_update<kUpdStrip, 1>), g, b, 0, st, f, K0, 0, 0); break;
+    case 2: ACS_LAUNCH((k_fac_update<kUpdStrip, 2>), g, b, 0, st, f, K0, 0, 0); break;
+    case 3: ACS_LAUNCH((k_fac_update<kUpdStrip, 3>), g, b, 0, st, f, K0, 0, 0); break;
     default: throw AcsError(ACS_ERR_ARG, "sweep strip: term count out of range");
   }
 }
 
-void launch_fac_pass(const FacDev& f, int K0, int terms, hipStream_t st) {
-  if (f.nb <= 1) return;
+namespace {
+template <int kMode>
+void launch_pass_mode(const FacDev& f, int K0, int terms, int nxt, int cntn, dim3 g, hipStream_t st) {
+  const dim3 b(kBlock);
   switch (terms) {
-    case 1: ACS_LAUNCH((k_fac_update<kUpdPass, 1>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
-    case 2: ACS_LAUNCH((k_fac_update<kUpdPass, 2>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
-    case 3: ACS_LAUNCH((k_fac_update<kUpdPass, 3>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
-    case 4: ACS_LAUNCH((k_fac_update<kUpdPass, 4>), dim3(f.upd_blocks), dim3(kBlock), 0, st, f, K0); break;
+    case 1: ACS_LAUNCH((k_fac_update<kMode, 1>), g, b, 0, st, f, K0, nxt, cntn); break;
+    case 2: ACS_LAUNCH((k_fac_update<kMode, 2>), g, b, 0, st, f, K0, nxt, cntn); break;
+    case 3: ACS_LAUNCH((k_fac_update<kMode, 3>), g, b, 0, st, f, K0, nxt, cntn); break;
+    case 4: ACS_LAUNCH((k_fac_update<kMode, 4>), g, b, 0, st, f, K0, nxt, cntn); break;
     default: throw AcsError(ACS_ERR_ARG, "sweep pass: term count out of range");
   }
+}
+
+void check_next(const FacDev& f, int K0, int terms, int nxt, int cntn) {
+  if (cntn < 1 || cntn > kFacGroup || nxt < K0 + terms || nxt + cntn > f.nb)
+    throw AcsError(ACS_ERR_ARG, "sweep pass: next group out of range");
+}
+}  // namespace
+
+void launch_fac_pass(const FacDev& f, int K0, int terms, hipStream_t st) {
+  if (f.nb > 1) launch_pass_mode<kUpdPass>(f, K0, terms, f.nb, 0, dim3(f.upd_blocks), st);
+}
+
+void launch_fac_pass_next(const FacDev& f, int K0, int terms, int nxt, int cntn, hipStream_t st) {
+  check_next(f, K0, terms, nxt, cntn);
+  launch_pass_mode<kUpdPassNext>(f, K0, terms, nxt, cntn, dim3(cntn * f.nb), st);
+}
+
+void launch_fac_pass_rest(const FacDev& f, int K0, int terms, int nxt, int cntn, hipStream_t st) {
+  check_next(f, K0, terms, nxt, cntn);
+  launch_pass_mode<kUpdPassRest>(f, K0, terms, nxt, cntn, dim3(f.upd_blocks), st);
 }
 
 void launch_fac_mirror(const FacDev& f, hipStream_t st) {

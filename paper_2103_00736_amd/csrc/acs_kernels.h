@@ -173,6 +173,7 @@ struct Dev {
 constexpr int kFacTile = 64;        // pivot block and tile of the inversion sweep
 constexpr int kFacPad = 128;        // the order of M is padded to a multiple of this
 constexpr int kFacGroup = 4;        // sweep steps applied by one pass over the inverse
+constexpr int kFacSlots = 2 * kFacGroup;  // W panels: this group's and the next group's
 constexpr int kFacMaxOrder = 32768; // largest padded order (8 GiB of FP64)
 constexpr double kFacPivotTol = 1e-11;  // pivots at or below it (unit-diagonal M) count as dependent rows
 
@@ -183,7 +184,7 @@ struct FacDev {
   int32_t nb;   // pivot blocks swept: ceil(m / kFacTile)
   double* S;    // mp x mp: M, then -M^{-1} (lower tiles) during the sweep, then M^{-1} (full)
   double* B;    // mp x ldb: A_s in FP64, zero outside m x n
-  double* C;    // kFacGroup x mp x kFacTile: W = Op L^{-T} of sweep step K in slot K mod kFacGroup (Op the pivot-column panel)
+  double* C;    // kFacSlots x mp x kFacTile: W = Op L^{-T} of sweep step K in slot K mod kFacSlots (Op the pivot-column panel)
   double* P;    // kFacTile x kFacTile: L^{-1}, L the Cholesky factor of the current pivot block
   // workgroup -> tile tables (fac_tile_order) of the form step (128 x 128
   // tiles of mp) and of the sweep's update (64 x 64 tiles of nb blocks)
@@ -231,12 +232,18 @@ template <typename VT> void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipSt
 template <typename VT> void launch_fac_copy(const Dev<VT>& d, const FacDev& f, hipStream_t st);
 void launch_fac_syrk(const FacDev& f, hipStream_t st);
 // Sweep steps in groups K0, .., K0 + cnt - 1 (K0 a multiple of kFacGroup,
-// cnt <= kFacGroup): for g = 0 .. cnt - 1, launch_fac_pivot_panel(K0 + g),
-// then (g + 1 < cnt) launch_fac_strip with g + 1 terms; then one
-// launch_fac_pass with cnt terms.
+// cnt <= kFacGroup).  The group's chain: for g = 0 .. cnt - 1,
+// launch_fac_pivot_panel(K0 + g), then (g + 1 < cnt) launch_fac_strip with
+// g + 1 terms.  Then its pass with cnt terms: launch_fac_pass for the last
+// group; otherwise launch_fac_pass_next (the tiles of the next group's block
+// rows and columns, nxt .. nxt + cntn - 1), after which the next group's
+// chain may run on another stream alongside launch_fac_pass_rest (all other
+// tiles).
 void launch_fac_pivot_panel(const FacDev& f, int K, int K0, hipStream_t st);
 void launch_fac_strip(const FacDev& f, int K0, int terms, hipStream_t st);
 void launch_fac_pass(const FacDev& f, int K0, int terms, hipStream_t st);
+void launch_fac_pass_next(const FacDev& f, int K0, int terms, int nxt, int cntn, hipStream_t st);
+void launch_fac_pass_rest(const FacDev& f, int K0, int terms, int nxt, int cntn, hipStream_t st);
 void launch_fac_mirror(const FacDev& f, hipStream_t st);
 template <typename VT> void launch_fac_apply(const Dev<VT>& d, const FacDev& f, hipStream_t st);
 

@@ -240,7 +240,7 @@ static int64_t factor_bytes(const Problem& p) {
   int32_t mp, ldb;
   factor_shape(p, &mp, &ldb);
   const int64_t orders = 4 * int64_t(fac_tile_order(mp / 128).size() + fac_tile_order((p.m + kFacTile - 1) / kFacTile).size());
-  return 8 * (int64_t(mp) * mp + int64_t(mp) * ldb + kFacGroup * int64_t(mp) * kFacTile + kFacTile * kFacTile + mp) +
+  return 8 * (int64_t(mp) * mp + int64_t(mp) * ldb + kFacSlots * int64_t(mp) * kFacTile + kFacTile * kFacTile + mp) +
          orders +
          7 * 256;
 }
@@ -331,6 +331,12 @@ class Instance final : public InstanceBase {
 
   ~Instance() override {
     if (st_) (void)hipStreamSynchronize(st_);
+    if (st2_) {
+      (void)hipStreamSynchronize(st2_);
+      (void)hipStreamDestroy(st2_);
+    }
+    if (fork_) (void)hipEventDestroy(fork_);
+    if (join_) (void)hipEventDestroy(join_);
     for (auto* v : {&prof_pending_, &prof_free_})
       for (auto& e : *v) {
         (void)hipEventDestroy(e.a);
@@ -448,7 +454,12 @@ class Instance final : public InstanceBase {
     f.nb = (p.m + kFacTile - 1) / kFacTile;
     f.S = arena_.alloc<double>(size_t(f.mp) * f.mp);
     f.B = arena_.alloc<double>(size_t(f.mp) * f.ldb);
-    f.C = arena_.alloc<double>(size_t(kFacGroup) * f.mp * kFacTile);
+    f.C = arena_.alloc<double>(size_t(kFacSlots) * f.mp * kFacTile);
+    // the next group's pivots, panels and strips run on a second stream
+    // (default priority) alongside the current group's pass
+    HIP_CHECK(hipStreamCreateWithFlags(&st2_, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
     f.P = arena_.alloc<double>(kFacTile * kFacTile);
     {
       const std::vector<int32_t> so = fac_tile_order(f.mp / 128), uo = fac_tile_order(f.nb);
@@ -471,17 +482,43 @@ class Instance final : public InstanceBase {
   void factorize() {
     timed(KC_COND, [&] { launch_fac_copy(d_, f_, st_); });
     timed(KC_FAC_SYRK, [&] { launch_fac_syrk(f_, st_); });
-    // steps in groups of kFacGroup: one pass over S per group (each strip
-    // brings the next block of the group up to date before its pivot)
-    for (int K0 = 0; K0 < f_.nb; K0 += kFacGroup) {
-      const int cnt = std::min(kFacGroup, f_.nb - K0);
-      timed(KC_FAC_PANEL, [&] {
-        for (int g = 0; g < cnt; ++g) {
-          launch_fac_pivot_panel(f_, K0 + g, K0, st_);
-          if (g + 1 < cnt) launch_fac_strip(f_, K0, g + 1, st_);
+    // Steps in groups of kFacGroup: one pass over S per group (each strip
+    // brings the next block of the group up to date before its pivot).  The
+    // pass first updates the next group's block rows and columns; the next
+    // group's chain of pivots, panels and strips (latency-bound, a few
+    // workgroups) then runs on the second stream while the rest of the pass
+    // runs here.  They touch disjoint tiles and W slots; the next pass waits
+    // for the chain.  The chain's launches are not part of the pass's timing.
+    const int nb = f_.nb;
+    auto chain = [&](int K0, hipStream_t s) {
+      const int cnt = std::min(kFacGroup, nb - K0);
+      for (int g = 0; g < cnt; ++g) {
+        launch_fac_pivot_panel(f_, K0 + g, K0, s);
+        if (g + 1 < cnt) launch_fac_strip(f_, K0, g + 1, s);
+      }
+    };
+    timed(KC_FAC_PANEL, [&] { chain(0, st_); });
+    for (int K0 = 0; K0 < nb; K0 += kFacGroup) {
+      const int cnt = std::min(kFacGroup, nb - K0), nxt = K0 + kFacGroup;
+      if (nxt >= nb) {
+        timed(KC_FAC_UPDATE, [&] { launch_fac_pass(f_, K0, cnt, st_); });
+        continue;
+      }
+      const int cntn = std::min(kFacGroup, nb - nxt);
+      timed(KC_FAC_UPDATE, [&] {
+        launch_fac_pass_next(f_, K0, cnt, nxt, cntn, st_);
+        HIP_CHECK(hipEventRecord(fork_, st_));
+        HIP_CHECK(hipStreamWaitEvent(st2_, fork_, 0));
+        {
+          LaunchEvents* timing = launch_events();
+          launch_events() = nullptr;
+          chain(nxt, st2_);
+          launch_events() = timing;
         }
+        HIP_CHECK(hipEventRecord(join_, st2_));
+        launch_fac_pass_rest(f_, K0, cnt, nxt, cntn, st_);
       });
-      timed(KC_FAC_UPDATE, [&] { launch_fac_pass(f_, K0, cnt, st_); });
+      HIP_CHECK(hipStreamWaitEvent(st_, join_, 0));
     }
     timed(KC_FAC_PANEL, [&] { launch_fac_mirror(f_, st_); });
     factored_ = true;
@@ -963,6 +1000,8 @@ class Instance final : public InstanceBase {
   bool fac_ = false;       // direct projection
   bool factored_ = false;  // M^{-1} matches the current scaling
   FacDev f_{};
+  hipStream_t st2_ = nullptr;                     // the next sweep group's chain
+  hipEvent_t fork_ = nullptr, join_ = nullptr;    // pass -> chain, chain -> next pass
   HostStatus* hs_ = nullptr;
   uint32_t prof_mask_ = 0;  // kernel classes timed with events
   std::vector<ProfEv> prof_pending_, prof_free_;

@@ -107,17 +107,17 @@ def test_device_byte_estimates_are_host_code():
 
 def test_factor_bytes():
     """The direct projection's extra memory: M (mp x mp) and the FP64 copy of A
-    (mp x ldb) with mp = m rounded up to 128 and ldb = n rounded up to 64, four
-    mp x 64 panels (the sweep steps of one group)."""
+    (mp x ldb) with mp = m rounded up to 128 and ldb = n rounded up to 64, eight
+    mp x 64 panels (the sweep steps of two groups)."""
     p = synth.lp_uniform(200, 500, 2000, 4)
     h = acs.Problem.from_synth(p)
     mp, ldb = 256, 512
-    want = 8 * (mp * mp + mp * ldb + 4 * mp * 64 + 64 * 64 + mp)
+    want = 8 * (mp * mp + mp * ldb + 8 * mp * 64 + 64 * 64 + mp)
     assert want <= h.factor_bytes() <= want + 8192
     h.close()
     d = synth.e3_lp(300)  # dense: m = 240, leading dimension 320
     hd = acs.Problem.from_synth(d)
     mp, ldb = 256, 320
-    want = 8 * (mp * mp + mp * ldb + 4 * mp * 64 + 64 * 64 + mp)
+    want = 8 * (mp * mp + mp * ldb + 8 * mp * 64 + 64 * 64 + mp)
     assert want <= hd.factor_bytes() <= want + 8192
     hd.close()
