@@ -8,7 +8,7 @@ A step is one outer iteration of Algorithm 2 (cone reflection, residual,
 warm-started CG projection, fused update; conditioning at l in L, a KKT check
 every `check_every` iterations).  Inputs are resident in HBM before timing.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the solver runs on
 one GPU.
 """
 import argparse
@@ -164,7 +164,7 @@ def main():
         cpu_child(args)
         return 0
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
     cpu_proc = (None if (args.no_cpu_baseline or args.workload in ("serve", "copy", "gather"))
                 else start_cpu_baseline(args))
