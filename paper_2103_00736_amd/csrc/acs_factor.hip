@@ -24,9 +24,10 @@
 //          column: the result is then the inverse on the other rows, with
 //          the oracle's pseudo-inverse's projection.  The trailing update is
 //          an FP64 MFMA product on the lower 64 x 64 tiles; steps are taken
-//          in pairs, so that one pass over S applies the rank-64 terms of
-//          two steps (the block row of the second step is brought up to date
-//          first, before its pivot).
+//          in groups of four, so that one pass over S applies the rank-64
+//          terms of four steps (each block row of the group is brought up to
+//          date before its pivot), and the next group's pivots and panels
+//          run on a second stream alongside the pass.
 //   mirror S <- -S, both triangles.
 //   apply  w += S r64 (FP64 rows, HBM-bound).
 #include <algorithm>
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_fac_pivot(FacDev f, int K, int K0) {
 
 // Panel of block K, one workgroup per other row block I: Op = S_IK (read
 // from the lower tile S_KI^T when I < K), W = Op L^{-T} (kept for the
-// update, in slot K mod 2), C = W L^{-1} = Op P^{-1} written back to S_IK
+// update, in slot K mod kFacSlots), C = W L^{-1} = Op P^{-1} written back to S_IK
 // (S_KI^T).
 __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
   __shared__ double T[kT * kPLd];   // Op, then W, then C
