@@ -268,7 +268,7 @@ def test_factor_full_solve(make, prec):
         assert abs(rec["pobj"] - p.p_star) <= 1e-3 * (1 + abs(p.p_star))
 
 
-@pytest.mark.parametrize("m", [1, 63, 64, 65, 127, 128, 129, 200, 257])
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 127, 128, 129, 200, 257, 500])
 def test_factor_tile_boundaries(m):
     """Orders around the 64-row pivot blocks and the 128-row padding, with
     odd and even block counts (steps are swept in pairs)."""
@@ -289,6 +289,31 @@ def test_factor_tile_boundaries(m):
     print(m, f"kappa {kappa:.2e} inverse {err:.2e} s {serr:.2e} bar {bar:.1e}")
     assert err <= 1e-14 * kappa * m + 1e-15
     assert serr <= bar
+
+
+@pytest.mark.parametrize("n", [700, 2500])
+def test_factor_sweep_bitwise_reproducible(n):
+    """The sweep's passes run beside the next group's pivots, panels and strips
+    on a second stream; the two touch disjoint tiles and W panels, so the
+    inverse is the same bit for bit on a refactorization and in a fresh state
+    (9 and 32 pivot blocks: one and seven overlapped groups)."""
+    p = synth.e3_lp(n)
+    s_prev, s, O, w = _random_state(p, 3)
+    h = acs.Problem.from_synth(p)
+    st = acs.State(h, precision=acs.PREC_FP64, **FACTOR)
+    st.set(57, s_prev, s, O, w)
+    X1 = st.normal_inverse()
+    st.set(57, s_prev, s, O, w)
+    X2 = st.normal_inverse()
+    st2 = acs.State(h, precision=acs.PREC_FP64, **FACTOR)
+    st2.set(57, s_prev, s, O, w)
+    X3 = st2.normal_inverse()
+    st.close()
+    st2.close()
+    h.close()
+    assert np.isfinite(X1).all()
+    assert np.array_equal(X1, X2)
+    assert np.array_equal(X1, X3)
 
 
 def test_factor_dependent_rows_solve():
