@@ -478,11 +478,10 @@ __global__ __launch_bounds__(kBlock) void k_fac_panel(FacDev f, int K) {
 // block row K).  So every tile takes every available term, with no case
 // analysis.  The order was checked against the one-step sweep in a CPU
 // emulation.
-// W columns are staged 32 at a time (35 KB of LDS), the next chunk fetched
-// into registers while the current chunk's MFMAs run; the tile's S values
-// are fetched into the same registers during the last chunk's MFMAs.  That
-// keeps the kernel within 128 registers, so four workgroups share a CU and
-// one's loads overlap the others' MFMAs.
+// The tile's S values are loaded first (their latency overlaps the staging
+// of the W blocks in LDS).  W columns are staged 32 at a time (35 KB of LDS,
+// three workgroups a CU at 164 registers), the next chunk fetched into
+// registers while the current chunk's MFMAs run.
 // S_IJ -= sum over kTerms steps K0, K0 + 1, .. of W_I W_J^T, the W columns
 // staged 32 at a time, the next chunk fetched into registers during the
 // current chunk's MFMAs
@@ -492,6 +491,12 @@ __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K
   const int wr = wave >> 1, wc = wave & 1, li = lane & 15, kq = lane >> 4;
   double* __restrict__ St = f.S + size_t(I) * kT * f.mp + size_t(J) * kT;
   double sv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sv[a][b][v] = St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li];
   const int r = tid >> 4, c = (tid & 15) * 2;  // staging: rows r + 16 q, columns c, c + 1
   d8 xi = w_fetch(w_chunk(f, K0, 0, I), r, c), xj = w_fetch(w_chunk(f, K0, 0, J), r, c);
   w_stage(Wi, r, c, xi);
@@ -508,14 +513,6 @@ __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K
     if (q + 1 < kChunks) {
       xi = w_fetch(w_chunk(f, K0, q + 1, I), r, c);
       xj = w_fetch(w_chunk(f, K0, q + 1, J), r, c);
-    } else {  // the tile's S values, in the registers the W fetches used
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            sv[a][b][v] = St[size_t(wr * 32 + a * 16 + kq + 4 * v) * f.mp + wc * 32 + b * 16 + li];
     }
     w_product(Wi, Wj, wr, wc, li, kq, acc);
     if (q + 1 < kChunks) {
@@ -535,7 +532,7 @@ __device__ __forceinline__ void update_tile(const FacDev& f, int I, int J, int K
 }
 
 template <int kMode, int kTerms>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_fac_update(FacDev f, int K0,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fac_update(FacDev f, int K0,
                                                                                                  int nxt, int cntn) {
   __shared__ double Wi[kT * kWcLd];
   __shared__ double Wj[kT * kWcLd];
