@@ -455,11 +455,6 @@ class Instance final : public InstanceBase {
     f.S = arena_.alloc<double>(size_t(f.mp) * f.mp);
     f.B = arena_.alloc<double>(size_t(f.mp) * f.ldb);
     f.C = arena_.alloc<double>(size_t(kFacSlots) * f.mp * kFacTile);
-    // the next group's pivots, panels and strips run on a second stream
-    // (default priority) alongside the current group's pass
-    HIP_CHECK(hipStreamCreateWithFlags(&st2_, hipStreamNonBlocking));
-    HIP_CHECK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
-    HIP_CHECK(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
     f.P = arena_.alloc<double>(kFacTile * kFacTile);
     {
       const std::vector<int32_t> so = fac_tile_order(f.mp / 128), uo = fac_tile_order(f.nb);
@@ -476,6 +471,12 @@ class Instance final : public InstanceBase {
     d_.r64 = arena_.alloc<double>(f.mp);
     // entries of the residual beyond m stay zero
     HIP_CHECK(hipMemsetAsync(d_.r64, 0, sizeof(double) * f.mp, st_));
+    // the next group's pivots, panels and strips run on a second stream
+    // (default priority) alongside the current group's pass; created after
+    // the allocations, so that a failed allocation does not leave them behind
+    HIP_CHECK(hipStreamCreateWithFlags(&st2_, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
   }
 
   // M = A_s A_s^T of the current scaling and its inverse
