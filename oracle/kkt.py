@@ -13,6 +13,23 @@ x^T z = 0; x, z in K) as relative errors:
     eps_K = max(dist(x, K), dist(z, K)) / (1 + max(||x||, ||z||))
     kkt   = max(eps_p, eps_d, eps_g, eps_K)
 
+Those terms are normalised by the norms of b and c, so a point that meets
+them can still carry a larger relative error in the objective.  Weak duality
+(Sec. II) bounds that error.  With r_p = A x - b and r_d = A^T y + z - c, for
+any optimal pair (x*, y*, z*) and x, z in K:
+
+    c^T x - p* = z*^T x + y*^T r_p            >= y*^T r_p
+    c^T x - p* = (c^T x - b^T y) + r_d^T x* - z^T x*  <= (c^T x - b^T y) + r_d^T x*
+
+(expand c = A^T y + z - r_d and b = A x - r_p; z^T x*, z*^T x >= 0 on K).
+Replacing (x*, y*) by the current (x, y) changes each bound by a product of
+two small quantities, which gives the estimate
+
+    eps_obj = max(|y^T r_p|, |c^T x - b^T y + r_d^T x|) / (1 + |c^T x|)
+
+of |c^T x - p*| / (1 + |c^T x|).  `objective_bounds` returns the two exact
+bounds for a known optimum, used to pin the estimate.
+
 `dual_multiplier_ls` gives the multiplier implicit in eq. stopcri's dual
 objective (A^dagger b)^T (c - z) = b^T (A A^T)^+ A (c - z).
 """
@@ -36,13 +53,30 @@ def kkt_errors(A: sp.csr_matrix, b: np.ndarray, c: np.ndarray, n_orth: int, soc_
     c = np.asarray(c, dtype=np.float64)
     pobj = float(c @ x)
     dobj = float(b @ y)
-    eps_p = float(np.linalg.norm(A @ x - b)) / (1.0 + float(np.linalg.norm(b)))
-    eps_d = float(np.linalg.norm(A.T @ y + z - c)) / (1.0 + float(np.linalg.norm(c)))
+    rp = A @ x - b
+    rd = A.T @ y + z - c
+    eps_p = float(np.linalg.norm(rp)) / (1.0 + float(np.linalg.norm(b)))
+    eps_d = float(np.linalg.norm(rd)) / (1.0 + float(np.linalg.norm(c)))
     eps_g = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
     eps_k = max(dist_K(x, n_orth, soc_sizes), dist_K(z, n_orth, soc_sizes)) / (
         1.0 + max(float(np.linalg.norm(x)), float(np.linalg.norm(z))))
+    eps_obj = max(abs(float(y @ rp)), abs(pobj - dobj + float(rd @ x))) / (1.0 + abs(pobj))
     return {"eps_p": eps_p, "eps_d": eps_d, "eps_g": eps_g, "eps_k": eps_k,
-            "kkt": max(eps_p, eps_d, eps_g, eps_k), "pobj": pobj, "dobj": dobj}
+            "kkt": max(eps_p, eps_d, eps_g, eps_k), "pobj": pobj, "dobj": dobj, "eps_obj": eps_obj}
+
+
+def objective_bounds(A: sp.csr_matrix, b: np.ndarray, c: np.ndarray, x: np.ndarray, y: np.ndarray,
+                     z: np.ndarray, x_opt: np.ndarray, y_opt: np.ndarray):
+    """(lower, upper) with lower <= c^T x - p* <= upper for x, z in K and an
+    optimal pair (x_opt, y_opt): lower = y*^T r_p, upper = c^T x - b^T y +
+    r_d^T x* (weak duality, see the module header)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    rp = A @ x - np.asarray(b, dtype=np.float64)
+    rd = A.T @ y + z - np.asarray(c, dtype=np.float64)
+    gap = float(np.asarray(c) @ x) - float(np.asarray(b) @ y)
+    return float(np.asarray(y_opt) @ rp), gap + float(rd @ np.asarray(x_opt))
 
 
 def dual_multiplier_ls(A: sp.csr_matrix, c: np.ndarray, z: np.ndarray) -> np.ndarray:

@@ -8,9 +8,11 @@ import pytest
 
 import oracle.alg2 as alg2
 import oracle.cones as cones
+import oracle.kkt as kkt
 import oracle.subspace as subspace
 from tests import test_oracle_alg2 as P2
 from tests import test_oracle_cones as PC
+from tests import test_oracle_kkt as PK
 from tests import test_oracle_subspace as PS
 
 PINS = [
@@ -33,6 +35,10 @@ PINS = [
     lambda: P2.test_algorithm1_is_douglas_rachford(True),
     P2.test_paper_example_reaches_vertex_optimum,
     P2.test_fused_update_identity,
+    P2.test_kkt_at_planted_point_and_ls_multiplier,
+    PK.test_cone_distance_closed_forms,
+    PK.test_kkt_terms_at_a_constructed_point,
+    PK.test_objective_bounds_hold_exactly_on_the_cone,
 ]
 
 
@@ -88,6 +94,30 @@ def _mut_no_cap(o_raw, t):
 
 
 alg2_orig_ratio = alg2.conditioning_ratio
+kkt_orig_errors = kkt.kkt_errors
+
+
+def _mut_dist_squared(v, n_orth, soc_sizes):
+    d = np.asarray(v, dtype=np.float64) - cones.proj_K(v, n_orth, soc_sizes)
+    return float(d @ d)  # squared distance
+
+
+def _mut_dual_residual_sign(A, b, c, n_orth, soc_sizes, x, y, z):
+    return kkt_orig_errors(A, b, c, n_orth, soc_sizes, x, y, -np.asarray(z))  # A^T y - z - c
+
+
+def _mut_objective_drops_rd(A, b, c, n_orth, soc_sizes, x, y, z):
+    rec = kkt_orig_errors(A, b, c, n_orth, soc_sizes, x, y, z)
+    rp = A @ np.asarray(x) - b
+    rec["eps_obj"] = max(abs(float(np.asarray(y) @ rp)), abs(rec["pobj"] - rec["dobj"])) / (1 + abs(rec["pobj"]))
+    return rec
+
+
+def _mut_objective_bounds_sign(A, b, c, x, y, z, x_opt, y_opt):
+    rp = A @ np.asarray(x) - b
+    rd = A.T @ np.asarray(y) + np.asarray(z) - c
+    gap = float(c @ x) - float(b @ y)
+    return float(np.asarray(y_opt) @ rp), gap - float(rd @ np.asarray(x_opt))
 
 
 def _patched_step(kind):
@@ -152,6 +182,10 @@ MUTATIONS = {
     "step 19 without O": (alg2.Algorithm2, "step", _patched_step("x_without_O")[0]),
     "step 14 scaling inverted": (alg2.Algorithm2, "condition", _patched_condition_recast()),
     "step 13 drops (AO)^dagger b": (alg2.Algorithm2, "condition", _patched_condition_no_pinv_b()),
+    "cone distance squared": (cones, "dist_K", _mut_dist_squared),
+    "dual residual with -z": (kkt, "kkt_errors", _mut_dual_residual_sign),
+    "objective estimate drops r_d^T x": (kkt, "kkt_errors", _mut_objective_drops_rd),
+    "objective bound with -r_d": (kkt, "objective_bounds", _mut_objective_bounds_sign),
 }
 
 
@@ -164,7 +198,7 @@ def test_mutation_is_caught(name, monkeypatch):
     target, attr, repl = MUTATIONS[name]
     monkeypatch.setattr(target, attr, repl)
     # modules that imported the name directly see the mutation too
-    for mod in (alg2, subspace, P2, PC, PS):
-        if hasattr(mod, attr) and mod is not target and callable(getattr(mod, attr)) and target in (cones, alg2):
+    for mod in (alg2, kkt, subspace, P2, PC, PK, PS):
+        if hasattr(mod, attr) and mod is not target and callable(getattr(mod, attr)) and target in (cones, alg2, kkt):
             monkeypatch.setattr(mod, attr, repl)
     assert _caught(), f"no pin caught: {name}"
