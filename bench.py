@@ -166,6 +166,13 @@ def main():
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
+    profiled = sorted(k for k in os.environ if k.startswith("ROCPROF"))
+    if profiled and not args.no_cpu_baseline:
+        # under a profiler the oracle child would start from a process the
+        # profiler's library has attached to the GPU: never start it there
+        print(f"bench.py: profiler environment ({profiled[0]}, ...) present: CPU baseline skipped",
+              file=sys.stderr, flush=True)
+        args.no_cpu_baseline = True
     cpu_proc = (None if (args.no_cpu_baseline or args.workload in ("serve", "copy", "gather"))
                 else start_cpu_baseline(args))
     if args.workload == "batch":

@@ -80,8 +80,9 @@ extern "C" {
  * With `auto_params` = 1 the library picks the paper's per-class values:
  * LP: t = 9.2, L = {300, 400, ...}; SOCP: t = 1.7, L = {200, 300, ...}; mu = 1.
  * Projection (Alg. 2 step 17) by warm-started CG, defaults cg_reduce = 0.1,
- * cg_max = 500.  The iteration just before a conditioning event (its x, z set
- * O) runs its CG to a 1e-6 reduction with up to 8 cg_max steps.  A cap that
+ * cg_max = 500; obj_stop = 1.  The iteration just before a conditioning
+ * event (its x, z set O) runs its CG to a 1e-6 reduction with up to 8 cg_max
+ * steps.  A cap that
  * stops the CG short of cg_reduce leaves an error the outer iteration may not
  * recover from once O is spread; smaller cg_reduce trades CG steps for outer
  * iterations (0.03 solves the 2M-variable LP fastest).
@@ -102,13 +103,22 @@ typedef struct acs_settings {
   double cg_abs;        /* ... or once ||r|| <= cg_abs (scaled system)          */
   int32_t verbose;      /* 0 quiet, 1 one line per check on stderr              */
   int32_t projection;   /* ACS_PROJ_CG (default) or ACS_PROJ_FACTOR              */
-  int32_t reserved[6];
+  int32_t obj_stop;     /* 1 (default): a check also needs eps_obj <= eps_kkt     */
+  int32_t reserved[5];
 } acs_settings;
 
 /* Per-solve report.  KKT errors follow the oracle's definition:
  *   eps_p = ||Ax-b||/(1+||b||), eps_d = ||A^T y+z-c||/(1+||c||),
  *   eps_gap = |c^T x - b^T y|/(1+|c^T x|+|b^T y|),
- *   eps_cone = max(dist(x,K), dist(z,K))/(1+max(||x||,||z||)).         */
+ *   eps_cone = max(dist(x,K), dist(z,K))/(1+max(||x||,||z||)).
+ * Those are relative to the norms of b and c, so they do not bound the
+ * relative error of the objective.  Weak duality (Sec. II) does: with
+ * r_p = Ax-b and r_d = A^T y+z-c, c^T x - p* lies between y*^T r_p and
+ * c^T x - b^T y + r_d^T x* for x, z in K, which the current (x, y) estimate
+ * up to second-order terms:
+ *   eps_obj = max(|y^T r_p|, |c^T x - b^T y + r_d^T x|)/(1+|c^T x|).
+ * With settings.obj_stop = 1 a solve stops only when kkt <= eps_kkt and
+ * eps_obj <= eps_kkt.                                                     */
 typedef struct acs_info {
   int32_t status;       /* ACS_SOLVED / ACS_MAX_ITER / ACS_NUMERIC / ACS_CANCELLED */
   int32_t iterations;   /* outer iterations run                                */
@@ -123,7 +133,8 @@ typedef struct acs_info {
   double o_range;       /* log(max O) - log(min O) after the last conditioning */
   double queue_ms;      /* server: submit -> admission                         */
   double latency_ms;    /* server: submit -> result ready                      */
-  double reserved[4];
+  double eps_obj;       /* objective-error estimate of the last check (above)  */
+  double reserved[3];
 } acs_info;
 
 typedef struct acs_problem acs_problem;
@@ -180,6 +191,18 @@ int64_t acs_batch_device_bytes(const acs_problem* p);
  */
 int acs_solve(const acs_problem* p, const acs_settings* s, double* x, double* y, double* z, acs_info* info,
               void* stream);
+
+/*
+ * The same solve with DEVICE outputs: x, z (n doubles) and y (m doubles, the
+ * caller's row order) are caller-owned device allocations (e.g. torch
+ * tensors; any may be NULL), written by a kernel on `stream` (e.g. torch's
+ * current stream; NULL = the library's own).  Results are bitwise those of
+ * acs_solve.  Returns after they are written (synchronises with `stream`).
+ * A pointer that is not a device allocation gives ACS_ERR_ARG before any
+ * GPU work.
+ */
+int acs_solve_device(const acs_problem* p, const acs_settings* s, double* x, double* y, double* z, acs_info* info,
+                     void* stream);
 
 /*
  * Solver state on the GPU (resident iterate and scalings; tests, benchmarks
@@ -269,6 +292,13 @@ int acs_batch_autotune(acs_batch* b, int32_t sample, int32_t iters, const char* 
 int acs_batch_run(acs_batch* b, int32_t iter_budget, int32_t use_graph, double* ms);
 /* Host outputs of instance i (any may be NULL); x, z length n_i, y length m_i. */
 int acs_batch_result(acs_batch* b, int32_t i, double* x, double* y, double* z, acs_info* info);
+/* Resident state of instance i (HOST outputs, any may be NULL): the
+ * iterations run, s_prev and s (FP32 iterates widened to double), O (n), w
+ * (unscaled, y = -w/mu) and the row norms sqrt(D_i) of the current scaling
+ * (m, the caller's row order), as acs_state_get reports them for one
+ * instance.  Synchronises with the batch's stream.  Tests and checkpoints. */
+int acs_batch_state_get(acs_batch* b, int32_t i, int32_t* l, double* s_prev, double* s, double* O, double* w,
+                        double* dsq);
 /* Sweep schedule chosen for instance i (rows of A and of A^T): G > 0 lanes per
  * row reading the matrix directly, or -S for LDS-staged row blocks of at most
  * S nonzeros. */

@@ -33,10 +33,12 @@ PROF_ALL = (1 << 13) - 1  # ACS_PROF_ALL
 
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
-    "acs_problem_destroy", "acs_problem_create_dense", "acs_problem_device_bytes", "acs_problem_factor_bytes", "acs_batch_device_bytes", "acs_solve", "acs_state_create", "acs_state_destroy",
+    "acs_problem_destroy", "acs_problem_create_dense", "acs_problem_device_bytes", "acs_problem_factor_bytes",
+    "acs_batch_device_bytes", "acs_solve", "acs_solve_device", "acs_state_create", "acs_state_destroy",
     "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
     "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_state_normal_inverse", "acs_batch_create", "acs_batch_destroy",
-    "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_lanes", "acs_batch_solve",
+    "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_state_get", "acs_batch_lanes",
+    "acs_batch_solve",
     "acs_server_create", "acs_server_destroy", "acs_server_submit", "acs_server_poll", "acs_server_wait",
     "acs_server_cancel", "acs_server_stats",
 ]
@@ -55,7 +57,7 @@ class Settings(ctypes.Structure):
         ("auto_params", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("eps_kkt", ctypes.c_double), ("precision", ctypes.c_int32), ("cg_max", ctypes.c_int32),
         ("cg_reduce", ctypes.c_double), ("cg_abs", ctypes.c_double), ("verbose", ctypes.c_int32),
-        ("projection", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+        ("projection", ctypes.c_int32), ("obj_stop", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -67,7 +69,7 @@ class Info(ctypes.Structure):
         ("eps_cone", ctypes.c_double), ("kkt", ctypes.c_double), ("pobj", ctypes.c_double),
         ("dobj", ctypes.c_double), ("solve_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
         ("alpha", ctypes.c_double), ("o_range", ctypes.c_double), ("queue_ms", ctypes.c_double),
-        ("latency_ms", ctypes.c_double), ("reserved", ctypes.c_double * 4),
+        ("latency_ms", ctypes.c_double), ("eps_obj", ctypes.c_double), ("reserved", ctypes.c_double * 3),
     ]
 
     def as_dict(self) -> dict:
@@ -117,6 +119,7 @@ def lib() -> ctypes.CDLL:
         "acs_problem_factor_bytes": (ctypes.c_int64, [P]),
         "acs_batch_device_bytes": (ctypes.c_int64, [P]),
         "acs_solve": (ctypes.c_int, [P, ctypes.POINTER(Settings), DP, DP, DP, ctypes.POINTER(Info), P]),
+        "acs_solve_device": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, P, P, ctypes.POINTER(Info), P]),
         "acs_state_create": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, ctypes.POINTER(P)]),
         "acs_state_destroy": (None, [P]),
         "acs_state_set": (ctypes.c_int, [P, ctypes.c_int32, DP, DP, DP, DP]),
@@ -136,6 +139,7 @@ def lib() -> ctypes.CDLL:
         "acs_batch_run": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, DP]),
         "acs_batch_result": (ctypes.c_int, [P, ctypes.c_int32, DP, DP, DP, ctypes.POINTER(Info)]),
         "acs_batch_lanes": (ctypes.c_int, [P, ctypes.c_int32, I32P, I32P]),
+        "acs_batch_state_get": (ctypes.c_int, [P, ctypes.c_int32, I32P, DP, DP, DP, DP, DP]),
         "acs_batch_solve": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(Settings),
                                            ctypes.POINTER(DP), ctypes.POINTER(DP), ctypes.POINTER(DP),
                                            ctypes.POINTER(Info), P]),
@@ -352,6 +356,19 @@ def solve(problem: Problem, settings: Optional[Settings] = None, stream: int = 0
     return x, y, z, info
 
 
+def solve_device(problem: Problem, x_ptr: int, y_ptr: int, z_ptr: int, stream: int = 0,
+                 settings: Optional[Settings] = None, **kw) -> Info:
+    """One-shot solve into caller-owned device buffers (addresses of float64
+    device arrays: x, z of length n, y of length m; 0 = not wanted) on
+    `stream` (a hipStream_t address, 0 = the library's own)."""
+    if settings is None:
+        settings = default_settings(**kw)
+    info = Info()
+    _check(lib().acs_solve_device(problem.handle, ctypes.byref(settings), P(x_ptr or None), P(y_ptr or None),
+                                  P(z_ptr or None), ctypes.byref(info), P(stream or None)))
+    return info
+
+
 class Batch:
     """Many independent problems solved by one persistent kernel (acs_batch)."""
 
@@ -383,6 +400,16 @@ class Batch:
         y = np.empty(p.m) if xyz else None
         _check(lib().acs_batch_result(self.handle, int(i), _dptr(x), _dptr(y), _dptr(z), ctypes.byref(info)))
         return x, y, z, info
+
+    def state(self, i: int) -> dict:
+        p = self.problems[i]
+        out = {k: np.empty(p.n) for k in ("s_prev", "s", "O")}
+        out["w"], out["dsq"] = np.empty(p.m), np.empty(p.m)
+        l = ctypes.c_int32()
+        _check(lib().acs_batch_state_get(self.handle, int(i), ctypes.byref(l), _dptr(out["s_prev"]), _dptr(out["s"]),
+                                         _dptr(out["O"]), _dptr(out["w"]), _dptr(out["dsq"])))
+        out["l"] = int(l.value)
+        return out
 
     def lanes(self, i: int):
         a, t = ctypes.c_int32(), ctypes.c_int32()

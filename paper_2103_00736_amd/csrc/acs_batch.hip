@@ -217,6 +217,7 @@ __device__ void sweep_update(BInst& I, int mode, bool check, double (&acc)[9], S
         }
         const double dr = (pj - sn - 2.0 * zt) / (2.0 * mu * Oj);
         acc[5] += dr * dr;
+        acc[8] += x * dr;  // r_d^T x of the objective-error estimate
       }
     }
     if (mode != 2) {
@@ -481,7 +482,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
     }
     __syncthreads();
     if (check) {
-      double a2[2] = {0, 0};
+      double a2[3] = {0, 0, 0};
       const double* __restrict__ av = I.a_val64;
       const int32_t* __restrict__ acol = I.a_col;
       const double* __restrict__ xh = I.xhat;
@@ -492,11 +493,12 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
         const double yi = -I.dinv[i] * I.w[i] / mu;
         I.y[i] = yi;
         a2[1] += I.b[i] * yi;
+        a2[2] += yi * res;
       };
       bsweep<double>(I, 0, prod, epi, sh);
       double tot[9];
-      for (int i = 0; i < 8; ++i) tot[i] = bsum(ac[i], sh.red);
-      const double pres2 = bsum(a2[0], sh.red), bty = bsum(a2[1], sh.red);
+      for (int i = 0; i < 9; ++i) tot[i] = bsum(ac[i], sh.red);
+      const double pres2 = bsum(a2[0], sh.red), bty = bsum(a2[1], sh.red), ytrp = bsum(a2[2], sh.red);
       const double ctx = tot[0];
       double e[7];
       e[0] = sqrt(pres2) / (1.0 + I.bnorm);
@@ -506,18 +508,21 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
       e[4] = fmax(fmax(e[0], e[1]), fmax(e[2], e[3]));
       e[5] = ctx;
       e[6] = bty;
-      bool nan = bad;
+      // weak-duality estimate of the objective's relative error (see acs.h)
+      const double eobj = fmax(fabs(ytrp), fabs(ctx - bty + tot[8])) / (1.0 + fabs(ctx));
+      bool nan = bad || !(eobj == eobj) || isinf(eobj);
       for (int i = 0; i < 7; ++i)
         if (!(e[i] == e[i]) || isinf(e[i])) nan = true;
       if (nan)
         status = ACS_NUMERIC;
-      else if (e[4] <= I.eps)
+      else if (e[4] <= I.eps && (!I.obj_stop || eobj <= I.eps))
         status = ACS_SOLVED;
       else if (l >= I.max_iter)
         status = ACS_MAX_ITER;
       __syncthreads();
       if (threadIdx.x == 0) {
         for (int i = 0; i < 7; ++i) I.kkt[i] = e[i];
+        I.kkt[8] = eobj;
         I.checked = l;
       }
     } else if (bad) {
@@ -536,7 +541,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
     gI->conds = I.conds;
     gI->checked = I.checked;
     gI->cg_total = I.cg_total;
-    for (int i = 0; i < 8; ++i) gI->kkt[i] = I.kkt[i];
+    for (int i = 0; i < 9; ++i) gI->kkt[i] = I.kkt[i];
   }
   __syncthreads();
 }

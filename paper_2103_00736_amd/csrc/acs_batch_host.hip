@@ -193,6 +193,7 @@ void init_instance_state(BInst& I, char* B, const InstLayout& o, const Problem& 
   I.max_iter = s.max_iter;
   I.check_every = s.check_every;
   I.cg_max = s.cg_max;
+  I.obj_stop = s.obj_stop;
   I.l = 0;
   I.cur = 0;
   I.status = -1;
@@ -240,7 +241,8 @@ class Batch {
     std::iota(order_.begin(), order_.end(), 0);
     std::stable_sort(order_.begin(), order_.end(), [&](int a, int b) { return probs_[a]->nnz > probs_[b]->nnz; });
     BHIP(hipMalloc(&d_order_, sizeof(int32_t) * std::max(count, 1)));
-    BHIP(hipMemcpy(d_order_, order_.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice));
+    BHIP(hipMemcpyAsync(d_order_, order_.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, st_));
+    BHIP(hipStreamSynchronize(st_));
     BHIP(hipMalloc(&d_queue_, sizeof(unsigned int)));
     hipDeviceProp_t prop;
     BHIP(hipGetDeviceProperties(&prop, 0));
@@ -297,13 +299,14 @@ class Batch {
     if (i < 0 || i >= count()) throw AcsError(ACS_ERR_ARG, "instance index out of range");
     const Problem& p = *probs_[i];
     const BInst& h = host_inst_[i];
-    if (x) BHIP(hipMemcpy(x, h.x, sizeof(double) * p.n, hipMemcpyDeviceToHost));
-    if (z) BHIP(hipMemcpy(z, h.z, sizeof(double) * p.n, hipMemcpyDeviceToHost));
-    if (y) {  // internal row order -> caller's
-      std::vector<double> yi(p.m);
-      BHIP(hipMemcpy(yi.data(), h.y, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+    // every copy is ordered after the work on the batch's stream
+    if (x) BHIP(hipMemcpyAsync(x, h.x, sizeof(double) * p.n, hipMemcpyDeviceToHost, st_));
+    if (z) BHIP(hipMemcpyAsync(z, h.z, sizeof(double) * p.n, hipMemcpyDeviceToHost, st_));
+    std::vector<double> yi(y ? p.m : 0);
+    if (y) BHIP(hipMemcpyAsync(yi.data(), h.y, sizeof(double) * p.m, hipMemcpyDeviceToHost, st_));
+    BHIP(hipStreamSynchronize(st_));
+    if (y)  // internal row order -> caller's
       for (int k = 0; k < p.m; ++k) y[p.row_perm[k]] = yi[k];
-    }
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->status = h.status < 0 ? ACS_MAX_ITER : h.status;
@@ -318,7 +321,35 @@ class Batch {
       info->pobj = h.kkt[5];
       info->dobj = h.kkt[6];
       info->alpha = h.kkt[7];
+      info->eps_obj = h.kkt[8];
       info->solve_ms = last_ms_;
+    }
+  }
+
+  // Resident state of instance i (tests, checkpoints): l, s_prev, s, O (n),
+  // w and the row norms sqrt(D) (m, caller's row order); w is unscaled
+  // (y = -w / mu), as in acs_state_get.
+  void state(int i, int32_t* l, double* s_prev, double* s, double* O, double* w, double* dsq) {
+    if (i < 0 || i >= count()) throw AcsError(ACS_ERR_ARG, "instance index out of range");
+    const Problem& p = *probs_[i];
+    const BInst& h = host_inst_[i];
+    std::vector<float> sp(p.n), sc(p.n);
+    std::vector<double> wi(p.m), di(p.m), ds(p.m);
+    BHIP(hipMemcpyAsync(sp.data(), h.s_buf[h.cur ^ 1], sizeof(float) * p.n, hipMemcpyDeviceToHost, st_));
+    BHIP(hipMemcpyAsync(sc.data(), h.s_buf[h.cur], sizeof(float) * p.n, hipMemcpyDeviceToHost, st_));
+    if (O) BHIP(hipMemcpyAsync(O, h.O, sizeof(double) * p.n, hipMemcpyDeviceToHost, st_));
+    BHIP(hipMemcpyAsync(wi.data(), h.w, sizeof(double) * p.m, hipMemcpyDeviceToHost, st_));
+    BHIP(hipMemcpyAsync(di.data(), h.dinv, sizeof(double) * p.m, hipMemcpyDeviceToHost, st_));
+    BHIP(hipMemcpyAsync(ds.data(), h.dsq, sizeof(double) * p.m, hipMemcpyDeviceToHost, st_));
+    BHIP(hipStreamSynchronize(st_));
+    if (l) *l = h.l;
+    for (int j = 0; j < p.n; ++j) {
+      if (s_prev) s_prev[j] = double(sp[j]);
+      if (s) s[j] = double(sc[j]);
+    }
+    for (int k = 0; k < p.m; ++k) {
+      if (w) w[p.row_perm[k]] = wi[k] * di[k];
+      if (dsq) dsq[p.row_perm[k]] = ds[k];
     }
   }
 
@@ -402,7 +433,7 @@ class Batch {
     std::vector<int32_t> ord(pick.begin(), pick.end());
     int32_t* d_ord = nullptr;
     BHIP(hipMalloc(&d_ord, sizeof(int32_t) * ord.size()));
-    BHIP(hipMemcpy(d_ord, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice));
+    BHIP(hipMemcpyAsync(d_ord, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice, st_));
     upload_desc();
     const int grid = std::max(1, std::min(int(ord.size()), cus_ * per_cu_));
     hipEvent_t a, b;
@@ -413,7 +444,7 @@ class Batch {
     launch_batch(d_inst_, d_ord, int(ord.size()), d_queue_, grid, lds_floats_, iters, st_);
     BHIP(hipGetLastError());
     BHIP(hipEventRecord(b, st_));
-    BHIP(hipEventSynchronize(b));
+    BHIP(hipStreamSynchronize(st_));
     float ms = 0;
     BHIP(hipEventElapsedTime(&ms, a, b));
     (void)hipEventDestroy(a);
@@ -437,7 +468,10 @@ class Batch {
       (void)hipGetLastError();
       throw AcsError(ACS_ERR_NOMEM, "batch arena of " + std::to_string(bytes_) + " bytes does not fit");
     }
-    BHIP(hipMemset(d_arena_, 0, bytes_));
+    // zero-filled on the batch's stream, so that the uploads below (same
+    // stream) land after it; the null stream does not order work on a
+    // non-blocking stream
+    BHIP(hipMemsetAsync(d_arena_, 0, bytes_, st_));
     for (int i = 0; i < count; ++i) upload_instance_const(d_arena_, offs_[i], *probs_[i], st_);
     host_inst_.resize(count);
     BHIP(hipMalloc(&d_inst_, sizeof(BInst) * std::max(count, 1)));
@@ -450,7 +484,9 @@ class Batch {
   }
 
   void upload_desc() {
-    BHIP(hipMemcpy(d_inst_, host_inst_.data(), sizeof(BInst) * host_inst_.size(), hipMemcpyHostToDevice));
+    BHIP(hipMemcpyAsync(d_inst_, host_inst_.data(), sizeof(BInst) * host_inst_.size(), hipMemcpyHostToDevice,
+                        st_));
+    BHIP(hipStreamSynchronize(st_));
   }
 
   void reset_all() {
@@ -468,7 +504,8 @@ class Batch {
 
   void fetch_state() {
     std::vector<BInst> tmp(host_inst_.size());
-    BHIP(hipMemcpy(tmp.data(), d_inst_, sizeof(BInst) * tmp.size(), hipMemcpyDeviceToHost));
+    BHIP(hipMemcpyAsync(tmp.data(), d_inst_, sizeof(BInst) * tmp.size(), hipMemcpyDeviceToHost, st_));
+    BHIP(hipStreamSynchronize(st_));
     for (size_t i = 0; i < tmp.size(); ++i) {
       BInst& h = host_inst_[i];
       h.l = tmp[i].l;
@@ -477,7 +514,7 @@ class Batch {
       h.conds = tmp[i].conds;
       h.checked = tmp[i].checked;
       h.cg_total = tmp[i].cg_total;
-      for (int k = 0; k < 8; ++k) h.kkt[k] = tmp[i].kkt[k];
+      for (int k = 0; k < 9; ++k) h.kkt[k] = tmp[i].kkt[k];
     }
   }
 
@@ -576,6 +613,14 @@ int acs_batch_result(acs_batch* b, int32_t i, double* x, double* y, double* z, a
   return guarded([&] {
     if (!b) throw AcsError(ACS_ERR_ARG, "null batch");
     b->b->result(i, x, y, z, info);
+  });
+}
+
+int acs_batch_state_get(acs_batch* b, int32_t i, int32_t* l, double* s_prev, double* s, double* O, double* w,
+                        double* dsq) {
+  return guarded([&] {
+    if (!b) throw AcsError(ACS_ERR_ARG, "null batch");
+    b->b->state(i, l, s_prev, s, O, w, dsq);
   });
 }
 

@@ -64,7 +64,7 @@ struct Ctl {
   double upd[8];  // reductions of the update kernel
   double cone[4]; // reductions of the cone kernel
   double cond[4]; // conditioning: min log o, -max log o, -any valid, alpha
-  double kkt[8];  // eps_p, eps_d, eps_gap, eps_cone, kkt, pobj, dobj, ds2
+  double kkt[9];  // eps_p, eps_d, eps_gap, eps_cone, kkt, pobj, dobj, ds2, eps_obj
 };
 
 // Host-visible status written by kernels into pinned, mapped host memory.
@@ -72,7 +72,7 @@ struct HostStatus {
   long long launch_seq;  // id of the last finished CG-A launch
   int32_t cg_done_iter;  // last outer iteration whose CG finished
   int32_t check_iter;    // last iteration whose KKT check finished
-  double kkt[8];         // copy of Ctl::kkt of check_iter
+  double kkt[9];         // copy of Ctl::kkt of check_iter
   long long cg_total;
   int32_t numeric;       // NaN/Inf seen
   int32_t pad;
@@ -226,6 +226,8 @@ template <typename VT> void launch_rescale(const Dev<VT>& d, int wmode, hipStrea
 // in the caller's row order
 template <typename VT> void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st);
 template <typename VT> void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st);
+// x, z (n) and y (m, caller's row order) of the last check into device buffers (any may be null)
+template <typename VT> void launch_out_device(const Dev<VT>& d, double* x, double* y, double* z, hipStream_t st);
 // direct projection: B = A_s (copy), M = B B^T (syrk), M -> M^{-1} (the
 // sweep: for K = 0..nb-1 pivot_panel(K) then update(K); then mirror),
 // w += M^{-1} r64 (apply)

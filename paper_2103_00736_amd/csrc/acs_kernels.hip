@@ -318,7 +318,7 @@ struct UpdateEpi {
   const Dev<VT>& d;
   const VT* __restrict__ s_cur;
   VT* __restrict__ s_new;
-  double (&acc)[7];
+  double (&acc)[8];
   __device__ __forceinline__ void operator()(int j, double u) const {
     const double mu = d.mu;
     const double zt = d.chat[j] + u;  // mu * (O z) implied by w
@@ -349,6 +349,7 @@ struct UpdateEpi {
         }
         const double dr = (pj - sn - 2.0 * zt) / (2.0 * mu * Oj);  // (A^T y + z - c)_j
         acc[6] += dr * dr;
+        acc[7] += x * dr;  // r_d^T x of the objective-error estimate
       }
     }
     if (MODE != UPD_UPDATE_ONLY) {
@@ -363,12 +364,12 @@ struct UpdateEpi {
 template <typename VT, int MODE, bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restrict__ s_cur, VT* __restrict__ s_new) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   UpdateEpi<VT, MODE, CHECK> upd{d, s_cur, s_new, acc};
   auto pre = [](int) -> double { return 0.0; };
   auto epi = [&](int j, double u, double) { upd(j, u); };
   sell_rows<double, double>(d.st, d.st_val64, 0, blk, d.w, pre, epi);
-  if (MODE != UPD_PROLOGUE) block_store_partials<7>(acc, d.partials, blk);
+  if (MODE != UPD_PROLOGUE) block_store_partials<8>(acc, d.partials, blk);
 }
 
 // ----------------------------------------------------------------------------
@@ -566,14 +567,16 @@ __global__ __launch_bounds__(kBlock) void k_sell_vals(const int32_t* __restrict_
 // KKT check (rows i of A_s): ||A x - b||^2 = sum (d_i^-1 ((A_s xhat)_i - b_s,i))^2,
 // y = -d w / mu, b^T y; the last workgroup assembles the relative errors
 // ----------------------------------------------------------------------------
-// check, row i given (A_s xhat)_i: ||A x - b||^2 term, y_i, b^T y term
+// check, row i given (A_s xhat)_i: ||A x - b||^2 term, y_i, b^T y term and
+// y^T (A x - b) of the objective-error estimate
 template <typename VT>
-__device__ __forceinline__ void pres_row(const Dev<VT>& d, int i, double ax, double mu, double (&acc)[2]) {
+__device__ __forceinline__ void pres_row(const Dev<VT>& d, int i, double ax, double mu, double (&acc)[3]) {
   const double res = (ax - d.bs[i]) * d.dsq[i];
   acc[0] += res * res;
   const double yi = -d.dinv[i] * d.w[i] / mu;
   d.yout[i] = yi;
   acc[1] += d.b[i] * yi;
+  acc[2] += yi * res;
 }
 
 template <typename VT>
@@ -584,11 +587,11 @@ __global__ __launch_bounds__(kBlock) void k_pres(Dev<VT> d) {
   const int32_t* __restrict__ ac = d.a_col;
   const double* __restrict__ xh = d.xhat;
   auto prod = [&](int k) -> double { return av[k] * xh[ac[k]]; };
-  double acc[2] = {0, 0};
+  double acc[3] = {0, 0, 0};
   const double mu = d.mu;
   auto epi = [&](int i, double ax) { pres_row(d, i, ax, mu, acc); };
   rows_block<double>(d.a_rp, rb, prod, epi);
-  block_store_partials<2>(acc, d.partials, blk);
+  block_store_partials<3>(acc, d.partials, blk);
 }
 
 // ----------------------------------------------------------------------------
@@ -809,6 +812,19 @@ __global__ __launch_bounds__(kBlock) void k_perm_in(Dev<VT> d, const VT* __restr
   if (i < d.m) d.mtmp[i] = x[d.row_perm[i]];
 }
 
+// outputs into caller-owned device buffers: x, z as they are, y in the
+// caller's row order (y[row_perm[i]] = yout[i])
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_out_device(Dev<VT> d, double* __restrict__ x, double* __restrict__ y,
+                                                      double* __restrict__ z) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < d.n) {
+    if (x) x[i] = d.xout[i];
+    if (z) z[i] = d.zout[i];
+  }
+  if (y && i < d.m) y[d.row_perm[i]] = d.yout[i];
+}
+
 template <typename VT>
 __global__ void k_ctl_reset(Dev<VT> d, int cg_max) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -822,7 +838,7 @@ __global__ void k_ctl_reset(Dev<VT> d, int cg_max) {
     for (int i = 0; i < 8; ++i) c->upd[i] = 0.0;
     for (int i = 0; i < 4; ++i) c->cone[i] = 0.0;
     for (int i = 0; i < 4; ++i) c->cond[i] = 0.0;
-    for (int i = 0; i < 8; ++i) c->kkt[i] = 0.0;
+    for (int i = 0; i < 9; ++i) c->kkt[i] = 0.0;
   }
 }
 
@@ -832,10 +848,10 @@ __global__ void k_ctl_reset(Dev<VT> d, int cg_max) {
 // ----------------------------------------------------------------------------
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_fin_upd(Dev<VT> d, int nb) {
-  double t[7];
-  sum_partials<7>(d.partials, nb, t);
+  double t[8];
+  sum_partials<8>(d.partials, nb, t);
   if (threadIdx.x == 0)
-    for (int i = 0; i < 7; ++i) d.ctl->upd[i] = t[i];
+    for (int i = 0; i < 8; ++i) d.ctl->upd[i] = t[i];
 }
 
 template <typename VT>
@@ -920,15 +936,15 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_a(Dev<VT> d, int nb, long lon
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_fin_pres(Dev<VT> d, int nb, int iter, double bnorm, double cnorm,
                                                      int has_soc) {
-  double t[2];
-  sum_partials<2>(d.partials, nb, t);
+  double t[3];
+  sum_partials<3>(d.partials, nb, t);
   if (threadIdx.x == 0) {
     Ctl* c = d.ctl;
     const double* u = c->upd;
     const double ctx = u[1], bty = t[1];
     const double dx2 = u[4] + (has_soc ? c->cone[0] : 0.0);
     const double dz2 = u[5] + (has_soc ? c->cone[1] : 0.0);
-    double e[8];
+    double e[9];
     e[0] = sqrt(t[0]) / (1.0 + bnorm);
     e[1] = sqrt(u[6]) / (1.0 + cnorm);
     e[2] = fabs(ctx - bty) / (1.0 + fabs(ctx) + fabs(bty));
@@ -937,8 +953,11 @@ __global__ __launch_bounds__(kBlock) void k_fin_pres(Dev<VT> d, int nb, int iter
     e[5] = ctx;
     e[6] = bty;
     e[7] = u[0];
+    // weak-duality estimate of |c^T x - p*| / (1 + |c^T x|): the objective
+    // lies between y^T r_p and c^T x - b^T y + r_d^T x up to second-order terms
+    e[8] = fmax(fabs(t[2]), fabs(ctx - bty + u[7])) / (1.0 + fabs(ctx));
     bool bad = false;
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 9; ++i) {
       c->kkt[i] = e[i];
       d.hs->kkt[i] = e[i];
       if (!(e[i] == e[i]) || isinf(e[i])) bad = true;
@@ -1063,7 +1082,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(Dev<VT> d, int aux, VT* _
   __shared__ int bad_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i0 = (blockIdx.x * (kBlock / 64) + wave) * kDenseRows;
-  double acc[2] = {0, 0};
+  double acc[3] = {0, 0, 0};
   double alpha = 0, beta = 0;
   if (KIND == DK_CG) {
     if (d.ctl->done) return;
@@ -1127,7 +1146,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(Dev<VT> d, int aux, VT* _
     double a1[1] = {acc[0]};
     block_store_partials<1>(a1, d.partials, blockIdx.x);
   } else if (KIND == DK_PRES) {
-    block_store_partials<2>(acc, d.partials, blockIdx.x);
+    block_store_partials<3>(acc, d.partials, blockIdx.x);
   }
 }
 
@@ -1184,7 +1203,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_fin(Dev<VT> d, const VT* 
   if (KIND == DK_CG && d.ctl->done) return;
   const int j = blockIdx.x * kBlock + threadIdx.x;
   const ACC* part = reinterpret_cast<const ACC*>(d.dpart);
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (j < d.n) {
     ACC sum = part[j];
     for (int ch = 1; ch < d.dnchunk; ++ch) sum += part[size_t(ch) * d.ld + j];
@@ -1206,7 +1225,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_fin(Dev<VT> d, const VT* 
     double a1[1] = {acc[0]};
     block_store_partials<1>(a1, d.partials2, blockIdx.x);
   } else if (KIND == DK_UPDATE && MODE != UPD_PROLOGUE) {
-    block_store_partials<7>(acc, d.partials, blockIdx.x);
+    block_store_partials<8>(acc, d.partials, blockIdx.x);
   }
 }
 
@@ -1423,6 +1442,11 @@ void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st
 }
 
 template <typename VT>
+void launch_out_device(const Dev<VT>& d, double* x, double* y, double* z, hipStream_t st) {
+  ACS_LAUNCH((k_out_device<VT>), dim3(ceil_div(std::max(d.m, d.n), kBlock)), dim3(kBlock), 0, st, d, x, y, z);
+}
+
+template <typename VT>
 void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
   ACS_LAUNCH((k_ctl_reset<VT>), dim3(1), dim3(64), 0, st, d, cg_max);
 }
@@ -1442,7 +1466,8 @@ void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
   template void launch_cond_scale<VT>(const Dev<VT>&, VT*, hipStream_t);                              \
   template void launch_rescale<VT>(const Dev<VT>&, int, hipStream_t);                                 \
   template void launch_spmv<VT>(const Dev<VT>&, int, const VT*, VT*, hipStream_t);                    \
-  template void launch_ctl_reset<VT>(const Dev<VT>&, int, hipStream_t);
+  template void launch_ctl_reset<VT>(const Dev<VT>&, int, hipStream_t);                              \
+  template void launch_out_device<VT>(const Dev<VT>&, double*, double*, double*, hipStream_t);
 
 ACS_INSTANTIATE(float)
 ACS_INSTANTIATE(double)

@@ -252,7 +252,8 @@ class Server {
       upload_instance_const(sl.arena, sl.lay, *r->p, pool_stream_);
       const Problem& p = *r->p;
       init_instance_state(sl.host, sl.arena, sl.lay, p, r->s, default_sched_a(p), default_sched_t(p), pool_stream_);
-      SHIP(hipMemcpy(d_inst_ + idx, &sl.host, sizeof(BInst), hipMemcpyHostToDevice));
+      SHIP(hipMemcpyAsync(d_inst_ + idx, &sl.host, sizeof(BInst), hipMemcpyHostToDevice, pool_stream_));
+      SHIP(hipStreamSynchronize(pool_stream_));
       sl.r = r;
       sl.active = true;
       ++pool_active_;
@@ -285,7 +286,8 @@ class Server {
     for (int idx : order) {
       Slot& sl = pool_[idx];
       BInst st;
-      SHIP(hipMemcpy(&st, d_inst_ + idx, sizeof(BInst), hipMemcpyDeviceToHost));
+      SHIP(hipMemcpyAsync(&st, d_inst_ + idx, sizeof(BInst), hipMemcpyDeviceToHost, pool_stream_));
+      SHIP(hipStreamSynchronize(pool_stream_));
       const bool cancelled = sl.r->cancel;
       if (st.status < 0 && !cancelled) continue;
       std::shared_ptr<Request> r = sl.r;
@@ -293,11 +295,12 @@ class Server {
       r->x.resize(p.n);
       r->z.resize(p.n);
       r->y.resize(p.m);
-      SHIP(hipMemcpy(r->x.data(), sl.host.x, sizeof(double) * p.n, hipMemcpyDeviceToHost));
-      SHIP(hipMemcpy(r->z.data(), sl.host.z, sizeof(double) * p.n, hipMemcpyDeviceToHost));
       {
         std::vector<double> yi(p.m);  // internal row order -> caller's
-        SHIP(hipMemcpy(yi.data(), sl.host.y, sizeof(double) * p.m, hipMemcpyDeviceToHost));
+        SHIP(hipMemcpyAsync(r->x.data(), sl.host.x, sizeof(double) * p.n, hipMemcpyDeviceToHost, pool_stream_));
+        SHIP(hipMemcpyAsync(r->z.data(), sl.host.z, sizeof(double) * p.n, hipMemcpyDeviceToHost, pool_stream_));
+        SHIP(hipMemcpyAsync(yi.data(), sl.host.y, sizeof(double) * p.m, hipMemcpyDeviceToHost, pool_stream_));
+        SHIP(hipStreamSynchronize(pool_stream_));
         for (int k = 0; k < p.m; ++k) r->y[p.row_perm[k]] = yi[k];
       }
       acs_info& in = r->info;
@@ -314,6 +317,7 @@ class Server {
       in.pobj = st.kkt[5];
       in.dobj = st.kkt[6];
       in.alpha = st.kkt[7];
+      in.eps_obj = st.kkt[8];
       in.solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - r->t_admit).count();
       mem_->release(sl.arena);
       sl.arena = nullptr;

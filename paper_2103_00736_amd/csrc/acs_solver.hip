@@ -291,6 +291,7 @@ class InstanceBase {
   virtual void set_state(int l, const double* s_prev, const double* s, const double* O, const double* w) = 0;
   virtual void run(int iters, bool stop_on_converge) = 0;
   virtual void get(int* l, double* s_prev, double* s, double* O, double* w, double* x, double* y, double* z) = 0;
+  virtual void get_device(double* x, double* y, double* z) = 0;
   virtual void spmv(int which, const void* x, void* y, int reps, double* avg_ms) = 0;
   virtual void check_now() = 0;
   virtual void profile(uint32_t mask) = 0;
@@ -323,33 +324,50 @@ class Instance final : public InstanceBase {
       HIP_CHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
       own_stream_ = true;
     }
-    setup_device();
-    set_initial();
-    HIP_CHECK(hipStreamSynchronize(st_));
+    // a constructor that throws (e.g. ACS_ERR_NOMEM from the arena or the
+    // server's pools) runs no destructor: release what was taken so far
+    try {
+      setup_device();
+      set_initial();
+      HIP_CHECK(hipStreamSynchronize(st_));
+    } catch (...) {
+      release();
+      throw;
+    }
     info.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
 
-  ~Instance() override {
+  ~Instance() override { release(); }
+
+  // streams, events, device memory and the status record; idempotent
+  void release() {
     if (st_) (void)hipStreamSynchronize(st_);
     if (st2_) {
       (void)hipStreamSynchronize(st2_);
       (void)hipStreamDestroy(st2_);
+      st2_ = nullptr;
     }
     if (fork_) (void)hipEventDestroy(fork_);
     if (join_) (void)hipEventDestroy(join_);
-    for (auto* v : {&prof_pending_, &prof_free_})
+    fork_ = join_ = nullptr;
+    for (auto* v : {&prof_pending_, &prof_free_}) {
       for (auto& e : *v) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
       }
+      v->clear();
+    }
     arena_.release();
     if (hs_) {
       if (res_.status)
         res_.status->give(hs_);
       else
         (void)hipHostFree(hs_);
+      hs_ = nullptr;
     }
-    if (own_stream_) (void)hipStreamDestroy(st_);
+    if (own_stream_ && st_) (void)hipStreamDestroy(st_);
+    st_ = nullptr;
+    own_stream_ = false;
   }
 
   // -------------------------------------------------------------- setup
@@ -829,16 +847,18 @@ class Instance final : public InstanceBase {
     info.kkt = h.kkt[4];
     info.pobj = h.kkt[5];
     info.dobj = h.kkt[6];
+    info.eps_obj = h.kkt[8];
     info.cg_steps = h.cg_total;
     checked_iter_ = l;
     if (S.verbose)
-      std::fprintf(stderr, "acs l=%d kkt=%.3e p=%.2e d=%.2e g=%.2e k=%.2e obj=%.10e cg=%lld\n", l, info.kkt,
-                   info.eps_p, info.eps_d, info.eps_gap, info.eps_cone, info.pobj, (long long)h.cg_total);
+        std::fprintf(stderr, "acs l=%d kkt=%.3e p=%.2e d=%.2e g=%.2e k=%.2e o=%.2e obj=%.10e cg=%lld\n", l, info.kkt,
+                   info.eps_p, info.eps_d, info.eps_gap, info.eps_cone, info.eps_obj, info.pobj,
+                   (long long)h.cg_total);
     if (__atomic_load_n(&hs_->numeric, __ATOMIC_ACQUIRE)) {
       info.status = ACS_NUMERIC;
       return true;
     }
-    return info.kkt <= S.eps_kkt;
+    return info.kkt <= S.eps_kkt && (!S.obj_stop || info.eps_obj <= S.eps_kkt);
   }
 
   // ------------------------------------------------------------ iterate
@@ -961,6 +981,15 @@ class Instance final : public InstanceBase {
         for (int i = 0; i < p.m; ++i) y[p.row_perm[i]] = yi[i];
       }
     }
+  }
+
+  // x, y, z of the last check into caller-owned device buffers, ordered on
+  // the instance's stream and complete on return
+  void get_device(double* x, double* y, double* z) override {
+    if (!have_xyz_) throw AcsError(ACS_ERR_STATE, "x, y, z need at least one iteration after the state was set");
+    launch_out_device(d_, x, y, z, st_);
+    check_launch();
+    HIP_CHECK(hipStreamSynchronize(st_));
   }
 
   void spmv(int which, const void* x, void* y, int reps, double* avg_ms) override {
@@ -1098,6 +1127,7 @@ void acs_settings_default(acs_settings* s) {
   s->cg_reduce = 0.1;
   s->cg_abs = 0.0;
   s->verbose = 0;
+  s->obj_stop = 1;
 }
 
 int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
@@ -1226,6 +1256,26 @@ int acs_state_timing(acs_state* st, int32_t cls, int64_t* count, double* total_m
   return guarded([&] {
     if (!st) throw AcsError(ACS_ERR_ARG, "null state");
     st->inst->timing(cls, count, total_ms);
+  });
+}
+
+int acs_solve_device(const acs_problem* p, const acs_settings* s, double* x, double* y, double* z,
+                     acs_info* info, void* stream) {
+  return guarded([&] {
+    if (!p || !s) throw AcsError(ACS_ERR_ARG, "null argument");
+    ensure_device();
+    for (const void* ptr : {static_cast<const void*>(x), static_cast<const void*>(y), static_cast<const void*>(z)}) {
+      if (!ptr) continue;
+      hipPointerAttribute_t attr;
+      if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        throw AcsError(ACS_ERR_ARG, "acs_solve_device: x, y and z must be device allocations");
+      }
+    }
+    auto inst = make_instance(p->p, *s, static_cast<hipStream_t>(stream));
+    inst->run(inst->S.max_iter, true);
+    if (x || y || z) inst->get_device(x, y, z);
+    if (info) *info = inst->info;
   });
 }
 

@@ -35,9 +35,35 @@ def test_settings_defaults_and_layout():
     s = acs.default_settings()
     assert s.mu == 1.0 and s.t == 9.2 and s.l_first == 300 and s.l_every == 100 and s.auto_params == 1
     assert s.eps_kkt == 1e-4 and s.precision == acs.PREC_MIXED and s.projection == acs.PROJ_CG
-    assert ctypes.sizeof(acs.Settings) == 104
-    assert acs.Settings.projection.offset == 76 and acs.Settings.reserved.offset == 80
+    assert s.obj_stop == 1
     assert acs.version().startswith("acs")
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler
+    gives it in include/acs.h (gcc on a generated probe)."""
+    import json
+    import subprocess
+
+    structs = {"acs_settings": acs.Settings, "acs_info": acs.Info, "acs_server_counters": acs.ServerStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "acs.h"', "int main(void) {", 'printf("{");']
+    first = True
+    for cname, cls in structs.items():
+        for fname, _ in cls._fields_:
+            sep = "" if first else ","
+            first = False
+            lines.append(f'printf("{sep}\\"{cname}.{fname}\\": %zu", offsetof({cname}, {fname}));')
+        lines.append(f'printf(",\\"{cname}\\": %zu", sizeof({cname}));')
+    lines += ['printf("}\\n");', "return 0; }"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    c = json.loads(subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout)
+    for cname, cls in structs.items():
+        assert c[cname] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert c[f"{cname}.{fname}"] == getattr(cls, fname).offset, (cname, fname)
 
 
 def _lp():

@@ -13,6 +13,7 @@ from oracle.cones import abs_K
 from oracle.kkt import kkt_errors
 from oracle.subspace import RangeProjector
 from paper_2103_00736_amd import acs, synth
+from tests._parity import assert_close, errors, fmt, obj_err as _obj_err
 
 pytestmark = pytest.mark.gpu
 
@@ -169,16 +170,18 @@ def test_factor_one_iteration_parity(name, prec, after_event):
     st.step(1)
     g = st.get()
     ref = one_iteration(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, 1.0, s, O)
-    errs = {k: _rel(g[k], ref[k]) for k in ("s", "x", "z")}
+    errs = errors(g, ref, ("s", "x", "z"))
     A = p.scipy_csr()
-    errs["A^T y"] = _rel(A.T @ g["y"], A.T @ ref["y"])
+    yerrs = errors({"A^T y": A.T @ g["y"]}, {"A^T y": A.T @ ref["y"]}, ("A^T y",))
     if name not in DEPENDENT:
-        errs["y"] = _rel(g["y"], ref["y"])
+        yerrs.update(errors(g, ref, ("y",)))
     tol = _fp64_bar(p, O, name) if prec == acs.PREC_FP64 else 1e-6
-    print(name, prec, l0, {k: f"{v:.2e}" for k, v in errs.items()}, f"bar {tol:.1e}")
-    for k in ("s", "x", "z"):
-        assert errs[k] <= tol, k
-    assert max(errs.get("y", 0.0), errs["A^T y"]) <= 10 * tol
+    # y solves the normal equations: its bar carries their conditioning in
+    # FP64 (ten times the bar of s); in mixed precision it is the 1e-5 bar
+    tol_y = 10 * tol if prec == acs.PREC_FP64 else 1e-5
+    print(name, prec, l0, "(normwise/elementwise)", fmt(errs), fmt(yerrs), f"bar {tol:.1e}")
+    assert_close(errs, tol, name)
+    assert_close(yerrs, tol_y, name)
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
@@ -265,7 +268,7 @@ def test_factor_full_solve(make, prec):
     rec = _check_solve(p, x, y, z, info, eps * 1.05)
     assert info.cg_steps == 0
     if hasattr(p, "p_star"):
-        assert abs(rec["pobj"] - p.p_star) <= 1e-3 * (1 + abs(p.p_star))
+        assert _obj_err(rec["pobj"], p.p_star) <= 1e-4
 
 
 @pytest.mark.parametrize("m", [1, 63, 64, 65, 127, 128, 129, 200, 257, 500])

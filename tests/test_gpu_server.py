@@ -93,3 +93,30 @@ def test_cancel():
     assert ra[3].status in (acs.CANCELLED, acs.SOLVED)
     assert srv.stats()["bytes_in_use"] == 0
     srv.close()
+
+
+def test_pool_k_iterations_match_oracle():
+    """Requests stopped after 20 iterations on the server's pool path (the
+    persistent kernel's ticks, other requests resident alongside): x, z and
+    y of iteration 20 against 20 iterations of the literal FP64 oracle."""
+    from oracle.alg2 import Algorithm2, default_parameters
+    from tests._parity import assert_close, errors, fmt
+
+    k = 20
+    probs = [synth.config3(0, m=120), synth.socp_percol(80, 240, 3, 41, 3, 12, 0.8)]
+    others = _stream(4)
+    srv = acs.Server(hbm_budget=8 << 30, max_slots=64, small_nnz=10 ** 9, workers=1, tick_iters=7)
+    handles = [acs.Problem.from_synth(p) for p in probs + others]
+    tickets = [srv.submit(h, eps_kkt=1e-14, max_iter=(k if i < len(probs) else 60), cg_reduce=1e-7, cg_max=4000,
+                          check_every=1000000) for i, h in enumerate(handles)]
+    res = [srv.wait(t, 120_000) for t in tickets]
+    srv.close()
+    for p, (x, y, z, info) in zip(probs, res[:len(probs)]):
+        t, L = default_parameters(p.soc_sizes)
+        alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
+        for _ in range(k):
+            alg.step()
+        errs = errors({"x": x, "z": z, "y": y}, {"x": alg.x, "z": alg.z, "y": alg.dual_multiplier()}, ("x", "z", "y"))
+        print(f"{p.name}: status={info.status} it={info.iterations} {fmt(errs)}")
+        assert info.status == acs.MAX_ITER and info.iterations == k
+        assert_close(errs, 1e-5, p.name)
