@@ -80,7 +80,7 @@ extern "C" {
  * With `auto_params` = 1 the library picks the paper's per-class values:
  * LP: t = 9.2, L = {300, 400, ...}; SOCP: t = 1.7, L = {200, 300, ...}; mu = 1.
  * Projection (Alg. 2 step 17) by warm-started CG, defaults cg_reduce = 0.1,
- * cg_max = 500; obj_stop = 1.  The iteration just before a conditioning
+ * cg_max = 500; obj_stop = 4.  The iteration just before a conditioning
  * event (its x, z set O) runs its CG to a 1e-6 reduction with up to 8 cg_max
  * steps.  A cap that
  * stops the CG short of cg_reduce leaves an error the outer iteration may not
@@ -103,7 +103,7 @@ typedef struct acs_settings {
   double cg_abs;        /* ... or once ||r|| <= cg_abs (scaled system)          */
   int32_t verbose;      /* 0 quiet, 1 one line per check on stderr              */
   int32_t projection;   /* ACS_PROJ_CG (default) or ACS_PROJ_FACTOR              */
-  int32_t obj_stop;     /* 1 (default): a check also needs eps_obj <= eps_kkt     */
+  int32_t obj_stop;     /* k > 0: a check also needs k * eps_obj <= eps_kkt (default 4); 0: KKT only */
   int32_t reserved[5];
 } acs_settings;
 
@@ -117,8 +117,10 @@ typedef struct acs_settings {
  * c^T x - b^T y + r_d^T x* for x, z in K, which the current (x, y) estimate
  * up to second-order terms:
  *   eps_obj = max(|y^T r_p|, |c^T x - b^T y + r_d^T x|)/(1+|c^T x|).
- * With settings.obj_stop = 1 a solve stops only when kkt <= eps_kkt and
- * eps_obj <= eps_kkt.                                                     */
+ * The second-order terms are not negligible near eps_kkt = 1e-4: on planted
+ * LPs the estimate fell short of the true error by up to a factor of about 3,
+ * so with settings.obj_stop = k (default 4) a solve stops only when
+ * kkt <= eps_kkt and k * eps_obj <= eps_kkt.                              */
 typedef struct acs_info {
   int32_t status;       /* ACS_SOLVED / ACS_MAX_ITER / ACS_NUMERIC / ACS_CANCELLED */
   int32_t iterations;   /* outer iterations run                                */

@@ -68,7 +68,7 @@ struct BInst {
   int32_t status;   // -1 running, else ACS_SOLVED / ACS_MAX_ITER / ACS_NUMERIC
   int32_t conds;    // conditioning events run
   int32_t checked;  // iteration of the last check
-  int32_t obj_stop; // a check also needs eps_obj <= eps (settings.obj_stop)
+  int32_t obj_stop; // a check also needs obj_stop * eps_obj <= eps (settings.obj_stop)
   long long cg_total;
   double kkt[9];    // eps_p, eps_d, eps_gap, eps_cone, kkt, pobj, dobj, alpha, eps_obj
 };

@@ -515,7 +515,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
         if (!(e[i] == e[i]) || isinf(e[i])) nan = true;
       if (nan)
         status = ACS_NUMERIC;
-      else if (e[4] <= I.eps && (!I.obj_stop || eobj <= I.eps))
+      else if (e[4] <= I.eps && eobj * I.obj_stop <= I.eps)
         status = ACS_SOLVED;
       else if (l >= I.max_iter)
         status = ACS_MAX_ITER;

@@ -73,7 +73,8 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
     s.l_last = -1;
   }
   if (!(s.mu > 0) || !(s.t > 0)) throw AcsError(ACS_ERR_ARG, "settings: mu and t must be > 0");
-  if (s.max_iter < 0 || s.check_every < 1 || s.cg_max < 0) throw AcsError(ACS_ERR_ARG, "settings: bad counts");
+  if (s.max_iter < 0 || s.check_every < 1 || s.cg_max < 0 || s.obj_stop < 0)
+    throw AcsError(ACS_ERR_ARG, "settings: bad counts");
   if (s.precision != ACS_PREC_MIXED && s.precision != ACS_PREC_FP64) throw AcsError(ACS_ERR_ARG, "settings: precision");
   if (s.projection != ACS_PROJ_CG && s.projection != ACS_PROJ_FACTOR) throw AcsError(ACS_ERR_ARG, "settings: projection");
   return s;
@@ -858,7 +859,7 @@ class Instance final : public InstanceBase {
       info.status = ACS_NUMERIC;
       return true;
     }
-    return info.kkt <= S.eps_kkt && (!S.obj_stop || info.eps_obj <= S.eps_kkt);
+    return info.kkt <= S.eps_kkt && info.eps_obj * S.obj_stop <= S.eps_kkt;
   }
 
   // ------------------------------------------------------------ iterate
@@ -1127,7 +1128,7 @@ void acs_settings_default(acs_settings* s) {
   s->cg_reduce = 0.1;
   s->cg_abs = 0.0;
   s->verbose = 0;
-  s->obj_stop = 1;
+  s->obj_stop = 4;
 }
 
 int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,

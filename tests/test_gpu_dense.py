@@ -11,7 +11,7 @@ from oracle.alg2 import Algorithm2, default_parameters, one_iteration
 from oracle.cones import abs_K
 from oracle.kkt import kkt_errors
 from paper_2103_00736_amd import acs, synth
-from tests._parity import assert_close, errors, fmt, obj_err as _obj_err
+from tests._parity import assert_close, assert_iterate, errors, fmt, iterate_errors, obj_err as _obj_err
 
 pytestmark = pytest.mark.gpu
 
@@ -62,10 +62,9 @@ def test_dense_one_iteration_parity(name, prec, after_event):
     st.step(1)
     g = st.get()
     ref = one_iteration(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, 1.0, s, O)
-    tol = 1e-9 if prec == acs.PREC_FP64 else 1e-5
-    errs = errors(g, ref, ("s", "x", "z", "y"))
+    errs = iterate_errors(g, ref, O)
     print(name, prec, l0, "(normwise/elementwise)", fmt(errs))
-    assert_close(errs, tol, name)
+    assert_iterate(errs, prec == acs.PREC_FP64, name)
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
