@@ -8,10 +8,12 @@ import pytest
 
 import oracle.alg2 as alg2
 import oracle.cones as cones
+import oracle.equilibrate as equilibrate
 import oracle.kkt as kkt
 import oracle.subspace as subspace
 from tests import test_oracle_alg2 as P2
 from tests import test_oracle_cones as PC
+from tests import test_oracle_equilibrate as PE
 from tests import test_oracle_kkt as PK
 from tests import test_oracle_subspace as PS
 
@@ -39,6 +41,11 @@ PINS = [
     PK.test_cone_distance_closed_forms,
     PK.test_kkt_terms_at_a_constructed_point,
     PK.test_objective_bounds_hold_exactly_on_the_cone,
+    PE.test_balance_reached_at_convergence,
+    PE.test_rank_one_balanced_after_one_sweep,
+    PE.test_lorentz_blocks_get_one_scale_and_mean_norm,
+    PE.test_paper_example_printed_factors,
+    lambda: PE.test_scaled_run_is_algorithm2_with_scaling_E_times_O("socp"),
 ]
 
 
@@ -171,6 +178,36 @@ def _patched_condition_no_pinv_b():
     return condition
 
 
+def _sk_variant(kind):
+    """The equilibration with one planted mistake."""
+    import scipy.sparse as sp
+
+    def sk(A, n_orth, soc_sizes, sweeps):
+        A = sp.csr_matrix(A, dtype=np.float64)
+        m, n = A.shape
+        S = abs(A) if kind == "abs" else A.multiply(A).tocsr()
+        v, u = np.ones(n), np.ones(m)
+        target = 1.0 if kind == "target" else m / n
+        for _ in range(int(sweeps)):
+            rs = S @ v
+            u = np.where(rs > 0, 1.0 / np.where(rs > 0, rs, 1.0), 1.0)
+            cs = S.T @ u
+            for start, k in cones.blocks(n_orth, soc_sizes):
+                if kind == "per_coordinate":
+                    c = cs[start:start + k]
+                    v[start:start + k] = np.where(c > 0, target / np.where(c > 0, c, 1.0), 1.0)
+                else:
+                    tot = float(cs[start:start + k].sum())
+                    v[start:start + k] = target * k / tot if tot > 0 else 1.0
+        return np.sqrt(u), np.sqrt(v)
+
+    return sk
+
+
+def _mut_z_mapped_with_e(self):
+    return self.inner.z * self.e  # z = E^{-1} z_hat
+
+
 MUTATIONS = {
     "abs_K returns proj_K": (cones, "abs_K", _mut_abs_dropped_term),
     "Lorentz projection scale": (cones, "proj_lorentz", _mut_lorentz_scale),
@@ -186,6 +223,10 @@ MUTATIONS = {
     "dual residual with -z": (kkt, "kkt_errors", _mut_dual_residual_sign),
     "objective estimate drops r_d^T x": (kkt, "kkt_errors", _mut_objective_drops_rd),
     "objective bound with -r_d": (kkt, "objective_bounds", _mut_objective_bounds_sign),
+    "equilibration on |a| instead of a^2": (equilibrate, "sinkhorn_knopp_l2", _sk_variant("abs")),
+    "equilibration column target 1": (equilibrate, "sinkhorn_knopp_l2", _sk_variant("target")),
+    "equilibration per coordinate on cones": (equilibrate, "sinkhorn_knopp_l2", _sk_variant("per_coordinate")),
+    "preconditioned z mapped back with E": (equilibrate.EquilibratedAlgorithm2, "z", property(_mut_z_mapped_with_e)),
 }
 
 
@@ -198,7 +239,8 @@ def test_mutation_is_caught(name, monkeypatch):
     target, attr, repl = MUTATIONS[name]
     monkeypatch.setattr(target, attr, repl)
     # modules that imported the name directly see the mutation too
-    for mod in (alg2, kkt, subspace, P2, PC, PK, PS):
-        if hasattr(mod, attr) and mod is not target and callable(getattr(mod, attr)) and target in (cones, alg2, kkt):
+    for mod in (alg2, kkt, subspace, P2, PC, PK, PS, PE):
+        if hasattr(mod, attr) and mod is not target and callable(getattr(mod, attr)) and target in (
+                cones, alg2, kkt, equilibrate):
             monkeypatch.setattr(mod, attr, repl)
     assert _caught(), f"no pin caught: {name}"
