@@ -207,6 +207,27 @@ int acs_solve_device(const acs_problem* p, const acs_settings* s, double* x, dou
                      void* stream);
 
 /*
+ * acs_solve_device for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, bitwise the same results, with every device array of the
+ * instance carved from a fixed 64 MiB array compiled into the library (one per
+ * GPU, held until the process ends) and the progress record and fallback
+ * stream (used when `stream` is NULL) set up once per device by acs_init or
+ * by the first call.  The call itself makes no hipMalloc, hipFree, pinned or
+ * other allocating HIP call.  Outputs as for acs_solve_device (device
+ * buffers, written on `stream`, complete on return).
+ * Limits and errors: ACS_ERR_NOMEM when acs_problem_device_bytes(p,
+ * precision) exceeds 64 MiB (checked before any GPU work); ACS_ERR_ARG for
+ * ACS_PROJ_FACTOR or a pointer that is not a device allocation.
+ * Every call on a GPU uses that GPU's one array, which keeps the last call's
+ * contents (the solve initialises everything it reads).  The library runs
+ * such calls one at a time per process; calls from several processes, or
+ * overlapping work by the caller on that memory, would race.
+ */
+int acs_solve_device_noalloc(const acs_problem* p, const acs_settings* s, double* x, double* y, double* z,
+                             acs_info* info, void* stream);
+
+/*
  * Solver state on the GPU (resident iterate and scalings; tests, benchmarks
  * and checkpoint/resume).  The state after l iterations is (l, s_prev, s, O, w):
  * s = s^{l+1}-to-be input of iteration l+1, s_prev the iterate before it, O the

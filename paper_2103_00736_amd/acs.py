@@ -34,7 +34,7 @@ PROF_ALL = (1 << 13) - 1  # ACS_PROF_ALL
 EXPORTED = [
     "acs_version", "acs_last_error", "acs_init", "acs_settings_default", "acs_problem_create",
     "acs_problem_destroy", "acs_problem_create_dense", "acs_problem_device_bytes", "acs_problem_factor_bytes",
-    "acs_batch_device_bytes", "acs_solve", "acs_solve_device", "acs_state_create", "acs_state_destroy",
+    "acs_batch_device_bytes", "acs_solve", "acs_solve_device", "acs_solve_device_noalloc", "acs_state_create", "acs_state_destroy",
     "acs_state_set", "acs_state_step", "acs_state_solve", "acs_state_get", "acs_state_info", "acs_state_check",
     "acs_state_spmv", "acs_state_profile", "acs_state_timing", "acs_state_normal_inverse", "acs_batch_create", "acs_batch_destroy",
     "acs_batch_autotune", "acs_batch_run", "acs_batch_result", "acs_batch_state_get", "acs_batch_lanes",
@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
         "acs_batch_device_bytes": (ctypes.c_int64, [P]),
         "acs_solve": (ctypes.c_int, [P, ctypes.POINTER(Settings), DP, DP, DP, ctypes.POINTER(Info), P]),
         "acs_solve_device": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, P, P, ctypes.POINTER(Info), P]),
+        "acs_solve_device_noalloc": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, P, P, ctypes.POINTER(Info), P]),
         "acs_state_create": (ctypes.c_int, [P, ctypes.POINTER(Settings), P, ctypes.POINTER(P)]),
         "acs_state_destroy": (None, [P]),
         "acs_state_set": (ctypes.c_int, [P, ctypes.c_int32, DP, DP, DP, DP]),
@@ -366,6 +367,19 @@ def solve_device(problem: Problem, x_ptr: int, y_ptr: int, z_ptr: int, stream: i
     info = Info()
     _check(lib().acs_solve_device(problem.handle, ctypes.byref(settings), P(x_ptr or None), P(y_ptr or None),
                                   P(z_ptr or None), ctypes.byref(info), P(stream or None)))
+    return info
+
+
+def solve_device_noalloc(problem: Problem, x_ptr: int, y_ptr: int, z_ptr: int, stream: int = 0,
+                         settings: Optional[Settings] = None, **kw) -> Info:
+    """solve_device without device allocations (acs_solve_device_noalloc:
+    the instance lives in the library's fixed 64 MiB scratch array)."""
+    if settings is None:
+        settings = default_settings(**kw)
+    info = Info()
+    _check(lib().acs_solve_device_noalloc(problem.handle, ctypes.byref(settings), P(x_ptr or None),
+                                          P(y_ptr or None), P(z_ptr or None), ctypes.byref(info),
+                                          P(stream or None)))
     return info
 
 

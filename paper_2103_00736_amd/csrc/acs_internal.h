@@ -153,6 +153,9 @@ void ensure_device();
 class SubAllocator {
  public:
   explicit SubAllocator(size_t bytes);
+  // first-fit over caller-provided device memory [base, base + bytes)
+  // (256-B aligned); allocates nothing and frees nothing
+  SubAllocator(void* base, size_t bytes);
   ~SubAllocator();
   void* alloc(size_t bytes);  // nullptr when no free range fits
   void release(void* p);
@@ -163,6 +166,7 @@ class SubAllocator {
   Impl* impl_;
   char* base_ = nullptr;
   size_t size_ = 0;
+  bool own_ = true;
 };
 
 struct HostStatus;

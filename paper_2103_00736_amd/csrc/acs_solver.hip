@@ -101,8 +101,13 @@ SubAllocator::SubAllocator(size_t bytes) : impl_(new Impl) {
   impl_->free_by_off[0] = size_;
 }
 
+SubAllocator::SubAllocator(void* base, size_t bytes)
+    : impl_(new Impl), base_(static_cast<char*>(base)), size_(bytes & ~size_t(255)), own_(false) {
+  impl_->free_by_off[0] = size_;
+}
+
 SubAllocator::~SubAllocator() {
-  if (base_) (void)hipFree(base_);
+  if (base_ && own_) (void)hipFree(base_);
   delete impl_;
 }
 
@@ -1087,6 +1092,50 @@ void ensure_device() {
   g_device = 0;
 }
 
+// ----------------------------------------------------------------------------
+// solves that allocate nothing (acs_solve_device_noalloc)
+// ----------------------------------------------------------------------------
+// The instance's device arrays come from this file-scope array.  In host code
+// `scratch` is only a stand-in for the symbol: its device address, one per
+// GPU, comes from hipGetSymbolAddress at set-up and is the only form handed
+// to kernels and copies.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+  std::mutex mu;                                  // calls on the device share the array: one at a time
+  void* ptr = nullptr;                            // device address of `scratch` on this device
+  std::unique_ptr<SubAllocator> mem;              // first-fit over ptr (no allocation)
+  std::unique_ptr<StatusPool> status;             // one pinned progress record
+  hipStream_t stream = nullptr;                   // used when the caller passes no stream
+};
+// device 0 (the only device this library drives); never destroyed, so that
+// nothing of it is released after the HIP runtime at process exit
+static NoAllocDevice* const g_noalloc = new NoAllocDevice;
+static std::mutex g_noalloc_setup_mu;
+
+// Once per device, with the device current: the array's address, the status
+// record and the fallback stream.  Called by acs_init and by the entry point.
+static NoAllocDevice& noalloc_device() {
+  std::lock_guard<std::mutex> lk(g_noalloc_setup_mu);
+  NoAllocDevice& na = *g_noalloc;
+  if (na.ptr) return na;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    throw AcsError(ACS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  auto status = std::make_unique<StatusPool>(1);
+  hipStream_t st = nullptr;
+  HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  na.mem = std::make_unique<SubAllocator>(ptr, kNoAllocBytes);
+  na.status = std::move(status);
+  na.stream = st;
+  na.ptr = ptr;
+  return na;
+}
+
 }  // namespace acs
 
 // ============================================================================
@@ -1108,6 +1157,7 @@ int acs_init(int32_t device) {
   return guarded([&] {
     if (device != 0) throw AcsError(ACS_ERR_ARG, "only device 0 is supported");
     ensure_device();
+    noalloc_device();
   });
 }
 
@@ -1274,6 +1324,35 @@ int acs_solve_device(const acs_problem* p, const acs_settings* s, double* x, dou
       }
     }
     auto inst = make_instance(p->p, *s, static_cast<hipStream_t>(stream));
+    inst->run(inst->S.max_iter, true);
+    if (x || y || z) inst->get_device(x, y, z);
+    if (info) *info = inst->info;
+  });
+}
+
+int acs_solve_device_noalloc(const acs_problem* p, const acs_settings* s, double* x, double* y, double* z,
+                             acs_info* info, void* stream) {
+  return guarded([&] {
+    if (!p || !s) throw AcsError(ACS_ERR_ARG, "null argument");
+    ensure_device();
+    NoAllocDevice& na = noalloc_device();
+    for (const void* ptr : {static_cast<const void*>(x), static_cast<const void*>(y), static_cast<const void*>(z)}) {
+      if (!ptr) continue;
+      hipPointerAttribute_t attr;
+      if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        throw AcsError(ACS_ERR_ARG, "acs_solve_device_noalloc: x, y and z must be device allocations");
+      }
+    }
+    if (s->projection != ACS_PROJ_CG)
+      throw AcsError(ACS_ERR_ARG, "acs_solve_device_noalloc: only the CG projection (ACS_PROJ_CG)");
+    const int64_t need = instance_device_bytes(*p->p, s->precision, ACS_PROJ_CG);
+    if (need > int64_t(kNoAllocBytes))
+      throw AcsError(ACS_ERR_NOMEM, "acs_solve_device_noalloc: the problem needs " + std::to_string(need) +
+                                        " device bytes, the fixed scratch holds " + std::to_string(kNoAllocBytes));
+    std::lock_guard<std::mutex> lk(na.mu);
+    const InstanceResources res{na.mem.get(), na.status.get()};
+    auto inst = make_instance(p->p, *s, stream ? static_cast<hipStream_t>(stream) : na.stream, res);
     inst->run(inst->S.max_iter, true);
     if (x || y || z) inst->get_device(x, y, z);
     if (info) *info = inst->info;
