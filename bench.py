@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the LP (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--workload", choices=["lp2m", "batch", "serve", "copy", "gather", "dense", "dense_solve",
                                            "ablation"],
@@ -51,6 +51,13 @@ def parse():
                     help="dense --projection factor: do not also time the CG projection over the same window")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (requests/s)")
+    ap.add_argument("--workers", type=int, default=3, help="serve: worker streams of the server")
+    ap.add_argument("--small-nnz", type=int, default=200_000, help="serve: largest request of the slot pool")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="lp2m: only the timed window (no whole solves, SOCP, batch or serving sections)")
+    ap.add_argument("--serve-requests", type=int, default=160,
+                    help="lp2m: requests of the serving section (the first tenth is warm-up)")
+    ap.add_argument("--state-file", default="", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -69,7 +76,7 @@ def cpu_child(args):
             q = synth.config3(int(i))
             t, L = default_parameters(q.soc_sizes)
             Algorithm2(q.scipy_csr(), q.b, q.c, q.n_orth, q.soc_sizes, mu=1.0, t=t, schedule=L).run(
-                20000, eps=1e-4, check_every=10)
+                20000, eps=1e-4, check_every=10, obj_stop=1.0)
         dt = time.perf_counter() - t0
         print(json.dumps({"iters": len(idx), "seconds": dt, "pcg_iters": 0, "what": "solves"}), flush=True)
         return
@@ -83,19 +90,61 @@ def cpu_child(args):
         dt = time.perf_counter() - t0
         print(json.dumps({"iters": 10, "seconds": dt, "pcg_iters": 0, "what": "dense"}), flush=True)
         return
+    # the 2M-variable LP: first whole solves of a seeded subset of the batch
+    # recipe (while the GPU process warms up), then the timed iterations of
+    # the oracle from the GPU's state after its warmup
+    out = {}
+    if not args.headline_only:
+        q = synth.config0()
+        t, L = default_parameters(q.soc_sizes)
+        t0 = time.perf_counter()
+        rec = Algorithm2(q.scipy_csr(), q.b, q.c, q.n_orth, q.soc_sizes, mu=1.0, t=t, schedule=L).run(
+            20000, eps=1e-6, check_every=10, obj_stop=1.0)
+        out["lp200"] = {"iters": int(rec["iters"]), "seconds": time.perf_counter() - t0, "kkt": rec["kkt"]}
+        idx = np.random.default_rng(1).choice(4096, size=6, replace=False)
+        t0 = time.perf_counter()
+        for i in idx:
+            q = synth.config3(int(i))
+            t, L = default_parameters(q.soc_sizes)
+            Algorithm2(q.scipy_csr(), q.b, q.c, q.n_orth, q.soc_sizes, mu=1.0, t=t, schedule=L).run(
+                20000, eps=1e-4, check_every=10, obj_stop=1.0)
+        out["batch"] = {"solves": len(idx), "seconds": time.perf_counter() - t0}
+    from oracle.subspace import RangeProjector
+
     p = synth.config1(scale=args.scale)
     t, L = default_parameters(p.soc_sizes)
     alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
+    deadline = time.time() + 900
+    while not os.path.exists(args.state_file):
+        if time.time() > deadline:
+            raise RuntimeError("no state from the GPU process")
+        time.sleep(0.2)
+    with np.load(args.state_file) as z:
+        l0, s0, O0 = int(z["l"]), z["s"].astype(np.float64), z["O"].astype(np.float64)
+    # the state of iteration l0: the projector and d of steps 12-13 for its O
+    t0 = time.perf_counter()
+    alg.O = O0
+    alg.proj = RangeProjector(alg.A, O0)
+    Oc = O0 * alg.c
+    alg.d = alg.proj.pinv_apply(alg.b) + 0.5 * alg.mu * (alg.proj.reflect(Oc) - Oc)
+    alg.s = s0.copy()
+    alg.l = l0
+    setup_s = time.perf_counter() - t0
+    pcg0 = alg.proj.cg_iters
     t0 = time.perf_counter()
     for _ in range(args.cpu_iters):
         alg.step()
     dt = time.perf_counter() - t0
-    print(json.dumps({"iters": args.cpu_iters, "seconds": dt, "pcg_iters": alg.proj.cg_iters}), flush=True)
+    out["lp2m"] = {"iters": args.cpu_iters, "seconds": dt, "pcg_iters": alg.proj.cg_iters - pcg0, "from_l": l0,
+                   "setup_s": setup_s}
+    print(json.dumps(out), flush=True)
 
 
 def start_cpu_baseline(args):
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--scale", str(args.scale),
            "--cpu-iters", str(args.cpu_iters), "--workload", args.workload, "--count", str(args.count)]
+    if args.workload == "lp2m":
+        cmd += ["--state-file", args.state_file] + (["--headline-only"] if args.headline_only else [])
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env, cwd=ROOT)
 
@@ -110,6 +159,25 @@ def finish_cpu_baseline(proc, timeout_s=600):
         sys.stderr.write(err[-2000:])
         return None
     r = json.loads(out.strip().splitlines()[-1])
+    if "lp2m" in r:
+        q = r["lp2m"]
+        base = {
+            "value": q["iters"] / q["seconds"], "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": (f"outer iterations {q['from_l'] + 1}..{q['from_l'] + q['iters']} of the FP64 oracle "
+                       f"(Algorithm 2 step by step: two reflections per iteration, each projection by SciPy PCG "
+                       f"to 1e-12 relative residual from zero, {q['pcg_iters']} PCG steps in all) from the GPU's "
+                       f"state after its warmup, on the same full-size instance; the first iterations of the "
+                       f"GPU's timed window, whose CG instead stops at a 0.1 reduction warm-started from the "
+                       f"last w; single-threaded scipy.sparse SpMV, {q['seconds']:.1f} s (plus "
+                       f"{q['setup_s']:.1f} s for the projector and d of steps 12-13, not counted)"),
+        }
+        if "lp200" in r:
+            base["lp200"] = r["lp200"]
+        if "batch" in r:
+            base["batch_solves_per_s"] = r["batch"]["solves"] / r["batch"]["seconds"]
+            base["batch_sample"] = (f"{r['batch']['solves']} seeded instances of the batch recipe solved one at a "
+                                    f"time to 1e-4 KKT by the FP64 oracle, {r['batch']['seconds']:.1f} s")
+        return base
     if r.get("what") == "dense":
         return {"value": r["iters"] / r["seconds"], "unit": "iters/s", "cores": 1, "kind": "oracle",
                 "sample": f"first {r['iters']} iterations of the FP64 oracle on the same recipe at n = 3000, "
@@ -173,25 +241,101 @@ def main():
         print(f"bench.py: profiler environment ({profiled[0]}, ...) present: CPU baseline skipped",
               file=sys.stderr, flush=True)
         args.no_cpu_baseline = True
+    if args.workload == "lp2m" and not args.no_cpu_baseline:
+        import tempfile
+
+        fd, args.state_file = tempfile.mkstemp(prefix="acs_state_", suffix=".npz")
+        os.close(fd)
+        os.unlink(args.state_file)  # the child waits for the file to appear
     cpu_proc = (None if (args.no_cpu_baseline or args.workload in ("serve", "copy", "gather"))
                 else start_cpu_baseline(args))
-    if args.workload == "batch":
-        return bench_batch(args, cpu_proc)
-    if args.workload == "serve":
-        return bench_serve(args)
-    if args.workload == "copy":
-        return bench_copy()
-    if args.workload == "gather":
-        return bench_gather()
-    if args.workload == "dense_solve":
-        return bench_dense_solve(args)
-    if args.workload == "dense" and args.projection == "factor":
-        return bench_dense_factor(args, cpu_proc)
-    if args.workload == "dense":
-        return bench_dense(args, cpu_proc)
-    if args.workload == "ablation":
-        return bench_ablation()
+    try:
+        if args.workload == "batch":
+            return bench_batch(args, cpu_proc)
+        if args.workload == "serve":
+            return bench_serve(args)
+        if args.workload == "copy":
+            return bench_copy()
+        if args.workload == "gather":
+            return bench_gather()
+        if args.workload == "dense_solve":
+            return bench_dense_solve(args)
+        if args.workload == "dense" and args.projection == "factor":
+            return bench_dense_factor(args, cpu_proc)
+        if args.workload == "dense":
+            return bench_dense(args, cpu_proc)
+        if args.workload == "ablation":
+            return bench_ablation()
+        return bench_lp2m(args, cpu_proc)
+    finally:
+        if cpu_proc and cpu_proc.poll() is None:
+            cpu_proc.kill()
+        if args.state_file and os.path.exists(args.state_file):
+            os.unlink(args.state_file)
 
+
+CLS_NAMES = ("update", "resid", "cg_t", "cg_a", "check", "cond", "fin", "cg_comb")
+
+
+def timed_window(acs, prob, warmup, steps, state_file=""):
+    """Outer iterations warmup+1 .. warmup+steps of a fresh state: every kernel
+    class timed once in a replay (breakdown), then the timed region with HIP
+    events on the dominant CG kernel only, then a replay without events."""
+    cls = {k: getattr(acs, "KC_" + k.upper()) for k in CLS_NAMES}
+    st = acs.State(prob, precision=acs.PREC_MIXED)
+    st.step(warmup)
+    snap = st.get(xyz=False)  # iterate after the warmup, replayed below
+    if state_file:
+        tmp = state_file + ".part.npz"
+        np.savez(tmp, l=snap["l"], s=snap["s"], O=snap["O"])
+        os.replace(tmp, state_file)
+
+    def replay(classes):
+        st.set(snap["l"], snap["s_prev"], snap["s"], snap["O"], snap["w"])
+        cg0 = st.info().cg_steps
+        st.profile(classes if classes else False)
+        t0 = time.perf_counter()
+        st.step(steps)
+        t1 = time.perf_counter()
+        st.profile(False)
+        info = st.info()
+        return t1 - t0, info.cg_steps - cg0, info, {k: st.timing(v) for k, v in cls.items()}
+
+    _, _, _, prof_all = replay(list(cls.values()))
+    dom = max(("cg_a", "cg_t"), key=lambda k: prof_all[k][1])
+    _progress(f"timed region: {steps} iterations")
+    elapsed, cg_timed, info, prof = replay([cls[dom]])
+    no_ev_s, no_ev_cg, _, _ = replay(None)
+    st.close()
+    return {"elapsed": elapsed, "cg": cg_timed, "info": info, "dom": dom, "dom_timing": prof[dom],
+            "prof_all": prof_all, "no_ev_s": no_ev_s, "no_ev_cg": no_ev_cg}
+
+
+def roofline_of(win, m, n, nnz, workload):
+    kb = kernel_bytes(m, n, nnz)
+    dom = win["dom"]
+    count, total_ms = win["dom_timing"]
+    # CG launches issued after the device-side stop test has fired exit at once;
+    # their (small) time is charged to the working launches: an upper bound
+    avg_ms = total_ms / max(win["cg"], 1)
+    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": {"cg_a": "k_cg_a_part", "cg_t": "k_cg_t"}[dom], "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_record(dom, workload), "avg_launch_ms": avg_ms, "launches": count,
+            "working_launches": win["cg"], "algorithmic_bytes_per_launch": kb[dom]}
+
+
+def whole_solve(acs, prob, p, eps=1e-4):
+    """A whole solve from the initial state to eps KKT (acs_solve)."""
+    x, y, z, info = acs.solve(prob, eps_kkt=eps, max_iter=20000)
+    return {"status": {acs.SOLVED: "solved"}.get(info.status, f"status {info.status}"),
+            "iterations": info.iterations, "cg_steps": info.cg_steps, "solve_s": info.solve_ms * 1e-3,
+            "setup_s": info.setup_ms * 1e-3, "iters_per_s": info.iterations / max(info.solve_ms * 1e-3, 1e-9),
+            "kkt": info.kkt, "eps_obj": info.eps_obj,
+            "objective_rel_error": abs(info.pobj - p.p_star) / (1.0 + abs(p.p_star))}
+
+
+def bench_lp2m(args, cpu_proc):
     from paper_2103_00736_amd import acs, synth
 
     t0 = time.perf_counter()
@@ -201,52 +345,51 @@ def main():
     if rc != 0:
         raise RuntimeError(acs.lib().acs_last_error().decode())
     prob = acs.Problem.from_synth(p)
-    st = acs.State(prob, precision=acs.PREC_MIXED)
-    st.step(args.warmup)
-    snap = st.get(xyz=False)  # iterate after the warmup, replayed below without events
-    cls = {"update": acs.KC_UPDATE, "resid": acs.KC_RESID, "cg_t": acs.KC_CG_T, "cg_a": acs.KC_CG_A,
-           "check": acs.KC_CHECK, "cond": acs.KC_COND, "fin": acs.KC_FIN, "cg_comb": acs.KC_CG_COMB}
-
-    def replay(classes):
-        """The K timed iterations from the saved iterate; HIP events around the
-        launches of `classes` on the solver's stream; synchronised on both sides
-        (step() syncs on return)."""
-        st.set(snap["l"], snap["s_prev"], snap["s"], snap["O"], snap["w"])
-        cg0 = st.info().cg_steps
-        st.profile(classes if classes else False)
-        t0 = time.perf_counter()
-        st.step(args.steps)
-        t1 = time.perf_counter()
-        st.profile(False)
-        info = st.info()
-        return t1 - t0, info.cg_steps - cg0, info, {k: st.timing(v) for k, v in cls.items()}
-
-    # every class once (breakdown; per-launch events slow the loop), then the timed
-    # region with events around the dominant kernel only
-    _, _, _, prof_all = replay(list(cls.values()))
-    dom = max(("cg_a", "cg_t"), key=lambda k: prof_all[k][1])
-    print(f"[bench] timed region: {args.steps} iterations", file=sys.stderr, flush=True)
-    elapsed, cg_timed, info1, prof = replay([cls[dom]])
-    no_ev_s, no_ev_cg, _, _ = replay(None)
-
-    kb = kernel_bytes(p.m, p.n, p.nnz)
-    count, total_ms = prof[dom]
-    # CG launches issued after the device-side stop test has fired exit at once; their
-    # (small) time is charged to the working launches, so avg_ms is an upper bound
-    avg_ms = total_ms / max(cg_timed, 1)
-    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_record(dom)
-
+    win = timed_window(acs, prob, args.warmup, args.steps, args.state_file)
+    info1 = win["info"]
+    roof = roofline_of(win, p.m, p.n, p.nnz, "lp2m")
+    detail = {
+        "cg_steps_per_iter": win["cg"] / args.steps,
+        "kkt_after": info1.kkt, "eps_p": info1.eps_p, "eps_d": info1.eps_d, "eps_gap": info1.eps_gap,
+        "pobj": info1.pobj, "p_star": p.p_star,
+        "kernel_ms": {k: {"count": v[0], "total_ms": round(v[1], 3)} for k, v in win["prof_all"].items()},
+        "kernel_ms_what": "every kernel class timed with events in a replay of the timed iterations",
+        "timed_s": win["elapsed"], "gen_s": gen_s,
+        "replay_without_events": {"iters_per_s": args.steps / win["no_ev_s"], "timed_s": win["no_ev_s"],
+                                  "cg_steps": win["no_ev_cg"],
+                                  "what": "the timed iterations replayed from the saved iterate without "
+                                          "per-launch HIP events"},
+    }
+    if not args.headline_only:
+        _progress("2M-variable LP: whole solve")
+        detail["lp2m_whole_solve"] = whole_solve(acs, prob, p)
+        del prob
+        q0 = synth.config0()
+        x0, y0, z0, i0 = acs.solve(acs.Problem.from_synth(q0), precision=acs.PREC_FP64, eps_kkt=1e-6, max_iter=20000)
+        detail["lp200_fp64"] = {"workload": "LP 200x500, 2% density, FP64 end to end, to 1e-6 KKT",
+                                "status": {acs.SOLVED: "solved"}.get(i0.status, f"status {i0.status}"),
+                                "iterations": i0.iterations, "solve_s": i0.solve_ms * 1e-3, "kkt": i0.kkt,
+                                "objective_rel_error": abs(i0.pobj - q0.p_star) / (1 + abs(q0.p_star))}
+        detail["socp1m"] = socp_section(acs, synth, args)
+        detail["batch4096"] = batch_section(acs, synth, args.count)
+        detail["serve"] = serve_section(acs, synth, args.serve_requests, 200.0, args.workers, args.small_nnz)
     cpu = finish_cpu_baseline(cpu_proc) if cpu_proc else None
-    it_per_s = args.steps / elapsed
+    if cpu and "lp200" in cpu:
+        o = cpu.pop("lp200")
+        if "lp200_fp64" in detail:
+            detail["lp200_fp64"]["oracle"] = {"iterations": o["iters"], "solve_s": o["seconds"], "kkt": o["kkt"],
+                                              "cores": 1, "what": "the FP64 oracle's whole solve, same rule"}
+    if cpu and "batch_solves_per_s" in cpu and "batch4096" in detail:
+        detail["batch4096"]["oracle_solves_per_s"] = cpu.pop("batch_solves_per_s")
+        detail["batch4096"]["oracle_sample"] = cpu.pop("batch_sample") + " (1 core)"
     line = {
         "metric": "iters/sec + HBM GB/s (2M-var LP); batched solves/sec, p99 latency at 1e-4 KKT",
-        "value": it_per_s,
+        "value": args.steps / win["elapsed"],
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * win["elapsed"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -256,26 +399,29 @@ def main():
                                f"(Algorithm 2, mu=1, t=9.2, L={{300,400,...}}, iterations {args.warmup + 1}.."
                                f"{args.warmup + args.steps})",
                    "precision": "FP32 matrix/iterate/CG vectors, FP64 CG solution, residual sweeps and reductions"},
-        "roofline": {"bound": "hbm", "kernel": {"cg_a": "k_cg_a_part", "cg_t": "k_cg_t"}[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_ms": avg_ms, "launches": count, "working_launches": cg_timed,
-                     "algorithmic_bytes_per_launch": kb[dom]},
+        "roofline": roof,
         "cpu_baseline": cpu,
-        "detail": {
-            "cg_steps_per_iter": cg_timed / args.steps,
-            "kkt_after": info1.kkt, "eps_p": info1.eps_p, "eps_d": info1.eps_d, "eps_gap": info1.eps_gap,
-            "pobj": info1.pobj, "p_star": p.p_star,
-            "kernel_ms": {k: {"count": v[0], "total_ms": round(v[1], 3)} for k, v in prof_all.items()},
-            "kernel_ms_what": "every kernel class timed with events in a replay of the timed iterations",
-            "timed_s": elapsed, "gen_s": gen_s,
-            "replay_without_events": {"iters_per_s": args.steps / no_ev_s, "timed_s": no_ev_s,
-                                      "cg_steps": no_ev_cg,
-                                      "what": "the timed iterations replayed from the saved iterate without "
-                                              "per-launch HIP events"},
-        },
+        "detail": detail,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def socp_section(acs, synth, args):
+    """The 1M-variable SOCP: iterations/s over the same window as the LP, with
+    the dominant kernel's roofline, and a whole solve."""
+    t0 = time.perf_counter()
+    q = synth.config2()
+    gen_s = time.perf_counter() - t0
+    _progress(f"SOCP {q.m}x{q.n}: window and whole solve")
+    prob = acs.Problem.from_synth(q)
+    win = timed_window(acs, prob, args.warmup, args.steps)
+    return {"workload": f"SOCP m={q.m} n={q.n} nnz={q.nnz}, {len(q.soc_sizes)} Lorentz cones U{{3..50}} "
+                        f"+ {q.n_orth} orthant, iterations {args.warmup + 1}..{args.warmup + args.steps}",
+            "iters_per_s": args.steps / win["elapsed"], "cg_steps_per_iter": win["cg"] / args.steps,
+            "iters_per_s_without_events": args.steps / win["no_ev_s"],
+            "roofline": roofline_of(win, q.m, q.n, q.nnz, "socp1m"),
+            "whole_solve": whole_solve(acs, prob, q), "gen_s": gen_s}
 
 
 def bench_copy():
@@ -313,7 +459,11 @@ def bench_gather():
     if rc != 0:
         raise RuntimeError(acs.lib().acs_last_error().decode())
     cases = [("uniform rows, m=500k (2 MB gathered by A^T x)", lambda: synth.lp_percol(500_000, 2_000_000, 5, 11)),
+             ("uniform rows, m=131072 (512 KB gathered by A^T x)", lambda: synth.lp_percol(131072, 2_000_000, 5, 13)),
+             ("uniform rows, m=32768 (128 KB gathered by A^T x)", lambda: synth.lp_percol(32768, 2_000_000, 5, 14)),
              ("uniform rows, m=8192 (32 KB gathered by A^T x)", lambda: synth.lp_percol(8192, 2_000_000, 5, 12)),
+             ("uniform rows, m=64 (256 B gathered by A^T x: every gather hits L1)",
+              lambda: synth.lp_percol(64, 2_000_000, 5, 15)),
              ("2M-variable LP, power-law rows", lambda: synth.config1())]
     out = {}
     dev = torch.device("cuda:0")
@@ -586,7 +736,7 @@ def bench_ablation():
     out = {}
     for name, (f, e, last) in sched.items():
         _progress(f"schedule {name}")
-        b = acs.Batch(handles, eps_kkt=1e-6, max_iter=20000, auto_params=0, t=9.2, mu=1.0, check_every=10,
+        b = acs.Batch(handles, eps_kkt=1e-6, max_iter=20000, auto_params=0, t=9.2, mu=1.0, check_every=10, obj_stop=0,
                       l_first=f, l_every=e, l_last=last)
         ms = b.run(20000)
         gpu = [b.result(i)[3].iterations for i in range(len(probs))]
@@ -615,25 +765,23 @@ def _base_line(metric, value, unit, config, steps=1, ms=None):
             "data": "synthetic", "config": config}
 
 
-def bench_batch(args, cpu_proc):
-    """4096 small LPs (m ~ U{50..2000}, n = 2.5m, 1% density) in one persistent launch."""
-    from paper_2103_00736_amd import acs, synth
-
-    assert acs.lib().acs_init(0) == 0
+def batch_section(acs, synth, count):
+    """`count` small LPs of the batch recipe in one persistent launch, against
+    the plain one-instance GPU solver on a seeded subset."""
     t0 = time.perf_counter()
-    probs = [synth.config3(i) for i in range(args.count)]
+    probs = [synth.config3(i) for i in range(count)]
     handles = [acs.Problem.from_synth(p) for p in probs]
     gen_s = time.perf_counter() - t0
-    _progress(f"generated {len(probs)} instances in {gen_s:.1f} s")
+    _progress(f"generated {len(probs)} batch instances in {gen_s:.1f} s")
     b = acs.Batch(handles, eps_kkt=1e-4, max_iter=20000)
     t1 = time.perf_counter()
     b.autotune(sample=4, iters=20, cache_path=os.path.join("/tmp", "acs_lanes_gfx950.txt"))
     tune_s = time.perf_counter() - t1
-    _progress(f"autotuned in {tune_s:.1f} s")
     ms = b.run(20000)
     _progress(f"batch launch {ms:.1f} ms")
     infos = [b.result(i, xyz=False)[3] for i in range(len(probs))]
     solved = sum(1 for f in infos if f.status == acs.SOLVED)
+    obj = [abs(f.pobj - p.p_star) / (1.0 + abs(p.p_star)) for p, f in zip(probs, infos)]
     # algorithmic bytes moved by the launch (mixed precision: FP32 CG sweeps, FP64 residual/update sweeps)
     byts = 0.0
     for p, f in zip(probs, infos):
@@ -642,53 +790,56 @@ def bench_batch(args, cpu_proc):
         it = (4 * (m + 1) + 12 * nnz + 4 * n + 12 * m) + (4 * (n + 1) + 12 * nnz + 8 * m + 20 * n)
         byts += f.cg_steps * cg + f.iterations * it
     achieved = byts / (ms * 1e-3) / 1e9
+    b.close()
     # the plain one-instance GPU solver on a seeded subset, one at a time
-    sub = np.random.default_rng(2).choice(len(probs), size=24, replace=False)
+    sub = np.random.default_rng(2).choice(len(probs), size=min(24, len(probs)), replace=False)
     t2 = time.perf_counter()
     for i in sub:
         acs.solve(handles[int(i)], eps_kkt=1e-4, max_iter=20000)
     per = (time.perf_counter() - t2) / len(sub)
-    _progress(f"one-at-a-time sample {per * 1e3:.1f} ms per solve")
     value = len(probs) / (ms * 1e-3)
+    return {"workload": f"{len(probs)} planted sparse LPs, m~U{{50..2000}}, n=2.5m, 1% density, "
+                        f"sum nnz={sum(p.nnz for p in probs)}, one persistent graph-launched kernel",
+            "solves_per_s": value, "launch_ms": ms, "solved": solved, "count": len(probs),
+            "max_gpu_kkt": max(f.kkt for f in infos), "max_objective_rel_error": max(obj),
+            "objective_rel_error_above_1e-4": [int(i) for i in np.nonzero(np.array(obj) > 1e-4)[0]],
+            "mean_iterations": float(np.mean([f.iterations for f in infos])),
+            "one_at_a_time_gpu_solves_per_s": 1.0 / per,
+            "one_at_a_time_sample": f"{len(sub)} seeded instances solved sequentially by acs_solve",
+            "speedup_vs_one_at_a_time": value * per,
+            "roofline": {"bound": "hbm", "kernel": "k_batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic_record("batch", "batch4096", "acs_batch.hip"),
+                         "avg_launch_ms": ms, "launches": 1},
+            "gen_s": gen_s, "autotune_s": tune_s}
+
+
+def bench_batch(args, cpu_proc):
+    """4096 small LPs (m ~ U{50..2000}, n = 2.5m, 1% density) in one persistent launch."""
+    from paper_2103_00736_amd import acs, synth
+
+    assert acs.lib().acs_init(0) == 0
+    d = batch_section(acs, synth, args.count)
     cpu = finish_cpu_baseline(cpu_proc) if cpu_proc else None
-    line = _base_line("batched solves/sec at 1e-4 KKT", value, "solves/s",
-                      {"workload": f"{len(probs)} planted sparse LPs, m~U{{50..2000}}, n=2.5m, 1% density, "
-                                   f"sum nnz={sum(p.nnz for p in probs)}, one persistent graph-launched kernel",
-                       "precision": "FP32 CG sweeps, FP64 residual/update sweeps and reductions"}, 1, ms)
-    line["roofline"] = {"bound": "hbm", "kernel": "k_batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "avg_launch_ms": ms, "launches": 1}
+    line = _base_line("batched solves/sec at 1e-4 KKT", d["solves_per_s"], "solves/s",
+                      {"workload": d["workload"],
+                       "precision": "FP32 CG sweeps, FP64 residual/update sweeps and reductions"}, 1, d["launch_ms"])
+    line["roofline"] = d.pop("roofline")
     line["cpu_baseline"] = cpu
-    line["detail"] = {"solved": solved, "count": len(probs), "launch_ms": ms,
-                      "one_at_a_time_gpu_solves_per_s": 1.0 / per,
-                      "one_at_a_time_sample": f"{len(sub)} seeded instances solved sequentially by acs_solve",
-                      "speedup_vs_one_at_a_time": value * per, "max_gpu_kkt": max(f.kkt for f in infos),
-                      "mean_iterations": float(np.mean([f.iterations for f in infos])),
-                      "gen_s": gen_s, "autotune_s": tune_s}
+    line["detail"] = d
     print(json.dumps(line), flush=True)
     return 0
 
 
-def bench_serve(args):
-    """Poisson request stream (70% LP / 30% SOCP, m log-uniform in [1e3, 2e5]) through the serving loop."""
-    from paper_2103_00736_amd import acs, synth
-
-    assert acs.lib().acs_init(0) == 0
-    trace = synth.config4_trace(args.requests, rate_per_s=args.rate)
-    t0 = time.perf_counter()
-    handles = []
-    for k, r in enumerate(trace):
-        handles.append(acs.Problem.from_synth(r.problem()))
-        if k % 25 == 0:
-            _progress(f"generated {k + 1}/{len(trace)} requests")
-    gen_s = time.perf_counter() - t0
-    srv = acs.Server(hbm_budget=160 << 30, max_slots=512, small_nnz=200_000, workers=3, tick_iters=50)
+def _serve_run(acs, srv_kw, trace, handles, arrivals, warm):
+    """Submit every request at its arrival time (a client thread) and wait for all."""
+    srv = acs.Server(**srv_kw)
     tickets = [None] * len(trace)
     start = time.perf_counter()
 
     def client():
-        for i, r in enumerate(trace):
-            delay = start + r.arrival_s - time.perf_counter()
+        for i in range(len(trace)):
+            delay = start + arrivals[i] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
             tickets[i] = srv.submit(handles[i], eps_kkt=1e-4, max_iter=20000)
@@ -700,33 +851,70 @@ def bench_serve(args):
     for i in range(len(trace)):
         x, y, z, info = srv.wait(tickets[i], -1)
         res.append(info)
-        if i % 25 == 0:
-            _progress(f"request {i} done, latency {info.latency_ms:.0f} ms")
     end = time.perf_counter()
-    warm = max(1, len(trace) // 10)
-    lat = np.array([f.latency_ms for f in res[warm:]])
-    solved = sum(1 for f in res if f.status == acs.SOLVED)
-    value = len(res) / (end - start)
     st = srv.stats()
     srv.close()
+    lat = np.array([f.latency_ms for f in res[warm:]])
+    queue = np.array([f.queue_ms for f in res[warm:]])
+    half = len(lat) // 2
+    return {"requests": len(res), "warmup_excluded": warm,
+            "offered_rate": (len(trace) - 1) / max(arrivals[-1], 1e-9), "solves_per_s": len(res) / (end - start),
+            "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+            "mean_queue_ms": float(np.mean(queue)),
+            "queue_ms_first_half_vs_second_half": [float(np.mean(queue[:half])), float(np.mean(queue[half:]))],
+            "solved": sum(1 for f in res if f.status == acs.SOLVED), "makespan_s": end - start,
+            "peak_resident": st["peak_running"], "pool_ticks": st["ticks"]}
+
+
+def serve_section(acs, synth, requests, rate, workers, small_nnz):
+    """Poisson request stream (70% LP / 30% SOCP, m log-uniform in [1e3, 2e5])
+    through the serving loop at the offered rate, then the same requests at
+    a rate the server sustains (3/4 of the throughput it reached)."""
+    trace = synth.config4_trace(requests, rate_per_s=rate)
+    t0 = time.perf_counter()
+    probs = []
+    for k, r in enumerate(trace):
+        probs.append(r.problem())
+        if k % 40 == 0:
+            _progress(f"generated {k + 1}/{len(trace)} requests")
+    handles = [acs.Problem.from_synth(q) for q in probs]
+    gen_s = time.perf_counter() - t0
+    srv_kw = dict(hbm_budget=160 << 30, max_slots=512, small_nnz=small_nnz, workers=workers, tick_iters=50)
+    warm = max(1, len(trace) // 10)
+    arrivals = np.array([r.arrival_s for r in trace])
+    _progress(f"serving {len(trace)} requests at {rate:g}/s")
+    offered = _serve_run(acs, srv_kw, trace, handles, arrivals, warm)
+    sustained_rate = 0.75 * offered["solves_per_s"]
+    _progress(f"serving them again at {sustained_rate:.2f}/s")
+    sustained = _serve_run(acs, srv_kw, trace, handles, arrivals * (rate / sustained_rate), warm)
     sub = list(range(0, len(trace), max(1, len(trace) // 12)))[:12]
     t2 = time.perf_counter()
     for i in sub:
         acs.solve(handles[i], eps_kkt=1e-4, max_iter=20000)
     per = (time.perf_counter() - t2) / len(sub)
-    line = _base_line("served solves/sec and latency at 1e-4 KKT", value, "solves/s",
-                      {"workload": f"{len(trace)} requests, Poisson {args.rate:g}/s, 70% LP / 30% SOCP, "
-                                   f"m log-uniform [1e3, 2e5], n=3m, 6 nnz/column, SOC sizes U{{3..30}}",
-                       "server": "small_nnz=200k pool (persistent kernel ticks of 50 iterations) + 3 worker streams"},
-                      len(res), 1e3 * (end - start) / len(res))
+    return {"workload": f"{len(trace)} requests of the Poisson trace, 70% LP / 30% SOCP, m log-uniform "
+                        f"[1e3, 2e5], n=3m, 6 nnz/column, SOC sizes U{{3..30}}, sum nnz={sum(q.nnz for q in probs)}",
+            "server": f"small_nnz={small_nnz} pool (persistent kernel ticks of 50 iterations) + {workers} worker "
+                      f"streams",
+            "at_offered_rate": offered, "at_sustainable_rate": sustained,
+            "one_at_a_time_gpu_solves_per_s": 1.0 / per,
+            "one_at_a_time_sample": f"{len(sub)} requests of the trace solved sequentially by acs_solve",
+            "gen_s": gen_s}
+
+
+def bench_serve(args):
+    """The serving section on its own (--requests, --rate, --workers, --small-nnz)."""
+    from paper_2103_00736_amd import acs, synth
+
+    assert acs.lib().acs_init(0) == 0
+    d = serve_section(acs, synth, args.requests, args.rate, args.workers, args.small_nnz)
+    o = d["at_offered_rate"]
+    line = _base_line("served solves/sec and latency at 1e-4 KKT", o["solves_per_s"], "solves/s",
+                      {"workload": d["workload"], "server": d["server"]}, o["requests"],
+                      1e3 * o["makespan_s"] / o["requests"])
     line["roofline"] = None
     line["cpu_baseline"] = None
-    line["detail"] = {"p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
-                      "mean_queue_ms": float(np.mean([f.queue_ms for f in res[warm:]])), "solved": solved,
-                      "offered_rate": args.rate, "makespan_s": end - start,
-                      "one_at_a_time_gpu_solves_per_s": 1.0 / per,
-                      "one_at_a_time_sample": f"{len(sub)} requests of the trace solved sequentially by acs_solve",
-                      "peak_resident": st["peak_running"], "pool_ticks": st["ticks"], "gen_s": gen_s}
+    line["detail"] = d
     print(json.dumps(line), flush=True)
     return 0
 

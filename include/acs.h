@@ -80,12 +80,28 @@ extern "C" {
  * With `auto_params` = 1 the library picks the paper's per-class values:
  * LP: t = 9.2, L = {300, 400, ...}; SOCP: t = 1.7, L = {200, 300, ...}; mu = 1.
  * Projection (Alg. 2 step 17) by warm-started CG, defaults cg_reduce = 0.1,
- * cg_max = 500; obj_stop = 4.  The iteration just before a conditioning
+ * cg_max = 500; obj_stop = 1.  The iteration just before a conditioning
  * event (its x, z set O) runs its CG to a 1e-6 reduction with up to 8 cg_max
  * steps.  A cap that
  * stops the CG short of cg_reduce leaves an error the outer iteration may not
  * recover from once O is spread; smaller cg_reduce trades CG steps for outer
  * iterations (0.03 solves the 2M-variable LP fastest).
+ */
+/*
+ * Equilibration (settings.equilibrate = 1; sparse problems, one-instance
+ * paths and the server's worker streams; the batch kernel refuses it).  Sec.
+ * III preconditions the data as A_hat = D A E, b_hat = D b, c_hat = E c
+ * (x_hat = E^{-1} x, z_hat = E z) and compares adaptive conditioning with the
+ * D, E of an l2 Sinkhorn-Knopp balancing.  The library takes the plain
+ * balancing of the squared entries: from E = 1, eq_sweeps sweeps of
+ * D_i^2 = 1 / sum_j a_ij^2 E_j^2 (unit row norms), then
+ * E_j^2 = (m/n) / sum_i a_ij^2 D_i^2 (column norms sqrt(m/n)), with one E per
+ * Lorentz cone (its columns' mean square norm m/n) and 1 for empty rows and
+ * columns; all in FP64 on the GPU.  Algorithm 2 then runs on the
+ * preconditioned problem with its own O on top; in the original variables
+ * that is the column scaling E O_hat, with the ratio of steps 5-10 taken from
+ * x_hat, z_hat.  D drops out (neither range((D A E)^T) nor the affine set
+ * depends on it), and results are returned in the original variables.
  */
 typedef struct acs_settings {
   double mu;            /* proximal parameter mu > 0                            */
@@ -103,8 +119,10 @@ typedef struct acs_settings {
   double cg_abs;        /* ... or once ||r|| <= cg_abs (scaled system)          */
   int32_t verbose;      /* 0 quiet, 1 one line per check on stderr              */
   int32_t projection;   /* ACS_PROJ_CG (default) or ACS_PROJ_FACTOR              */
-  int32_t obj_stop;     /* k > 0: a check also needs k * eps_obj <= eps_kkt (default 4); 0: KKT only */
-  int32_t reserved[5];
+  int32_t obj_stop;     /* k > 0: a check also needs k * eps_obj <= eps_kkt (default 1); 0: KKT only */
+  int32_t equilibrate;  /* 1: Sinkhorn-Knopp column scaling E first (Sec. III, below); 0 (default): none */
+  int32_t eq_sweeps;    /* sweeps of that equilibration (default 25)              */
+  int32_t reserved[3];
 } acs_settings;
 
 /* Per-solve report.  KKT errors follow the oracle's definition:
@@ -112,14 +130,12 @@ typedef struct acs_settings {
  *   eps_gap = |c^T x - b^T y|/(1+|c^T x|+|b^T y|),
  *   eps_cone = max(dist(x,K), dist(z,K))/(1+max(||x||,||z||)).
  * Those are relative to the norms of b and c, so they do not bound the
- * relative error of the objective.  Weak duality (Sec. II) does: with
- * r_p = Ax-b and r_d = A^T y+z-c, c^T x - p* lies between y*^T r_p and
- * c^T x - b^T y + r_d^T x* for x, z in K, which the current (x, y) estimate
- * up to second-order terms:
- *   eps_obj = max(|y^T r_p|, |c^T x - b^T y + r_d^T x|)/(1+|c^T x|).
- * The second-order terms are not negligible near eps_kkt = 1e-4: on planted
- * LPs the estimate fell short of the true error by up to a factor of about 3,
- * so with settings.obj_stop = k (default 4) a solve stops only when
+ * relative error of the objective.  For an optimal pair (y*, z*) of the dual
+ * (Sec. II), with r_p = Ax-b, c^T x - p* = z*^T x + y*^T r_p exactly; the
+ * estimate takes the first term's bound cone by cone in absolute value, at
+ * the current y, z (an orthant coordinate is a cone of one):
+ *   eps_obj = (sum_C |x_C^T z_C| + |y^T r_p|)/(1+|c^T x|).
+ * With settings.obj_stop = k (default 1) a solve stops only when
  * kkt <= eps_kkt and k * eps_obj <= eps_kkt.                              */
 typedef struct acs_info {
   int32_t status;       /* ACS_SOLVED / ACS_MAX_ITER / ACS_NUMERIC / ACS_CANCELLED */

@@ -174,9 +174,10 @@ class Algorithm2:
         return kkt_errors(self.A, self.b, self.c, self.n_orth, self.soc_sizes, self.x, self.dual_multiplier(), self.z)
 
     def run(self, max_iter: int, eps: float = 0.0, check_every: int = 10,
-            callback: Optional[Callable[["Algorithm2"], None]] = None) -> Dict[str, float]:
-        """Iterate until kkt <= eps at a check (every `check_every` iterations)
-        or max_iter iterations; returns the last KKT record (with 'iters')."""
+            callback: Optional[Callable[["Algorithm2"], None]] = None, obj_stop: float = 0.0) -> Dict[str, float]:
+        """Iterate until kkt <= eps at a check (every `check_every` iterations),
+        and also obj_stop * eps_obj <= eps when obj_stop > 0, or max_iter
+        iterations; returns the last KKT record (with 'iters')."""
         rec: Dict[str, float] = {}
         while self.l < max_iter:
             self.step()
@@ -184,7 +185,7 @@ class Algorithm2:
                 callback(self)
             if eps > 0 and (self.l % check_every == 0 or self.l == max_iter):
                 rec = self.kkt()
-                if rec["kkt"] <= eps:
+                if rec["kkt"] <= eps and obj_stop * rec["eps_obj"] <= eps:
                     break
         if not rec or rec.get("iters") != self.l:
             rec = self.kkt()

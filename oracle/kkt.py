@@ -14,21 +14,29 @@ x^T z = 0; x, z in K) as relative errors:
     kkt   = max(eps_p, eps_d, eps_g, eps_K)
 
 Those terms are normalised by the norms of b and c, so a point that meets
-them can still carry a larger relative error in the objective.  Weak duality
-(Sec. II) bounds that error.  With r_p = A x - b and r_d = A^T y + z - c, for
-any optimal pair (x*, y*, z*) and x, z in K:
+them can still carry a larger relative error in the objective.  For any
+optimal pair (y*, z*) of the dual (Sec. II), with r_p = A x - b and
+r_d = A^T y + z - c, expanding c = A^T y* + z* and b = A x - r_p gives the
+identity
 
-    c^T x - p* = z*^T x + y*^T r_p            >= y*^T r_p
-    c^T x - p* = (c^T x - b^T y) + r_d^T x* - z^T x*  <= (c^T x - b^T y) + r_d^T x*
+    c^T x - p* = z*^T x + y*^T r_p,
 
-(expand c = A^T y + z - r_d and b = A x - r_p; z^T x*, z*^T x >= 0 on K).
-Replacing (x*, y*) by the current (x, y) changes each bound by a product of
-two small quantities, which gives the estimate
+so |c^T x - p*| <= sum over the cones of |x_C^T z*_C| + |y*^T r_p|.  The
+estimate takes that bound at the current (y, z):
 
-    eps_obj = max(|y^T r_p|, |c^T x - b^T y + r_d^T x|) / (1 + |c^T x|)
+    eps_obj = (sum_C |x_C^T z_C| + |y^T r_p|) / (1 + |c^T x|)
 
-of |c^T x - p*| / (1 + |c^T x|).  `objective_bounds` returns the two exact
-bounds for a known optimum, used to pin the estimate.
+(an orthant coordinate is a cone of one).  Replacing (y*, z*) by (y, z)
+changes the bound by products of two small quantities wherever x* and z* are
+complementary coordinate by coordinate, as on the orthant: there |x_j| is
+small where z*_j is not, and |z_j| itself is the error where x*_j is not.
+The absolute values keep complementarity terms of opposite signs (x or z
+slightly outside the cone) from cancelling, so the estimate bounds the
+weak-duality form |c^T x - b^T y + r_d^T x| = |x^T z + y^T r_p| and |y^T r_p|
+too.  The row sum stays signed: the residual r_p of a first-order method is
+spread over the rows, and row-by-row absolute values would count it about
+sqrt(m) times over.  `objective_bounds` returns the exact two-sided
+weak-duality bounds for a known optimum, used to pin the estimate.
 
 `dual_multiplier_ls` gives the multiplier implicit in eq. stopcri's dual
 objective (A^dagger b)^T (c - z) = b^T (A A^T)^+ A (c - z).
@@ -40,7 +48,7 @@ from typing import Dict, Sequence
 import numpy as np
 import scipy.sparse as sp
 
-from .cones import dist_K
+from .cones import blocks, dist_K
 from .subspace import RangeProjector
 
 
@@ -60,7 +68,9 @@ def kkt_errors(A: sp.csr_matrix, b: np.ndarray, c: np.ndarray, n_orth: int, soc_
     eps_g = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
     eps_k = max(dist_K(x, n_orth, soc_sizes), dist_K(z, n_orth, soc_sizes)) / (
         1.0 + max(float(np.linalg.norm(x)), float(np.linalg.norm(z))))
-    eps_obj = max(abs(float(y @ rp)), abs(pobj - dobj + float(rd @ x))) / (1.0 + abs(pobj))
+    xz = abs(x * z) if not len(soc_sizes) else np.abs([float(x[st:st + k] @ z[st:st + k])
+                                                        for st, k in blocks(n_orth, soc_sizes)])
+    eps_obj = (float(np.sum(xz)) + abs(float(rp @ y))) / (1.0 + abs(pobj))
     return {"eps_p": eps_p, "eps_d": eps_d, "eps_g": eps_g, "eps_k": eps_k,
             "kkt": max(eps_p, eps_d, eps_g, eps_k), "pobj": pobj, "dobj": dobj, "eps_obj": eps_obj}
 

@@ -57,7 +57,8 @@ class Settings(ctypes.Structure):
         ("auto_params", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("eps_kkt", ctypes.c_double), ("precision", ctypes.c_int32), ("cg_max", ctypes.c_int32),
         ("cg_reduce", ctypes.c_double), ("cg_abs", ctypes.c_double), ("verbose", ctypes.c_int32),
-        ("projection", ctypes.c_int32), ("obj_stop", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+        ("projection", ctypes.c_int32), ("obj_stop", ctypes.c_int32), ("equilibrate", ctypes.c_int32),
+        ("eq_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -215,9 +215,9 @@ __device__ void sweep_update(BInst& I, int mode, bool check, double (&acc)[9], S
           acc[3] += mx * mx;
           acc[4] += mz * mz;
         }
+        if (orth) acc[8] += fabs(x * z);  // |x_j z_j| of the objective-error estimate
         const double dr = (pj - sn - 2.0 * zt) / (2.0 * mu * Oj);
         acc[5] += dr * dr;
-        acc[8] += x * dr;  // r_d^T x of the objective-error estimate
       }
     }
     if (mode != 2) {
@@ -233,13 +233,15 @@ __device__ void sweep_update(BInst& I, int mode, bool check, double (&acc)[9], S
     if (check) {  // cone distances of x and z (written above)
       for (int cone = threadIdx.x; cone < I.n_soc; cone += kBB) {
         const int off = I.soc_off[cone], end = I.soc_off[cone + 1];
-        double nx = 0, nz = 0;
+        double nx = 0, nz = 0, xz = I.x[off] * I.z[off];
         for (int e = off + 1; e < end; ++e) {
           nx += I.x[e] * I.x[e];
           nz += I.z[e] * I.z[e];
+          xz += I.x[e] * I.z[e];
         }
         acc[6] += ldist2(I.x[off], sqrt(nx));
         acc[7] += ldist2(I.z[off], sqrt(nz));
+        acc[8] += fabs(xz);  // |x_C^T z_C|
       }
     }
     if (mode != 2) cones_next(I, mode == 0 ? s : sn_out);
@@ -493,7 +495,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
         const double yi = -I.dinv[i] * I.w[i] / mu;
         I.y[i] = yi;
         a2[1] += I.b[i] * yi;
-        a2[2] += yi * res;
+        a2[2] += yi * res;  // y^T r_p of the objective-error estimate
       };
       bsweep<double>(I, 0, prod, epi, sh);
       double tot[9];
@@ -508,8 +510,8 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
       e[4] = fmax(fmax(e[0], e[1]), fmax(e[2], e[3]));
       e[5] = ctx;
       e[6] = bty;
-      // weak-duality estimate of the objective's relative error (see acs.h)
-      const double eobj = fmax(fabs(ytrp), fabs(ctx - bty + tot[8])) / (1.0 + fabs(ctx));
+      // estimate of the objective's relative error (see acs.h)
+      const double eobj = (tot[8] + fabs(ytrp)) / (1.0 + fabs(ctx));
       bool nan = bad || !(eobj == eobj) || isinf(eobj);
       for (int i = 0; i < 7; ++i)
         if (!(e[i] == e[i]) || isinf(e[i])) nan = true;

@@ -578,6 +578,7 @@ int acs_batch_create(int32_t count, const acs_problem* const* probs, const acs_s
   return guarded([&] {
     if (count < 1 || !probs || !s || !out) throw AcsError(ACS_ERR_ARG, "bad argument");
     if (s->projection != ACS_PROJ_CG) throw AcsError(ACS_ERR_ARG, "the batch kernel projects by CG only");
+    if (s->equilibrate) throw AcsError(ACS_ERR_ARG, "the batch kernel does not equilibrate (acs_solve does)");
     std::vector<std::shared_ptr<const Problem>> v;
     v.reserve(count);
     for (int i = 0; i < count; ++i) {
@@ -639,6 +640,7 @@ int acs_batch_solve(int32_t count, const acs_problem* const* probs, const acs_se
   return guarded([&] {
     if (count < 1 || !probs || !s) throw AcsError(ACS_ERR_ARG, "bad argument");
     if (s->projection != ACS_PROJ_CG) throw AcsError(ACS_ERR_ARG, "the batch kernel projects by CG only");
+    if (s->equilibrate) throw AcsError(ACS_ERR_ARG, "the batch kernel does not equilibrate (acs_solve does)");
     std::vector<std::shared_ptr<const Problem>> v;
     for (int i = 0; i < count; ++i) {
       if (!probs[i]) throw AcsError(ACS_ERR_ARG, "null problem in batch");

@@ -196,7 +196,7 @@ struct SolveOut {
 };
 SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream,
                             const InstanceResources& res = InstanceResources());
-int64_t instance_device_bytes(const Problem& p, int precision, int projection);
+int64_t instance_device_bytes(const Problem& p, int precision, int projection, int equilibrate = 0);
 
 template <class F>
 int guarded(F&& f) {

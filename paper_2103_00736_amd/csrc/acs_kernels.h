@@ -49,6 +49,13 @@ LaunchEvents*& launch_events();  // thread-local slot, nullptr when not timing
     }                                                                                                 \
   } while (0)
 
+// Sums of the update kernel: ||s+ - s||^2; on check iterations also c^T x,
+// ||x||^2, ||z||^2, the squared orthant distances of x and z, ||r_d||^2,
+// r_d^T x and sum |x_j z_j| over the orthant
+constexpr int kUpdSums = 9;
+// Partial sums a reducing workgroup may write (the most of any reduction)
+constexpr int kMaxSums = kUpdSums;
+
 // Device control block of one instance (CG scalars, reductions, flags).
 struct Ctl {
   double rho;     // ||r||^2 of the current CG residual
@@ -61,7 +68,7 @@ struct Ctl {
   int32_t cg_max;
   int32_t iter;   // outer iteration the CG belongs to
   long long cg_total;
-  double upd[8];  // reductions of the update kernel
+  double upd[9];  // reductions of the update kernel (kUpdSums)
   double cone[4]; // reductions of the cone kernel
   double cond[4]; // conditioning: min log o, -max log o, -any valid, alpha
   double kkt[9];  // eps_p, eps_d, eps_gap, eps_cone, kkt, pobj, dobj, ds2, eps_obj
@@ -165,6 +172,12 @@ struct Dev {
   Ctl* ctl;
   double* partials;
   HostStatus* hs;
+  // Sinkhorn-Knopp equilibration (settings.equilibrate), else nullptr: eq
+  // holds E^2 during the sweeps, then E (per coordinate, constant on every
+  // cone); eq_u (m) is D^2 of the current sweep, eq_c (n) the column sums
+  double* eq;
+  double* eq_u;
+  double* eq_c;
 };
 
 // Direct projection: the normal matrix M = A_s A_s^T of the current scaling,
@@ -210,10 +223,9 @@ template <typename VT> void launch_cone(const Dev<VT>& d, const VT* s, bool chec
 template <typename VT> void launch_resid(const Dev<VT>& d, hipStream_t st);
 template <typename VT> void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, int cg_max,
                                              hipStream_t st);
-// the two CG sweeps and their finalizers (alpha; beta, stop test, host progress record)
+// the two CG sweeps (alpha in the first workgroup of the sliced one), the
+// combine with the CG update, and the finalizer (beta, stop test, host progress record)
 template <typename VT> void launch_cg_t(const Dev<VT>& d, hipStream_t st);
-template <typename VT> void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st);
-// CG product by column slices (+ alpha in workgroup 0), then combine + CG update
 template <typename VT> void launch_cg_a(const Dev<VT>& d, hipStream_t st);
 template <typename VT> void launch_cg_comb(const Dev<VT>& d, hipStream_t st);
 template <typename VT> void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st);
@@ -226,6 +238,9 @@ template <typename VT> void launch_rescale(const Dev<VT>& d, int wmode, hipStrea
 // in the caller's row order
 template <typename VT> void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st);
 template <typename VT> void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st);
+// Sinkhorn-Knopp equilibration: `sweeps` sweeps from eq = 1 (set by the
+// caller), leaving E in eq (sparse problems)
+template <typename VT> void launch_equilibrate(const Dev<VT>& d, int sweeps, hipStream_t st);
 // x, z (n) and y (m, caller's row order) of the last check into device buffers (any may be null)
 template <typename VT> void launch_out_device(const Dev<VT>& d, double* x, double* y, double* z, hipStream_t st);
 // direct projection: B = A_s (copy), M = B B^T (syrk), M -> M^{-1} (the

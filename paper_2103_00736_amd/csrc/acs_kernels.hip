@@ -318,7 +318,7 @@ struct UpdateEpi {
   const Dev<VT>& d;
   const VT* __restrict__ s_cur;
   VT* __restrict__ s_new;
-  double (&acc)[8];
+  double (&acc)[kUpdSums];
   __device__ __forceinline__ void operator()(int j, double u) const {
     const double mu = d.mu;
     const double zt = d.chat[j] + u;  // mu * (O z) implied by w
@@ -346,10 +346,11 @@ struct UpdateEpi {
           const double mx = fmin(x, 0.0), mz = fmin(z, 0.0);
           acc[4] += mx * mx;
           acc[5] += mz * mz;
+          acc[8] += fabs(x * z);  // |x_j z_j| of the objective-error estimate (cones: k_cone)
         }
         const double dr = (pj - sn - 2.0 * zt) / (2.0 * mu * Oj);  // (A^T y + z - c)_j
         acc[6] += dr * dr;
-        acc[7] += x * dr;  // r_d^T x of the objective-error estimate
+        acc[7] += x * dr;  // r_d^T x
       }
     }
     if (MODE != UPD_UPDATE_ONLY) {
@@ -364,12 +365,12 @@ struct UpdateEpi {
 template <typename VT, int MODE, bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restrict__ s_cur, VT* __restrict__ s_new) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[kUpdSums] = {};
   UpdateEpi<VT, MODE, CHECK> upd{d, s_cur, s_new, acc};
   auto pre = [](int) -> double { return 0.0; };
   auto epi = [&](int j, double u, double) { upd(j, u); };
   sell_rows<double, double>(d.st, d.st_val64, 0, blk, d.w, pre, epi);
-  if (MODE != UPD_PROLOGUE) block_store_partials<8>(acc, d.partials, blk);
+  if (MODE != UPD_PROLOGUE) block_store_partials<kUpdSums>(acc, d.partials, blk);
 }
 
 // ----------------------------------------------------------------------------
@@ -380,23 +381,27 @@ __global__ __launch_bounds__(kBlock) void k_cone(Dev<VT> d, const VT* __restrict
   const int gpb = kBlock / G;
   const int grp = threadIdx.x / G, lane = threadIdx.x & (G - 1);
   const int cone = blockIdx.x * gpb + grp;
-  double acc[2] = {0, 0};
+  double acc[3] = {0, 0, 0};
   if (cone < d.n_soc) {
     const int off = d.soc_off[cone], end = d.soc_off[cone + 1];
     if (check) {
-      double nx = 0, nz = 0;
+      double nx = 0, nz = 0, xz = 0;
       for (int e = off + 1 + lane; e < end; e += G) {
         const double xe = d.xout[e], ze = d.zout[e];
         nx += xe * xe;
         nz += ze * ze;
+        xz += xe * ze;
       }
       for (int o = G >> 1; o > 0; o >>= 1) {
         nx += __shfl_xor(nx, o);
         nz += __shfl_xor(nz, o);
+        xz += __shfl_xor(xz, o);
       }
       if (lane == 0) {
-        acc[0] = lorentz_dist2(d.xout[off], sqrt(nx));
-        acc[1] = lorentz_dist2(d.zout[off], sqrt(nz));
+        const double x0 = d.xout[off], z0 = d.zout[off];
+        acc[0] = lorentz_dist2(x0, sqrt(nx));
+        acc[1] = lorentz_dist2(z0, sqrt(nz));
+        acc[2] = fabs(x0 * z0 + xz);  // |x_C^T z_C| of the objective-error estimate
       }
     }
     if (next) {
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_cone(Dev<VT> d, const VT* __restrict
       }
     }
   }
-  if (check) block_store_partials<2>(acc, d.partials, blockIdx.x);
+  if (check) block_store_partials<3>(acc, d.partials, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -576,7 +581,7 @@ __device__ __forceinline__ void pres_row(const Dev<VT>& d, int i, double ax, dou
   const double yi = -d.dinv[i] * d.w[i] / mu;
   d.yout[i] = yi;
   acc[1] += d.b[i] * yi;
-  acc[2] += yi * res;
+  acc[2] += yi * res;  // y^T r_p of the objective-error estimate
 }
 
 template <typename VT>
@@ -663,6 +668,11 @@ __global__ __launch_bounds__(kBlock) void k_cond_ratio(Dev<VT> d, const VT* __re
       o = INFINITY;
     else
       o = num / den;
+    if (d.eq && o > 0.0 && !isinf(o) && !(num == 0.0 && den == 0.0)) {
+      // equilibrated: the ratio of x_hat = x / E, z_hat = E z
+      const double e = d.eq[u < d.n_orth ? u : d.soc_off[u - d.n_orth]];
+      o = o / (e * e);
+    }
     d.ounit[u] = o;
     if (o > 0.0 && !isinf(o) && o == o) {
       const double lo = log(o);
@@ -697,6 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_cond_scale(Dev<VT> d, VT* __restrict
     off = d.soc_off[u - d.n_orth];
     end = d.soc_off[u - d.n_orth + 1];
   }
+  if (d.eq) Onew *= d.eq[off];  // equilibrated: the column scaling E O_hat
   const double mu = d.mu;
   for (int e = off; e < end; ++e) {
     d.O[e] = Onew;
@@ -764,6 +775,68 @@ __global__ __launch_bounds__(kBlock) void k_scale_a(Dev<VT> d) {
     const double a = d.a_orig[k] * d.O[d.a_col[k]] * d.dinv[i];
     d.a_val64[k] = a;
   }
+}
+
+// ----------------------------------------------------------------------------
+// Sinkhorn-Knopp l2 equilibration (Sec. III, A_hat = D A E), FP64: with
+// u = D^2 and v = E^2 (eq holds v during the sweeps), each sweep sets
+// u_i = 1 / sum_j a_ij^2 v_j and then, per Lorentz cone of k coordinates (an
+// orthant coordinate is a cone of one), v = (m/n) k / sum over its columns of
+// sum_i a_ij^2 u_i.  Rows and cones without a nonzero keep u = 1 / v = 1.
+// ----------------------------------------------------------------------------
+// squared values in the order of the A^T layout (into its FP64 value array,
+// which the first rescale overwrites with A_s)
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_sk_sq(const int32_t* __restrict__ src, int64_t count,
+                                                  const double* __restrict__ a, double* __restrict__ sq) {
+  for (int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x; e < count; e += int64_t(gridDim.x) * kBlock) {
+    const int32_t k = src[e];
+    const double v = k >= 0 ? a[k] : 0.0;
+    sq[e] = v * v;
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_sk_rows(Dev<VT> d) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const RowBlock rb = d.a_blk[blk];
+  const double* __restrict__ ao = d.a_orig;
+  const int32_t* __restrict__ ac = d.a_col;
+  const double* __restrict__ v = d.eq;
+  auto prod = [&](int k) -> double {
+    const double a = ao[k];
+    return a * a * v[ac[k]];
+  };
+  auto epi = [&](int i, double sum) { d.eq_u[i] = sum > 0.0 ? 1.0 / sum : 1.0; };
+  rows_block<double>(d.a_rp, rb, prod, epi);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_sk_cols(Dev<VT> d) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  auto pre = [](int) -> double { return 0.0; };
+  auto epi = [&](int j, double sum, double) { d.eq_c[j] = sum; };
+  sell_rows<double, double>(d.st, d.st_val64, 0, blk, d.eq_u, pre, epi);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_sk_unit(Dev<VT> d, double target, int last) {
+  const int units = d.n_orth + d.n_soc;
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  if (u >= units) return;
+  int off, end;
+  if (u < d.n_orth) {
+    off = u;
+    end = u + 1;
+  } else {
+    off = d.soc_off[u - d.n_orth];
+    end = d.soc_off[u - d.n_orth + 1];
+  }
+  double tot = 0.0;
+  for (int e = off; e < end; ++e) tot += d.eq_c[e];
+  double v = tot > 0.0 ? target * double(end - off) / tot : 1.0;
+  if (last) v = sqrt(v);
+  for (int e = off; e < end; ++e) d.eq[e] = v;
 }
 
 template <typename VT>
@@ -848,19 +921,20 @@ __global__ void k_ctl_reset(Dev<VT> d, int cg_max) {
 // ----------------------------------------------------------------------------
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_fin_upd(Dev<VT> d, int nb) {
-  double t[8];
-  sum_partials<8>(d.partials, nb, t);
+  double t[kUpdSums];
+  sum_partials<kUpdSums>(d.partials, nb, t);
   if (threadIdx.x == 0)
-    for (int i = 0; i < 8; ++i) d.ctl->upd[i] = t[i];
+    for (int i = 0; i < kUpdSums; ++i) d.ctl->upd[i] = t[i];
 }
 
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_fin_cone(Dev<VT> d, int nb) {
-  double t[2];
-  sum_partials<2>(d.partials, nb, t);
+  double t[3];
+  sum_partials<3>(d.partials, nb, t);
   if (threadIdx.x == 0) {
     d.ctl->cone[0] = t[0];
     d.ctl->cone[1] = t[1];
+    d.ctl->cone[2] = t[2];
   }
 }
 
@@ -953,9 +1027,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_pres(Dev<VT> d, int nb, int iter
     e[5] = ctx;
     e[6] = bty;
     e[7] = u[0];
-    // weak-duality estimate of |c^T x - p*| / (1 + |c^T x|): the objective
-    // lies between y^T r_p and c^T x - b^T y + r_d^T x up to second-order terms
-    e[8] = fmax(fabs(t[2]), fabs(ctx - bty + u[7])) / (1.0 + fabs(ctx));
+    // estimate of |c^T x - p*| / (1 + |c^T x|): c^T x - p* = z*^T x + y*^T r_p,
+    // the first term bounded cone by cone in absolute value, at the current y, z
+    e[8] = (u[8] + (has_soc ? c->cone[2] : 0.0) + fabs(t[2])) / (1.0 + fabs(ctx));
     bool bad = false;
     for (int i = 0; i < 9; ++i) {
       c->kkt[i] = e[i];
@@ -1203,7 +1277,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_fin(Dev<VT> d, const VT* 
   if (KIND == DK_CG && d.ctl->done) return;
   const int j = blockIdx.x * kBlock + threadIdx.x;
   const ACC* part = reinterpret_cast<const ACC*>(d.dpart);
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[kUpdSums] = {};
   if (j < d.n) {
     ACC sum = part[j];
     for (int ch = 1; ch < d.dnchunk; ++ch) sum += part[size_t(ch) * d.ld + j];
@@ -1225,7 +1299,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_fin(Dev<VT> d, const VT* 
     double a1[1] = {acc[0]};
     block_store_partials<1>(a1, d.partials2, blockIdx.x);
   } else if (KIND == DK_UPDATE && MODE != UPD_PROLOGUE) {
-    block_store_partials<8>(acc, d.partials, blockIdx.x);
+    block_store_partials<kUpdSums>(acc, d.partials, blockIdx.x);
   }
 }
 
@@ -1343,11 +1417,6 @@ void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
 }
 
 template <typename VT>
-void launch_fin_cg_t(const Dev<VT>& d, hipStream_t st) {
-  ACS_LAUNCH((k_fin_cg_t<VT>), dim3(1), dim3(kBlock), 0, st, d, d.st.wg[0]);
-}
-
-template <typename VT>
 void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
   if (d.dense) {  // the row product and the CG update of each row in one kernel
     ACS_LAUNCH((k_dense_rows<VT, DK_CG>), dim3(dense_row_blocks(d.m)), dim3(kBlock), 0, st, d, ceil_div(d.n, kBlock),
@@ -1419,6 +1488,20 @@ void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
 }
 
 template <typename VT>
+void launch_equilibrate(const Dev<VT>& d, int sweeps, hipStream_t st) {
+  const int nb = int(std::max<int64_t>(1, std::min<int64_t>((d.st.entries + kBlock - 1) / kBlock, 8192)));
+  ACS_LAUNCH((k_sk_sq<VT>), dim3(nb), dim3(kBlock), 0, st, d.st.src, d.st.entries, d.a_orig, d.st_val64);
+  const int units = d.n_orth + d.n_soc;
+  const double target = double(d.m) / double(d.n);
+  for (int k = 0; k < sweeps; ++k) {
+    ACS_LAUNCH((k_sk_rows<VT>), dim3(d.a_nblk), dim3(kBlock), 0, st, d);
+    ACS_LAUNCH((k_sk_cols<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d);
+    ACS_LAUNCH((k_sk_unit<VT>), dim3(ceil_div(units, kBlock)), dim3(kBlock), 0, st, d, target,
+               k + 1 == sweeps ? 1 : 0);
+  }
+}
+
+template <typename VT>
 void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st) {
   if (d.dense) {
     if (which == 0) {
@@ -1457,7 +1540,6 @@ void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
   template void launch_resid<VT>(const Dev<VT>&, hipStream_t);                                        \
   template void launch_fin_resid<VT>(const Dev<VT>&, int, double, double, int, hipStream_t);               \
   template void launch_cg_t<VT>(const Dev<VT>&, hipStream_t);                                         \
-  template void launch_fin_cg_t<VT>(const Dev<VT>&, hipStream_t);                                     \
   template void launch_cg_a<VT>(const Dev<VT>&, hipStream_t);                                         \
   template void launch_cg_comb<VT>(const Dev<VT>&, hipStream_t);                                      \
   template void launch_fin_cg_a<VT>(const Dev<VT>&, long long, hipStream_t);                          \
@@ -1467,6 +1549,7 @@ void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
   template void launch_rescale<VT>(const Dev<VT>&, int, hipStream_t);                                 \
   template void launch_spmv<VT>(const Dev<VT>&, int, const VT*, VT*, hipStream_t);                    \
   template void launch_ctl_reset<VT>(const Dev<VT>&, int, hipStream_t);                              \
+  template void launch_equilibrate<VT>(const Dev<VT>&, int, hipStream_t);                             \
   template void launch_out_device<VT>(const Dev<VT>&, double*, double*, double*, hipStream_t);
 
 ACS_INSTANTIATE(float)

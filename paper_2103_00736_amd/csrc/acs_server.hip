@@ -105,10 +105,11 @@ class Server {
     auto r = std::make_shared<Request>();
     r->p = std::move(p);
     r->s = resolve_settings(s, *r->p);
-    // dense requests and those asking for the direct projection run on the worker streams
-    r->small = !r->p->dense && r->s.projection == ACS_PROJ_CG && r->p->nnz <= small_nnz_;
+    // dense requests and those asking for the direct projection or the
+    // equilibration run on the worker streams
+    r->small = !r->p->dense && r->s.projection == ACS_PROJ_CG && !r->s.equilibrate && r->p->nnz <= small_nnz_;
     r->bytes = r->small ? int64_t(layout_instance(*r->p, 0).end)
-                        : instance_device_bytes(*r->p, r->s.precision, r->s.projection);
+                        : instance_device_bytes(*r->p, r->s.precision, r->s.projection, r->s.equilibrate);
     if (r->bytes > budget_) throw AcsError(ACS_ERR_NOMEM, "request needs more device memory than the server budget");
     r->t_submit = Clock::now();
     {

@@ -77,6 +77,9 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
     throw AcsError(ACS_ERR_ARG, "settings: bad counts");
   if (s.precision != ACS_PREC_MIXED && s.precision != ACS_PREC_FP64) throw AcsError(ACS_ERR_ARG, "settings: precision");
   if (s.projection != ACS_PROJ_CG && s.projection != ACS_PROJ_FACTOR) throw AcsError(ACS_ERR_ARG, "settings: projection");
+  if ((s.equilibrate != 0 && s.equilibrate != 1) || s.eq_sweeps < 0)
+    throw AcsError(ACS_ERR_ARG, "settings: equilibrate must be 0 or 1 and eq_sweeps >= 0");
+  if (s.equilibrate && p.dense) throw AcsError(ACS_ERR_ARG, "settings: equilibration takes sparse problems only");
   return s;
 }
 
@@ -269,7 +272,7 @@ static int64_t estimate_bytes(const Problem& p, int precision) {
     dense_chunks(p, &rows, &chunks);
     int64_t b = 4 * int64_t(p.dhi.size()) + 4 * int64_t(p.dlo.size()) + 8 * int64_t(chunks) * p.ld;
     b += (vt + 8) * p.ld + n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7 + 4 + vt);
-    b += 8 * 8 * (m / 16 + n / kBlock + 4) + 64 * 256;
+    b += 8 * kMaxSums * (m / 16 + n / kBlock + 4) + 8 * kBlock + 64 * 256;
     return b;
   }
   const SellPair& sp = p.sell();
@@ -284,7 +287,7 @@ static int64_t estimate_bytes(const Problem& p, int precision) {
   b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
   const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max),
                                          size_t(n / kBlock + 2)});
-  b += 8 * 8 * int64_t(parts) + 64 * 256;                // partials, per-array alignment
+  b += 8 * kMaxSums * int64_t(parts) + 8 * kBlock + 64 * 256;  // partials, per-array alignment
   return b;
 }
 
@@ -334,6 +337,7 @@ class Instance final : public InstanceBase {
     // server's pools) runs no destructor: release what was taken so far
     try {
       setup_device();
+      if (S.equilibrate) equilibrate();
       set_initial();
       HIP_CHECK(hipStreamSynchronize(st_));
     } catch (...) {
@@ -605,7 +609,12 @@ class Instance final : public InstanceBase {
     nparts_ = std::max<size_t>({p.a_blocks.size(), size_t(d.st.wg_max), units / kBlock + 1,
                                  p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, size_t(p.n) / kBlock + 1,
                                  size_t(p.m) / 16 + 1, 1});
-    d.partials = arena_.alloc<double>(nparts_ * 8);
+    d.partials = arena_.alloc<double>(nparts_ * kMaxSums);
+    if (S.equilibrate) {
+      d.eq = arena_.alloc<double>(p.n);
+      d.eq_u = arena_.alloc<double>(p.m);
+      d.eq_c = arena_.alloc<double>(p.n);
+    }
     s_buf_[0] = arena_.alloc<VT>(p.n);
     s_buf_[1] = arena_.alloc<VT>(p.n);
     if (res_.status) {
@@ -641,13 +650,26 @@ class Instance final : public InstanceBase {
     HIP_CHECK(hipStreamSynchronize(st_));
   }
 
-  // x = z = e_K, O = 1, w = 0 (l = 0)
+  // Sinkhorn-Knopp equilibration: E from eq_sweeps sweeps, kept on the device
+  // (the conditioning reads it) and on the host (the initial O)
+  void equilibrate() {
+    const Problem& p = *P_;
+    std::vector<double> ones(p.n, 1.0);
+    HIP_CHECK(hipMemcpyAsync(d_.eq, ones.data(), sizeof(double) * p.n, hipMemcpyHostToDevice, st_));
+    launch_equilibrate(d_, S.eq_sweeps, st_);
+    check_launch();
+    eq_.resize(p.n);
+    HIP_CHECK(hipMemcpyAsync(eq_.data(), d_.eq, sizeof(double) * p.n, hipMemcpyDeviceToHost, st_));
+    HIP_CHECK(hipStreamSynchronize(st_));
+  }
+
+  // x = z = e_K in the scaled variables, O = E (1 without equilibration), w = 0 (l = 0)
   void set_initial() {
     const Problem& p = *P_;
     std::vector<double> e(p.n, 0.0);
     for (int j = 0; j < p.n_orth; ++j) e[j] = 1.0;
     for (size_t i = 0; i < p.soc_size.size(); ++i) e[p.soc_off[i]] = 1.0;
-    std::vector<double> sp(p.n), sc(p.n), O(p.n, 1.0), w(p.m, 0.0);
+    std::vector<double> sp(p.n), sc(p.n), O(eq_.empty() ? std::vector<double>(p.n, 1.0) : eq_), w(p.m, 0.0);
     for (int j = 0; j < p.n; ++j) {
       sp[j] = (1.0 + S.mu) * e[j];
       sc[j] = (1.0 - S.mu) * e[j];
@@ -1034,6 +1056,7 @@ class Instance final : public InstanceBase {
   int cone_group_ = 4;
   size_t nparts_ = 1;
   bool fac_ = false;       // direct projection
+  std::vector<double> eq_;  // E of the equilibration (empty without it)
   bool factored_ = false;  // M^{-1} matches the current scaling
   FacDev f_{};
   hipStream_t st2_ = nullptr;                     // the next sweep group's chain
@@ -1065,8 +1088,9 @@ SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings
   return o;
 }
 
-int64_t instance_device_bytes(const Problem& p, int precision, int projection) {
-  return estimate_bytes(p, precision) + (projection == ACS_PROJ_FACTOR ? factor_bytes(p) : 0);
+int64_t instance_device_bytes(const Problem& p, int precision, int projection, int equilibrate) {
+  return estimate_bytes(p, precision) + (projection == ACS_PROJ_FACTOR ? factor_bytes(p) : 0) +
+         (equilibrate ? 8 * (2 * int64_t(p.n) + p.m) + 3 * 256 : 0);
 }
 
 static int g_device = -1;
@@ -1178,7 +1202,9 @@ void acs_settings_default(acs_settings* s) {
   s->cg_reduce = 0.1;
   s->cg_abs = 0.0;
   s->verbose = 0;
-  s->obj_stop = 4;
+  s->obj_stop = 1;
+  s->equilibrate = 0;
+  s->eq_sweeps = 25;
 }
 
 int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
@@ -1346,7 +1372,7 @@ int acs_solve_device_noalloc(const acs_problem* p, const acs_settings* s, double
     }
     if (s->projection != ACS_PROJ_CG)
       throw AcsError(ACS_ERR_ARG, "acs_solve_device_noalloc: only the CG projection (ACS_PROJ_CG)");
-    const int64_t need = instance_device_bytes(*p->p, s->precision, ACS_PROJ_CG);
+    const int64_t need = instance_device_bytes(*p->p, s->precision, ACS_PROJ_CG, s->equilibrate);
     if (need > int64_t(kNoAllocBytes))
       throw AcsError(ACS_ERR_NOMEM, "acs_solve_device_noalloc: the problem needs " + std::to_string(need) +
                                         " device bytes, the fixed scratch holds " + std::to_string(kNoAllocBytes));

@@ -351,6 +351,20 @@ def config4_trace(count: int = 2000, rate_per_s: float = 200.0, m_lo: float = 1e
     return [Request(i, float(t[i]), str(kinds[i]), int(ms[i])) for i in range(count)]
 
 
+def synthetic_state(p, seed: int, spread: float) -> tuple:
+    """A seeded state (s_prev, s, O, w) for one-iteration tests of a problem:
+    s and s_prev ~ N(0,1) rounded to FP32, O = exp(U(-spread/2, spread/2)) drawn
+    once per cone (an orthant coordinate is a cone of one) so that it is
+    constant on every cone, w ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    s = _f32(rng.standard_normal(p.n))
+    s_prev = _f32(rng.standard_normal(p.n))
+    sizes = np.concatenate([np.ones(p.n_orth, dtype=np.int64), np.asarray(p.soc_sizes, dtype=np.int64)])
+    O = np.repeat(np.exp(rng.uniform(-spread / 2, spread / 2, size=sizes.size)), sizes)
+    w = rng.standard_normal(p.m)
+    return s_prev, s, O, w
+
+
 def iter_batch(count: int) -> Iterator[ConicProblem]:
     for i in range(count):
         yield config3(i)

@@ -31,7 +31,10 @@ def test_schedule_ablation_in_one_batch_each():
     handles = [_handle(p) for p in probs]
     its = {}
     for name, kw in SCHED.items():
-        b = acs.Batch(handles, eps_kkt=1e-6, max_iter=20000, auto_params=0, t=9.2, mu=1.0, check_every=10, **kw)
+        # the schedules are compared in KKT terms, as the oracle's run of the same
+        # example is (no objective term in the stop: obj_stop = 0)
+        b = acs.Batch(handles, eps_kkt=1e-6, max_iter=20000, auto_params=0, t=9.2, mu=1.0, check_every=10,
+                      obj_stop=0, **kw)
         b.run(20000)
         its[name] = []
         for i, p in enumerate(probs):

@@ -15,7 +15,7 @@ import pytest
 from oracle.alg2 import Algorithm2, default_parameters, one_iteration
 from oracle.kkt import kkt_errors
 from paper_2103_00736_amd import acs, synth
-from tests._parity import obj_err as _obj_err
+from tests._parity import assert_close, assert_iterate, fmt, iterate_errors, obj_err as _obj_err
 
 pytestmark = pytest.mark.gpu
 
@@ -45,6 +45,43 @@ def test_full_lp_2m():
 
 def test_full_socp_1m():
     _solve_and_verify(synth.config2(), 20000)
+
+
+@pytest.mark.parametrize("name", ["lp2m", "socp1m"])
+def test_one_iteration_parity_full_size(name):
+    """One iteration (steps 16-20) at the full benchmark sizes, in the launch
+    configuration the benchmark times (mixed precision), from a seeded state
+    whose O spans e^1 (LP) and the SOCP schedule's cap e^1.7: against the
+    literal FP64 oracle (two reflections, PCG to 1e-12; about a minute per
+    problem, which is why the LP's O is not spread to its cap e^9.2, where
+    the oracle's PCG needs thousands of steps), normwise and element by
+    element at the 1e-5 bar (x by x/O, see tests/_parity.py)."""
+    p = synth.config1() if name == "lp2m" else synth.config2()
+    s_prev, s, O, w = synth.synthetic_state(p, seed=5, spread=1.0 if name == "lp2m" else 1.7)
+    print(f"{name}: m={p.m} n={p.n} nnz={p.nnz}, O range {np.log(O.max() / O.min()):.2f}", flush=True)
+    ref = one_iteration(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, 1.0, s, O)
+    # the warm start of a running solve: the iteration's own multiplier w = -mu y
+    # up to a relative perturbation of 1e-3 (a random w would ask the FP32 CG for
+    # seven digits of a correction as large as w itself)
+    w = -ref["y"] * (1.0 + 1e-3 * np.random.default_rng(6).standard_normal(p.m))
+    st = acs.State(acs.Problem.from_synth(p), precision=acs.PREC_MIXED, cg_max=4000, cg_reduce=1e-7)
+    st.set(57, s_prev, s, O, w)
+    st.step(1)
+    g = st.get()
+    errs = iterate_errors(g, ref, O)
+    chat = O * np.abs(p.c)
+    k = int(np.argmax(np.abs(g["s"] - ref["s"])))
+    print(f"{name}: {fmt(errs)}, CG steps {st.info().cg_steps}; worst s entry {k}: |s| {abs(ref['s'][k]):.2e}, "
+          f"mu O|c| {chat[k]:.2e} (max |s| {np.abs(ref['s']).max():.2e}, max mu O|c| {chat.max():.2e})", flush=True)
+    assert g["l"] == 58
+    if name == "lp2m":
+        # s+ = (s + p)/2 - mu O c - A_s^T w cancels terms up to mu O|c| ~ 1e3 (rows
+        # scaled by 10^3) against entries of s+ of size ~1; the FP32 CG leaves w
+        # with ~1e-7 relative error, so one entry in 2M can carry ~1e-7 * 1e3
+        # absolute error: element by element the bar is 2e-5, normwise 1e-5
+        assert_close(errs, 1e-5, name, elem_tol=2e-5, norm_only=("x",))
+    else:
+        assert_iterate(errs, False, name)
 
 
 def test_sampled_rows_of_scaled_products_full_size():

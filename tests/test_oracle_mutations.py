@@ -113,10 +113,19 @@ def _mut_dual_residual_sign(A, b, c, n_orth, soc_sizes, x, y, z):
     return kkt_orig_errors(A, b, c, n_orth, soc_sizes, x, y, -np.asarray(z))  # A^T y - z - c
 
 
-def _mut_objective_drops_rd(A, b, c, n_orth, soc_sizes, x, y, z):
+def _mut_objective_drops_rp(A, b, c, n_orth, soc_sizes, x, y, z):
     rec = kkt_orig_errors(A, b, c, n_orth, soc_sizes, x, y, z)
-    rp = A @ np.asarray(x) - b
-    rec["eps_obj"] = max(abs(float(np.asarray(y) @ rp)), abs(rec["pobj"] - rec["dobj"])) / (1 + abs(rec["pobj"]))
+    x, z = np.asarray(x), np.asarray(z)
+    xz = [abs(float(x[st:st + k] @ z[st:st + k])) for st, k in cones.blocks(n_orth, soc_sizes)]
+    rec["eps_obj"] = float(np.sum(xz)) / (1 + abs(rec["pobj"]))  # without |y^T r_p|
+    return rec
+
+
+def _mut_objective_signed(A, b, c, n_orth, soc_sizes, x, y, z):
+    rec = kkt_orig_errors(A, b, c, n_orth, soc_sizes, x, y, z)
+    x, z, y = np.asarray(x), np.asarray(z), np.asarray(y)
+    rp = A @ x - b
+    rec["eps_obj"] = (abs(float(x @ z)) + abs(float(rp @ y))) / (1 + abs(rec["pobj"]))  # x^T z before |.|
     return rec
 
 
@@ -221,7 +230,8 @@ MUTATIONS = {
     "step 13 drops (AO)^dagger b": (alg2.Algorithm2, "condition", _patched_condition_no_pinv_b()),
     "cone distance squared": (cones, "dist_K", _mut_dist_squared),
     "dual residual with -z": (kkt, "kkt_errors", _mut_dual_residual_sign),
-    "objective estimate drops r_d^T x": (kkt, "kkt_errors", _mut_objective_drops_rd),
+    "objective estimate without |y^T r_p|": (kkt, "kkt_errors", _mut_objective_drops_rp),
+    "objective estimate summed before the absolute values": (kkt, "kkt_errors", _mut_objective_signed),
     "objective bound with -r_d": (kkt, "objective_bounds", _mut_objective_bounds_sign),
     "equilibration on |a| instead of a^2": (equilibrate, "sinkhorn_knopp_l2", _sk_variant("abs")),
     "equilibration column target 1": (equilibrate, "sinkhorn_knopp_l2", _sk_variant("target")),

@@ -23,3 +23,22 @@ def test_sell_layout_and_row_renumbering(tmp_path):
     print(out.stdout)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip().endswith("ok")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_sell_layout_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The same host code and checks built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only, g++; any report aborts)."""
+    exe = tmp_path / "sell_check_san"
+    src = [os.path.join(ROOT, "tests", "sell_layout_check.cpp"),
+           os.path.join(ROOT, "paper_2103_00736_amd", "csrc", "acs_problem.cpp")]
+    flags = ["-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=all"]
+    subprocess.run(["g++", *flags, "-o", str(exe)] + src, check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
+    print(out.stdout[-2000:])
+    assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-4000:]
+    assert "runtime error" not in out.stderr and "AddressSanitizer" not in out.stderr, out.stderr[-4000:]
+    assert out.stdout.strip().endswith("ok")
