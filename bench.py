@@ -810,7 +810,7 @@ def batch_section(acs, synth, count):
             "roofline": {"bound": "hbm", "kernel": "k_batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "traffic": traffic_record("batch", "batch4096", "acs_batch.hip"),
-                         "avg_launch_ms": ms, "launches": 1},
+                         "avg_launch_ms": ms, "launches": 1, "algorithmic_bytes_per_launch": byts},
             "gen_s": gen_s, "autotune_s": tune_s}
 
 

@@ -48,7 +48,9 @@ __device__ __forceinline__ double bmin(double v, double* sh) {
   return s;
 }
 
-// Row sums of prod(k) with G lanes per row; epi(row, sum) on one lane.
+// Row sums of prod(k) with G lanes per row; epi(row, sum) on one lane.  A
+// lane takes its entries four at a time, all four products' loads issued
+// before the first add (the adds keep the order of k, so sums do not change).
 template <typename Acc, class Prod, class Epi>
 __device__ __forceinline__ void bspmv(const int32_t* __restrict__ rp, int nrows, int G, Prod& prod, Epi& epi) {
   const int tid = threadIdx.x, ngrp = kBB / G, grp = tid / G, lane = tid & (G - 1);
@@ -57,7 +59,15 @@ __device__ __forceinline__ void bspmv(const int32_t* __restrict__ rp, int nrows,
     Acc s = 0;
     if (r < nrows) {
       const int e = rp[r + 1];
-      for (int k = rp[r] + lane; k < e; k += G) s += prod(k);
+      int k = rp[r] + lane;
+      for (; k + 3 * G < e; k += 4 * G) {
+        const Acc p0 = prod(k), p1 = prod(k + G), p2 = prod(k + 2 * G), p3 = prod(k + 3 * G);
+        s += p0;
+        s += p1;
+        s += p2;
+        s += p3;
+      }
+      for (; k < e; k += G) s += prod(k);
     }
     for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane == 0 && r < nrows) epi(r, s);
