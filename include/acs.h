@@ -79,13 +79,16 @@ extern "C" {
  * l_every = 0 means L = {l_first}.  Iteration 1 always conditions.
  * With `auto_params` = 1 the library picks the paper's per-class values:
  * LP: t = 9.2, L = {300, 400, ...}; SOCP: t = 1.7, L = {200, 300, ...}; mu = 1.
- * Projection (Alg. 2 step 17) by warm-started CG, defaults cg_reduce = 0.1,
- * cg_max = 500; obj_stop = 1.  The iteration just before a conditioning
- * event (its x, z set O) runs its CG to a 1e-6 reduction with up to 8 cg_max
- * steps.  A cap that
- * stops the CG short of cg_reduce leaves an error the outer iteration may not
- * recover from once O is spread; smaller cg_reduce trades CG steps for outer
- * iterations (0.03 solves the 2M-variable LP fastest).
+ * Projection (Alg. 2 step 17) by warm-started CG, defaults cg_reduce = 0
+ * (per class: 0.1 for LPs, 0.2 for SOCPs; a negative value is ACS_ERR_ARG),
+ * cg_max = 500; obj_stop = 1.  The iteration just before a conditioning event
+ * (its x, z set O) runs its CG to a 1e-6 reduction with up to 8 cg_max steps.
+ * A cap that stops the CG short of cg_reduce leaves an error the outer
+ * iteration may not recover from once O is spread; smaller cg_reduce trades
+ * CG steps for outer iterations.  Measured whole solves: the row-scaled
+ * 2M-variable LP runs fastest at 0.03 and takes 3x longer at 0.2, while the
+ * 1M-variable SOCP, the small LPs of the batch recipe and the serving trace's
+ * requests run fastest at 0.2-0.3.
  */
 /*
  * Equilibration (settings.equilibrate = 1; sparse problems, one-instance
@@ -115,7 +118,7 @@ typedef struct acs_settings {
   double eps_kkt;       /* stop when max(eps_p, eps_d, eps_gap, eps_cone) <= it */
   int32_t precision;    /* ACS_PREC_MIXED or ACS_PREC_FP64                      */
   int32_t cg_max;       /* CG steps per outer iteration, at most                */
-  double cg_reduce;     /* stop CG once ||r|| <= cg_reduce * ||r_0|| (warm)     */
+  double cg_reduce;     /* stop CG once ||r|| <= cg_reduce * ||r_0|| (warm); 0 = per class */
   double cg_abs;        /* ... or once ||r|| <= cg_abs (scaled system)          */
   int32_t verbose;      /* 0 quiet, 1 one line per check on stderr              */
   int32_t projection;   /* ACS_PROJ_CG (default) or ACS_PROJ_FACTOR              */

@@ -31,6 +31,9 @@ constexpr int kSlices = 8;        // column slices of A, one per XCD
 // from noise; the paper's projection is exact.
 constexpr double kEventCgReduce = 1e-6;
 constexpr int kEventCgMaxFactor = 8;
+// CG residual reduction of the other iterations when settings.cg_reduce = 0
+constexpr double kCgReduceLp = 0.1;
+constexpr double kCgReduceSocp = 0.2;
 constexpr int kSellChunk = 64;    // rows per SELL chunk (one per lane of a wave64)
 constexpr int kSellMaxLen = 64;   // longest row packed into a chunk
 constexpr int kWaveRowMax = 2048; // longest row given to one wave; longer rows get a workgroup

@@ -72,6 +72,10 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
     s.l_every = 100;
     s.l_last = -1;
   }
+  // cg_reduce = 0 picks the per-class reduction: measured whole solves of the
+  // SOCPs run fastest near 0.2, the row-scaled LPs need 0.1 or tighter
+  if (s.cg_reduce == 0.0) s.cg_reduce = p.is_socp() ? kCgReduceSocp : kCgReduceLp;
+  if (!(s.cg_reduce > 0)) throw AcsError(ACS_ERR_ARG, "settings: cg_reduce must be >= 0 (0 = per class)");
   if (!(s.mu > 0) || !(s.t > 0)) throw AcsError(ACS_ERR_ARG, "settings: mu and t must be > 0");
   if (s.max_iter < 0 || s.check_every < 1 || s.cg_max < 0 || s.obj_stop < 0)
     throw AcsError(ACS_ERR_ARG, "settings: bad counts");
@@ -816,16 +820,23 @@ class Instance final : public InstanceBase {
   }
 
   // --------------------------------------------------------- host waits
+  // Spins on the pinned progress record; the stream is queried (a runtime
+  // call, which takes the runtime's locks that concurrent solves on other
+  // threads need to launch) only every 200 us, to catch a stream that went
+  // idle without posting or failed.
   template <class Pred>
   void wait_for(Pred pred) {
-    auto t0 = std::chrono::steady_clock::now();
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    auto next_query = t0 + std::chrono::microseconds(200);
     int spins = 0;
     while (!pred()) {
-      if (++spins < 2000) {
-        std::atomic_thread_fence(std::memory_order_acquire);
-        continue;
-      }
+      std::atomic_thread_fence(std::memory_order_acquire);
+      if (++spins < 256) continue;
       spins = 0;
+      const auto now = clk::now();
+      if (now < next_query) continue;
+      next_query = now + std::chrono::microseconds(200);
       hipError_t q = hipStreamQuery(st_);
       if (q == hipSuccess) {
         // stream idle: every record has landed; re-test once
@@ -834,8 +845,7 @@ class Instance final : public InstanceBase {
         throw AcsError(ACS_ERR_DEVICE, "stream idle but progress record missing");
       }
       if (q != hipErrorNotReady) throw AcsError(ACS_ERR_DEVICE, std::string("stream error: ") + hipGetErrorString(q));
-      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
-        throw AcsError(ACS_ERR_DEVICE, "timed out waiting for the GPU");
+      if (now - t0 > std::chrono::seconds(120)) throw AcsError(ACS_ERR_DEVICE, "timed out waiting for the GPU");
       std::this_thread::yield();
     }
   }
@@ -1199,7 +1209,7 @@ void acs_settings_default(acs_settings* s) {
   s->eps_kkt = 1e-4;
   s->precision = ACS_PREC_MIXED;
   s->cg_max = 500;
-  s->cg_reduce = 0.1;
+  s->cg_reduce = 0.0;  // per class: kCgReduceLp, kCgReduceSocp
   s->cg_abs = 0.0;
   s->verbose = 0;
   s->obj_stop = 1;

@@ -36,6 +36,7 @@ def test_settings_defaults_and_layout():
     assert s.mu == 1.0 and s.t == 9.2 and s.l_first == 300 and s.l_every == 100 and s.auto_params == 1
     assert s.eps_kkt == 1e-4 and s.precision == acs.PREC_MIXED and s.projection == acs.PROJ_CG
     assert s.obj_stop == 1
+    assert s.cg_reduce == 0.0  # per class: 0.1 for LPs, 0.2 for SOCPs
     assert acs.version().startswith("acs")
 
 
