@@ -135,9 +135,10 @@ typedef struct acs_settings {
  * Those are relative to the norms of b and c, so they do not bound the
  * relative error of the objective.  For an optimal pair (y*, z*) of the dual
  * (Sec. II), with r_p = Ax-b, c^T x - p* = z*^T x + y*^T r_p exactly; the
- * estimate takes the first term's bound cone by cone in absolute value, at
- * the current y, z (an orthant coordinate is a cone of one):
- *   eps_obj = (sum_C |x_C^T z_C| + |y^T r_p|)/(1+|c^T x|).
+ * estimate takes the first term's bound at the current y, z, coordinate by
+ * coordinate in absolute value on the orthant and summed with signs over the
+ * Lorentz cones (each cone's term carries first-order errors of either sign):
+ *   eps_obj = (sum_j |x_j z_j| + |sum_C x_C^T z_C| + |y^T r_p|)/(1+|c^T x|).
  * With settings.obj_stop = k (default 1) a solve stops only when
  * kkt <= eps_kkt and k * eps_obj <= eps_kkt.                              */
 typedef struct acs_info {

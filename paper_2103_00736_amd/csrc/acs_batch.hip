@@ -191,7 +191,7 @@ __device__ void cones_next(BInst& I, const float* __restrict__ s) {
 }
 
 // A_s^T w sweep: prologue (mode 0), update (1), update without next p/v (2)
-__device__ void sweep_update(BInst& I, int mode, bool check, double (&acc)[9], Shared& sh) {
+__device__ void sweep_update(BInst& I, int mode, bool check, double (&acc)[10], Shared& sh) {
   const float* __restrict__ s = I.s_buf[I.cur];
   float* __restrict__ sn_out = I.s_buf[I.cur ^ 1];
   const double* __restrict__ tv = I.t_val64;
@@ -251,7 +251,7 @@ __device__ void sweep_update(BInst& I, int mode, bool check, double (&acc)[9], S
         }
         acc[6] += ldist2(I.x[off], sqrt(nx));
         acc[7] += ldist2(I.z[off], sqrt(nz));
-        acc[8] += fabs(xz);  // |x_C^T z_C|
+        acc[9] += xz;  // x_C^T z_C, summed with signs over the cones
       }
     }
     if (mode != 2) cones_next(I, mode == 0 ? s : sn_out);
@@ -476,7 +476,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
     const int l = I.l + 1;
     if (in_sched(I, l)) {
       condition(I, sh);
-      double dummy[9];
+      double dummy[10];
       sweep_update(I, 0, false, dummy, sh);
     }
     bool bad = false;
@@ -485,7 +485,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
     __syncthreads();
     const bool next_event = in_sched(I, l + 1);
     const bool check = (l % I.check_every == 0) || l == I.max_iter;
-    double ac[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double ac[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     sweep_update(I, next_event ? 2 : 1, check, ac, sh);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -508,8 +508,8 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
         a2[2] += yi * res;  // y^T r_p of the objective-error estimate
       };
       bsweep<double>(I, 0, prod, epi, sh);
-      double tot[9];
-      for (int i = 0; i < 9; ++i) tot[i] = bsum(ac[i], sh.red);
+      double tot[10];
+      for (int i = 0; i < 10; ++i) tot[i] = bsum(ac[i], sh.red);
       const double pres2 = bsum(a2[0], sh.red), bty = bsum(a2[1], sh.red), ytrp = bsum(a2[2], sh.red);
       const double ctx = tot[0];
       double e[7];
@@ -521,7 +521,7 @@ __device__ void solve_one(BInst* gI, int budget, Shared& sh, float* __restrict__
       e[5] = ctx;
       e[6] = bty;
       // estimate of the objective's relative error (see acs.h)
-      const double eobj = (tot[8] + fabs(ytrp)) / (1.0 + fabs(ctx));
+      const double eobj = (tot[8] + fabs(tot[9]) + fabs(ytrp)) / (1.0 + fabs(ctx));
       bool nan = bad || !(eobj == eobj) || isinf(eobj);
       for (int i = 0; i < 7; ++i)
         if (!(e[i] == e[i]) || isinf(e[i])) nan = true;

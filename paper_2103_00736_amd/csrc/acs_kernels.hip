@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_cone(Dev<VT> d, const VT* __restrict
         const double x0 = d.xout[off], z0 = d.zout[off];
         acc[0] = lorentz_dist2(x0, sqrt(nx));
         acc[1] = lorentz_dist2(z0, sqrt(nz));
-        acc[2] = fabs(x0 * z0 + xz);  // |x_C^T z_C| of the objective-error estimate
+        acc[2] = x0 * z0 + xz;  // x_C^T z_C: the estimate sums the cones with their signs
       }
     }
     if (next) {
@@ -1028,8 +1028,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_pres(Dev<VT> d, int nb, int iter
     e[6] = bty;
     e[7] = u[0];
     // estimate of |c^T x - p*| / (1 + |c^T x|): c^T x - p* = z*^T x + y*^T r_p,
-    // the first term bounded cone by cone in absolute value, at the current y, z
-    e[8] = (u[8] + (has_soc ? c->cone[2] : 0.0) + fabs(t[2])) / (1.0 + fabs(ctx));
+    // at the current y, z: |x_j z_j| per orthant coordinate, the Lorentz
+    // cones' x_C^T z_C summed with their signs, |y^T r_p|
+    e[8] = (u[8] + (has_soc ? fabs(c->cone[2]) : 0.0) + fabs(t[2])) / (1.0 + fabs(ctx));
     bool bad = false;
     for (int i = 0; i < 9; ++i) {
       c->kkt[i] = e[i];

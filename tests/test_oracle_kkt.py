@@ -55,6 +55,21 @@ def test_kkt_terms_at_a_constructed_point():
     assert math.isclose(pobj - dobj, float(z @ x - rd @ x + rp @ y), rel_tol=1e-14)
 
 
+def test_objective_estimate_sums_lorentz_cones_with_signs():
+    """Two Lorentz cones whose x_C^T z_C are +25 and -7 contribute |25 - 7|;
+    orthant coordinates with products +3 and -2 contribute 3 + 2."""
+    A = sp.csr_matrix(np.array([[1.0, 0.0, 2.0, 0.0, -1.0, 0.0, 1.0, 0.5]]))
+    x = np.array([3.0, -1.0, 0.0, 3.0, 4.0, 1.0, 2.0, 2.0])
+    z = np.array([1.0, 2.0, 6.0, 3.0, 4.0, 1.0, -2.0, -2.0])  # cone 2: 1 - 4 - 4 = -7
+    y = np.array([2.0])
+    rp = np.array([0.25])
+    b = A @ x - rp
+    c = A.T @ y + z
+    rec = kkt_errors(A, b, c, 2, [3, 3], x, y, z)
+    pobj = float(c @ x)
+    assert math.isclose(rec["eps_obj"], (3.0 + 2.0 + 18.0 + 0.5) / (1.0 + abs(pobj)), rel_tol=1e-14)
+
+
 def test_objective_bounds_hold_exactly_on_the_cone():
     """For x, z in K and a planted optimum (x0, y0, z0): y0^T r_p <= c^T x - p*
     <= c^T x - b^T y + r_d^T x0, whatever y; and the estimate eps_obj is within

@@ -41,6 +41,7 @@ PINS = [
     PK.test_cone_distance_closed_forms,
     PK.test_kkt_terms_at_a_constructed_point,
     PK.test_objective_bounds_hold_exactly_on_the_cone,
+    PK.test_objective_estimate_sums_lorentz_cones_with_signs,
     PE.test_balance_reached_at_convergence,
     PE.test_rank_one_balanced_after_one_sweep,
     PE.test_lorentz_blocks_get_one_scale_and_mean_norm,
@@ -126,6 +127,15 @@ def _mut_objective_signed(A, b, c, n_orth, soc_sizes, x, y, z):
     x, z, y = np.asarray(x), np.asarray(z), np.asarray(y)
     rp = A @ x - b
     rec["eps_obj"] = (abs(float(x @ z)) + abs(float(rp @ y))) / (1 + abs(rec["pobj"]))  # x^T z before |.|
+    return rec
+
+
+def _mut_objective_cones_absolute(A, b, c, n_orth, soc_sizes, x, y, z):
+    rec = kkt_orig_errors(A, b, c, n_orth, soc_sizes, x, y, z)
+    x, z, y = np.asarray(x), np.asarray(z), np.asarray(y)
+    rp = A @ x - b
+    xz = [abs(float(x[st:st + k] @ z[st:st + k])) for st, k in cones.blocks(n_orth, soc_sizes)]
+    rec["eps_obj"] = (float(np.sum(xz)) + abs(float(rp @ y))) / (1 + abs(rec["pobj"]))  # |.| cone by cone
     return rec
 
 
@@ -232,6 +242,7 @@ MUTATIONS = {
     "dual residual with -z": (kkt, "kkt_errors", _mut_dual_residual_sign),
     "objective estimate without |y^T r_p|": (kkt, "kkt_errors", _mut_objective_drops_rp),
     "objective estimate summed before the absolute values": (kkt, "kkt_errors", _mut_objective_signed),
+    "objective estimate with |x_C^T z_C| cone by cone": (kkt, "kkt_errors", _mut_objective_cones_absolute),
     "objective bound with -r_d": (kkt, "objective_bounds", _mut_objective_bounds_sign),
     "equilibration on |a| instead of a^2": (equilibrate, "sinkhorn_knopp_l2", _sk_variant("abs")),
     "equilibration column target 1": (equilibrate, "sinkhorn_knopp_l2", _sk_variant("target")),
