@@ -106,6 +106,17 @@ extern "C" {
  * x_hat, z_hat.  D drops out (neither range((D A E)^T) nor the affine set
  * depends on it), and results are returned in the original variables.
  */
+/*
+ * Layout of the sparse products with A_s (a_slices).  With 8 slices each of
+ * the MI355X's 8 XCDs multiplies one column slice of A_s, so the gathered
+ * vector of one slice stays in that XCD's L2, and a second launch adds the
+ * 8 partial sums of every row (and applies the CG update).  With 1 slice a
+ * workgroup sums whole rows and applies the CG update itself: one launch
+ * fewer per CG step and per outer iteration, for problems whose gathered
+ * vector fits every L2.  0 picks 1 slice for n <= 262144, else 8.  The two
+ * layouts add the products of a row in different orders, so their results
+ * agree to rounding, not bit for bit; each is deterministic.
+ */
 typedef struct acs_settings {
   double mu;            /* proximal parameter mu > 0                            */
   double t;             /* cap on log(max O) - log(min O), t > 0 (step 11)      */
@@ -125,7 +136,8 @@ typedef struct acs_settings {
   int32_t obj_stop;     /* k > 0: a check also needs k * eps_obj <= eps_kkt (default 1); 0: KKT only */
   int32_t equilibrate;  /* 1: Sinkhorn-Knopp column scaling E first (Sec. III, below); 0 (default): none */
   int32_t eq_sweeps;    /* sweeps of that equilibration (default 25)              */
-  int32_t reserved[3];
+  int32_t a_slices;     /* column slices of the sparse A_s products: 0 (default) by size, 1 or 8 (below) */
+  int32_t reserved[2];
 } acs_settings;
 
 /* Per-solve report.  KKT errors follow the oracle's definition:

@@ -58,7 +58,7 @@ class Settings(ctypes.Structure):
         ("eps_kkt", ctypes.c_double), ("precision", ctypes.c_int32), ("cg_max", ctypes.c_int32),
         ("cg_reduce", ctypes.c_double), ("cg_abs", ctypes.c_double), ("verbose", ctypes.c_int32),
         ("projection", ctypes.c_int32), ("obj_stop", ctypes.c_int32), ("equilibrate", ctypes.c_int32),
-        ("eq_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("eq_sweeps", ctypes.c_int32), ("a_slices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -23,6 +23,7 @@ struct RowBlock {
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kStageNnz = 2048;   // products staged in LDS per multi-row block
 constexpr int kSlices = 8;        // column slices of A, one per XCD
+constexpr int32_t kOneSliceMaxN = 262144;  // settings.a_slices = 0: one slice up to this n
 // The iteration whose x, z feed a conditioning event (Alg. 2 steps 5-10 read
 // the x, z of the previous iteration) projects accurately: its CG runs to a
 // relative residual reduction of kEventCgReduce, with up to kEventCgMaxFactor
@@ -69,7 +70,7 @@ struct Sell {
 };
 
 struct SellPair {
-  Sell a;  // A t, kSlices column slices of A
+  Sell a;  // A t, 1 or kSlices column slices of A
   Sell t;  // A^T r, one slice
 };
 
@@ -103,13 +104,16 @@ struct Problem {
   double bnorm = 0, cnorm = 0;
   int32_t max_soc = 0;
   bool is_socp() const { return !soc_size.empty(); }
-  // SELL layouts of the CG products, built on first use by the one-instance
-  // path (the batched kernel does not use them).
-  const SellPair& sell() const;
+  // SELL layouts of the CG products with A split into `slices` (1 or
+  // kSlices) column slices, built on first use by the one-instance path (the
+  // batched kernel does not use them).
+  const SellPair& sell(int slices) const;
+  // the column slices settings.a_slices asks for (0: by size)
+  int a_slices(int requested) const { return requested ? requested : (n <= kOneSliceMaxN ? 1 : kSlices); }
 
  private:
-  mutable std::once_flag sell_once_;
-  mutable std::unique_ptr<SellPair> sell_;
+  mutable std::once_flag sell_once_[2];
+  mutable std::unique_ptr<SellPair> sell_[2];
 };
 
 // Validates and copies a dense problem (A row-major m x n).
@@ -199,7 +203,8 @@ struct SolveOut {
 };
 SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings& s, void* stream,
                             const InstanceResources& res = InstanceResources());
-int64_t instance_device_bytes(const Problem& p, int precision, int projection, int equilibrate = 0);
+int64_t instance_device_bytes(const Problem& p, int precision, int projection, int equilibrate = 0,
+                              int a_slices = 0);
 
 template <class F>
 int guarded(F&& f) {

@@ -440,9 +440,19 @@ __global__ __launch_bounds__(kBlock) void k_cone(Dev<VT> d, const VT* __restrict
 // ----------------------------------------------------------------------------
 // CG start: r = A_s v - b_s (rows i of A_s), FP64 accumulation
 // ----------------------------------------------------------------------------
+// row i given (A_s v)_i: r in VT (and in FP64 for the direct projection), ||r||^2
+template <typename VT>
+__device__ __forceinline__ void resid_row(const Dev<VT>& d, int i, double sum, double& rr) {
+  const double r64 = sum - d.bs[i];
+  const VT ri = VT(r64);
+  d.r[i] = ri;
+  if (d.r64) d.r64[i] = r64;
+  rr += double(ri) * double(ri);
+}
+
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_resid_part(Dev<VT> d) {
-  const int x = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
+  const int x = blockIdx.x % d.sa.slices, lb = blockIdx.x / d.sa.slices;
   if (lb >= d.sa.wg[x]) return;
   double* __restrict__ part = d.part64 + size_t(x) * d.m;
   auto pre = [](int) -> double { return 0.0; };
@@ -456,15 +466,21 @@ __global__ __launch_bounds__(kBlock) void k_resid_comb(Dev<VT> d) {
   const int m = d.m;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
     double sum = d.part64[i];
-#pragma unroll
-    for (int x = 1; x < kSlices; ++x) sum += d.part64[size_t(x) * m + i];
-    const double r64 = sum - d.bs[i];
-    const VT ri = VT(r64);
-    d.r[i] = ri;
-    if (d.r64) d.r64[i] = r64;
-    acc[0] += double(ri) * double(ri);
+    for (int x = 1; x < d.sa.slices; ++x) sum += d.part64[size_t(x) * m + i];
+    resid_row(d, i, sum, acc[0]);
   }
   block_store_partials<1>(acc, d.partials, blockIdx.x);
+}
+
+// One column slice: r = A_s v - b_s from whole rows, no partials to combine
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_resid_one(Dev<VT> d) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  double acc[1] = {0};
+  auto pre = [](int) -> double { return 0.0; };
+  auto epi = [&](int i, double sum, double) { resid_row(d, i, sum, acc[0]); };
+  sell_rows<double, VT>(d.sa, d.sa_val64, 0, blk, d.v, pre, epi);
+  block_store_partials<1>(acc, d.partials, blk);
 }
 
 // ----------------------------------------------------------------------------
@@ -485,7 +501,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
     acc[0] += double(tj) * double(tj);
   };
   sell_rows<VT, VT>(d.st, d.st_val, 0, blk, d.r, pre, epi);
-  block_store_partials<1>(acc, d.partials, blk);
+  // one slice: the fused second half reads them while it writes d.partials
+  block_store_partials<1>(acc, d.sa.slices == 1 ? d.partials2 : d.partials, blk);
 }
 
 // ----------------------------------------------------------------------------
@@ -512,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
       }
     }
   }
-  const int x = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
+  const int x = blockIdx.x % d.sa.slices, lb = blockIdx.x / d.sa.slices;
   if (lb >= d.sa.wg[x]) return;
   VT* __restrict__ part = d.part + size_t(x) * d.m;
   auto pre = [](int) -> VT { return VT(0); };
@@ -543,11 +560,42 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_comb(Dev<VT> d) {
   const int m = d.m;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
     VT mq = d.part[i];
-#pragma unroll
-    for (int x = 1; x < kSlices; ++x) mq += d.part[size_t(x) * m + i];
+    for (int x = 1; x < d.sa.slices; ++x) mq += d.part[size_t(x) * m + i];
     cg_row_update(d, i, mq, alpha, beta, valpha, vbeta, acc[0]);
   }
   block_store_partials<1>(acc, d.partials, blockIdx.x);
+}
+
+// CG, second half with one column slice: whole rows of A_s t and the CG
+// update of each row in one kernel.  Every workgroup turns the first half's
+// partials into alpha in the same order (so all agree); workgroup 0 records it.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_cg_a_one(Dev<VT> d, int t_nb) {
+  __shared__ int bad_sh;
+  if (d.ctl->done) return;
+  double tt[1];
+  sum_partials<1>(d.partials2, t_nb, tt);
+  if (threadIdx.x == 0) bad_sh = !(tt[0] > 0.0) || isinf(tt[0]);
+  __syncthreads();
+  if (bad_sh) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Ctl* c = d.ctl;
+      c->alpha = 0.0;
+      c->done = 1;
+      if (!(tt[0] == tt[0])) host_post(&d.hs->numeric, 1);
+      host_post(&d.hs->cg_done_iter, c->iter);
+    }
+    return;
+  }
+  const double alpha = d.ctl->rho / tt[0], beta = d.ctl->beta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctl->alpha = alpha;
+  const VT valpha = VT(alpha), vbeta = VT(beta);
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  double acc[1] = {0};
+  auto pre = [](int) -> VT { return VT(0); };
+  auto epi = [&](int i, VT mq, VT) { cg_row_update(d, i, mq, alpha, beta, valpha, vbeta, acc[0]); };
+  sell_rows<VT, VT>(d.sa, d.sa_val, 0, blk, d.t, pre, epi);
+  block_store_partials<1>(acc, d.partials, blk);
 }
 
 // values of a SELL layout from the FP64 A_s (padding entries hold 0), in VT
@@ -858,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_t(Dev<VT> d, const VT* __restri
 
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_spmv_a(Dev<VT> d, const VT* __restrict__ x) {
-  const int xs = blockIdx.x % kSlices, lb = blockIdx.x / kSlices;
+  const int xs = blockIdx.x % d.sa.slices, lb = blockIdx.x / d.sa.slices;
   if (lb >= d.sa.wg[xs]) return;
   VT* __restrict__ part = d.part + size_t(xs) * d.m;
   auto pre = [](int) -> VT { return VT(0); };
@@ -872,8 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_comb(Dev<VT> d, VT* __restrict_
   const int m = d.m;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
     VT s = d.part[i];
-#pragma unroll
-    for (int x = 1; x < kSlices; ++x) s += d.part[size_t(x) * m + i];
+    for (int x = 1; x < d.sa.slices; ++x) s += d.part[size_t(x) * m + i];
     y[d.row_perm[i]] = s;
   }
 }
@@ -1395,13 +1442,23 @@ void launch_resid(const Dev<VT>& d, hipStream_t st) {
                static_cast<VT*>(nullptr));
     return;
   }
-  ACS_LAUNCH((k_resid_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d);
+  if (d.sa.slices == 1) {
+    ACS_LAUNCH((k_resid_one<VT>), dim3(d.sa.wg[0]), dim3(kBlock), 0, st, d);
+    return;
+  }
+  ACS_LAUNCH((k_resid_part<VT>), dim3(d.sa.slices * d.sa.wg_max), dim3(kBlock), 0, st, d);
   ACS_LAUNCH((k_resid_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
+}
+
+// workgroups whose ||r||^2 partials the finalize kernels of the CG sum
+template <typename VT>
+static int rr_blocks(const Dev<VT>& d) {
+  return d.dense ? dense_row_blocks(d.m) : d.sa.slices == 1 ? d.sa.wg[0] : comb_blocks(d.m);
 }
 
 template <typename VT>
 void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, int cg_max, hipStream_t st) {
-  const int nb = d.dense ? dense_row_blocks(d.m) : comb_blocks(d.m);
+  const int nb = rr_blocks(d);
   ACS_LAUNCH((k_fin_resid<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, iter, red2, abs2, cg_max);
 }
 
@@ -1424,18 +1481,22 @@ void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
                static_cast<VT*>(nullptr));
     return;
   }
-  ACS_LAUNCH((k_cg_a_part<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
+  if (d.sa.slices == 1) {  // the row product and the CG update of each row in one kernel
+    ACS_LAUNCH((k_cg_a_one<VT>), dim3(d.sa.wg[0]), dim3(kBlock), 0, st, d, d.st.wg[0]);
+    return;
+  }
+  ACS_LAUNCH((k_cg_a_part<VT>), dim3(d.sa.slices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
 }
 
 template <typename VT>
 void launch_cg_comb(const Dev<VT>& d, hipStream_t st) {
-  if (d.dense) return;  // fused into the row product
+  if (d.dense || d.sa.slices == 1) return;  // fused into the row product
   ACS_LAUNCH((k_cg_a_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 
 template <typename VT>
 void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
-  const int nb = d.dense ? dense_row_blocks(d.m) : comb_blocks(d.m);
+  const int nb = rr_blocks(d);
   ACS_LAUNCH((k_fin_cg_a<VT>), dim3(1), dim3(kBlock), 0, st, d, nb, launch_id);
 }
 
@@ -1517,7 +1578,7 @@ void launch_spmv(const Dev<VT>& d, int which, const VT* x, VT* y, hipStream_t st
     return;
   }
   if (which == 0) {
-    ACS_LAUNCH((k_spmv_a<VT>), dim3(kSlices * d.sa.wg_max), dim3(kBlock), 0, st, d, x);
+    ACS_LAUNCH((k_spmv_a<VT>), dim3(d.sa.slices * d.sa.wg_max), dim3(kBlock), 0, st, d, x);
     ACS_LAUNCH((k_spmv_comb<VT>), dim3(comb_blocks(d.m)), dim3(kBlock), 0, st, d, y);
   } else {
     ACS_LAUNCH((k_perm_in<VT>), dim3(ceil_div(d.m, kBlock)), dim3(kBlock), 0, st, d, x);

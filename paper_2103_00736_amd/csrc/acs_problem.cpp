@@ -159,25 +159,27 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
   return true;
 }
 
-const SellPair& Problem::sell() const {
+const SellPair& Problem::sell(int slices) const {
   if (dense) throw AcsError(ACS_ERR_STATE, "a dense problem has no sparse layout");
-  std::call_once(sell_once_, [this] {
+  if (slices != 1 && slices != kSlices) throw AcsError(ACS_ERR_ARG, "column slices of A must be 1 or 8");
+  const int which = slices == 1 ? 0 : 1;
+  std::call_once(sell_once_[which], [this, slices, which] {
     auto sp = std::make_unique<SellPair>();
-    // A t by column slices [x*w, (x+1)*w), w = ceil(n/kSlices): slice x holds
+    // A t by column slices [x*w, (x+1)*w), w = ceil(n/slices): slice x holds
     // the nonzeros of its columns, in row order
-    const int64_t w = (int64_t(n) + kSlices - 1) / kSlices;
-    std::vector<int32_t> srp(size_t(kSlices) * (m + 1), 0), scol(nnz), ssrc(nnz);
+    const int64_t w = (int64_t(n) + slices - 1) / slices;
+    std::vector<int32_t> srp(size_t(slices) * (m + 1), 0), scol(nnz), ssrc(nnz);
     for (int32_t i = 0; i < m; ++i)
       for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) srp[size_t(col[k] / w) * (m + 1) + i + 1]++;
     int32_t base = 0;
-    for (int x = 0; x < kSlices; ++x) {
+    for (int x = 0; x < slices; ++x) {
       int32_t* rp = &srp[size_t(x) * (m + 1)];
       rp[0] = base;
       for (int32_t i = 0; i < m; ++i) rp[i + 1] += rp[i];
       base = rp[m];
     }
-    std::vector<int32_t> fill(size_t(kSlices) * m);
-    for (int x = 0; x < kSlices; ++x)
+    std::vector<int32_t> fill(size_t(slices) * m);
+    for (int x = 0; x < slices; ++x)
       for (int32_t i = 0; i < m; ++i) fill[size_t(x) * m + i] = srp[size_t(x) * (m + 1) + i];
     for (int32_t i = 0; i < m; ++i)
       for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
@@ -187,7 +189,7 @@ const SellPair& Problem::sell() const {
       }
     std::vector<const int32_t*> rps;
     std::vector<int32_t> pads;
-    for (int x = 0; x < kSlices; ++x) {
+    for (int x = 0; x < slices; ++x) {
       rps.push_back(&srp[size_t(x) * (m + 1)]);
       pads.push_back(int32_t(std::min<int64_t>(x * w, n - 1)));
     }
@@ -196,9 +198,9 @@ const SellPair& Problem::sell() const {
     std::string err;
     if (!check_sell(sp->a, m, nnz, &err) || !check_sell(sp->t, n, nnz, &err))
       throw AcsError(ACS_ERR_DEVICE, "internal error in the SELL layout: " + err);
-    sell_ = std::move(sp);
+    sell_[which] = std::move(sp);
   });
-  return *sell_;
+  return *sell_[which];
 }
 
 void build_sell(const std::vector<const int32_t*>& rps, int32_t rows, const int32_t* col, const int32_t* src,

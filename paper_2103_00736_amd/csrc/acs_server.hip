@@ -109,7 +109,8 @@ class Server {
     // equilibration run on the worker streams
     r->small = !r->p->dense && r->s.projection == ACS_PROJ_CG && !r->s.equilibrate && r->p->nnz <= small_nnz_;
     r->bytes = r->small ? int64_t(layout_instance(*r->p, 0).end)
-                        : instance_device_bytes(*r->p, r->s.precision, r->s.projection, r->s.equilibrate);
+                        : instance_device_bytes(*r->p, r->s.precision, r->s.projection, r->s.equilibrate,
+                                                r->s.a_slices);
     if (r->bytes > budget_) throw AcsError(ACS_ERR_NOMEM, "request needs more device memory than the server budget");
     r->t_submit = Clock::now();
     {

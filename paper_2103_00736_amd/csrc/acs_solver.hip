@@ -84,6 +84,9 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
   if ((s.equilibrate != 0 && s.equilibrate != 1) || s.eq_sweeps < 0)
     throw AcsError(ACS_ERR_ARG, "settings: equilibrate must be 0 or 1 and eq_sweeps >= 0");
   if (s.equilibrate && p.dense) throw AcsError(ACS_ERR_ARG, "settings: equilibration takes sparse problems only");
+  if (s.a_slices != 0 && s.a_slices != 1 && s.a_slices != kSlices)
+    throw AcsError(ACS_ERR_ARG, "settings: a_slices must be 0, 1 or 8");
+  if (!p.dense) s.a_slices = p.a_slices(s.a_slices);
   return s;
 }
 
@@ -268,7 +271,7 @@ static void check_factor_fits(const Problem& p) {
     throw AcsError(ACS_ERR_ARG, "direct projection: the dense copy of A (m x n) exceeds 2^31 entries");
 }
 
-static int64_t estimate_bytes(const Problem& p, int precision) {
+static int64_t estimate_bytes(const Problem& p, int precision, int a_slices) {
   const int64_t vt = precision == ACS_PREC_FP64 ? 8 : 4;
   const int64_t nnz = p.nnz, m = p.m, n = p.n;
   if (p.dense) {
@@ -279,17 +282,19 @@ static int64_t estimate_bytes(const Problem& p, int precision) {
     b += 8 * kMaxSums * (m / 16 + n / kBlock + 4) + 8 * kBlock + 64 * 256;
     return b;
   }
-  const SellPair& sp = p.sell();
+  const int slices = p.a_slices(a_slices);
+  const SellPair& sp = p.sell(slices);
   int64_t b = 0;
   b += 4 * (m + 1) + 4 * nnz + 8 * nnz + 8 * nnz;        // A pattern, original and FP64 scaled values
   const int64_t v64 = vt == 8 ? 0 : 8;                   // FP64 SELL values beside the VT ones
   for (const Sell* S : {&sp.a, &sp.t})                   // SELL layouts: entries, tasks, chunk rows
     b += (8 + vt + v64) * int64_t(S->col.size()) + 12 * int64_t(S->wt_ptr.size() + S->long_row.size()) +
          4 * int64_t(S->chunk_row.size());
-  b += (vt + 8) * kSlices * m + (4 + vt) * m;            // slice partials, row permutation, scratch
+  b += (vt + 8) * slices * m + (4 + vt) * m;             // slice partials, row permutation, scratch
+  b += 8 * int64_t(sp.t.wg_max) + 256;                   // ||t||^2 partials of the one-slice CG
   b += 8 * int64_t(p.a_blocks.size());
   b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
-  const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max),
+  const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max), size_t(sp.a.wg_max),
                                          size_t(n / kBlock + 2)});
   b += 8 * kMaxSums * int64_t(parts) + 8 * kBlock + 64 * 256;  // partials, per-array alignment
   return b;
@@ -408,7 +413,7 @@ class Instance final : public InstanceBase {
     d.a_nblk = int(p.a_blocks.size());
     d.a_rp_nnz = int32_t(p.nnz);
     {
-      const SellPair& sp = p.sell();
+      const SellPair& sp = p.sell(S.a_slices);
       auto sell_dev = [&](const Sell& S, SellDev* D) {
         auto put = [&](const std::vector<int32_t>& v) -> const int32_t* {
           int32_t* ptr = arena_.alloc<int32_t>(std::max<size_t>(v.size(), 1));
@@ -445,8 +450,10 @@ class Instance final : public InstanceBase {
         d.sa_val64 = arena_.alloc<double>(std::max<size_t>(sp.a.col.size(), 1));
         d.st_val64 = arena_.alloc<double>(std::max<size_t>(sp.t.col.size(), 1));
       }
-      d.part = arena_.alloc<VT>(size_t(kSlices) * p.m);
-      d.part64 = arena_.alloc<double>(size_t(kSlices) * p.m);
+      d.part = arena_.alloc<VT>(size_t(S.a_slices) * p.m);
+      d.part64 = arena_.alloc<double>(size_t(S.a_slices) * p.m);
+      // ||t||^2 partials of k_cg_t, read by the one-slice second half
+      d.partials2 = arena_.alloc<double>(std::max<size_t>(size_t(sp.t.wg_max), 1));
     }
   }
 
@@ -610,7 +617,7 @@ class Instance final : public InstanceBase {
     d.ounit = arena_.alloc<double>(size_t(p.n_orth) + p.soc_size.size());
     d.ctl = arena_.alloc<Ctl>(1);
     const size_t units = size_t(p.n_orth) + p.soc_size.size();
-    nparts_ = std::max<size_t>({p.a_blocks.size(), size_t(d.st.wg_max), units / kBlock + 1,
+    nparts_ = std::max<size_t>({p.a_blocks.size(), size_t(d.st.wg_max), size_t(d.sa.wg_max), units / kBlock + 1,
                                  p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, size_t(p.n) / kBlock + 1,
                                  size_t(p.m) / 16 + 1, 1});
     d.partials = arena_.alloc<double>(nparts_ * kMaxSums);
@@ -1098,8 +1105,8 @@ SolveOut solve_one_instance(std::shared_ptr<const Problem> p, const acs_settings
   return o;
 }
 
-int64_t instance_device_bytes(const Problem& p, int precision, int projection, int equilibrate) {
-  return estimate_bytes(p, precision) + (projection == ACS_PROJ_FACTOR ? factor_bytes(p) : 0) +
+int64_t instance_device_bytes(const Problem& p, int precision, int projection, int equilibrate, int a_slices) {
+  return estimate_bytes(p, precision, a_slices) + (projection == ACS_PROJ_FACTOR ? factor_bytes(p) : 0) +
          (equilibrate ? 8 * (2 * int64_t(p.n) + p.m) + 3 * 256 : 0);
 }
 
@@ -1247,7 +1254,7 @@ void acs_problem_destroy(acs_problem* p) { delete p; }
 
 int64_t acs_problem_device_bytes(const acs_problem* p, int32_t precision) {
   if (!p) return -1;
-  return estimate_bytes(*p->p, precision);
+  return estimate_bytes(*p->p, precision, 0);
 }
 
 int acs_state_create(const acs_problem* p, const acs_settings* s, void* stream, acs_state** out) {
@@ -1382,7 +1389,7 @@ int acs_solve_device_noalloc(const acs_problem* p, const acs_settings* s, double
     }
     if (s->projection != ACS_PROJ_CG)
       throw AcsError(ACS_ERR_ARG, "acs_solve_device_noalloc: only the CG projection (ACS_PROJ_CG)");
-    const int64_t need = instance_device_bytes(*p->p, s->precision, ACS_PROJ_CG, s->equilibrate);
+    const int64_t need = instance_device_bytes(*p->p, s->precision, ACS_PROJ_CG, s->equilibrate, s->a_slices);
     if (need > int64_t(kNoAllocBytes))
       throw AcsError(ACS_ERR_NOMEM, "acs_solve_device_noalloc: the problem needs " + std::to_string(need) +
                                         " device bytes, the fixed scratch holds " + std::to_string(kNoAllocBytes));

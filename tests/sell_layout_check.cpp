@@ -95,7 +95,6 @@ static int check_case(const char* name, const Csr& A) {
       if (p.col[p.row_ptr[i] + k] != A.col[A.rp[o] + k] || p.val[p.row_ptr[i] + k] != A.val[A.rp[o] + k])
         return std::printf("%s: row contents\n", name), 1;
   }
-  const SellPair& sp = p.sell();
   std::mt19937_64 rng(3);
   std::normal_distribution<double> N(0, 1);
   std::vector<double> xn(A.n), xm(A.m);
@@ -116,26 +115,33 @@ static int check_case(const char* name, const Csr& A) {
       atx[A.col[k]] += A.val[k] * xm[i];
       atx_abs[A.col[k]] += std::fabs(A.val[k] * xm[i]);
     }
-  // A x: slices summed in order, written back through row_perm
+  // A x with 1 and with kSlices column slices: slices summed in order,
+  // written back through row_perm
   std::vector<int> writes;
-  std::vector<double> part = sell_product(sp.a, A.m, vals_of(sp.a), xn, &writes);
-  for (int w : writes)
-    if (w != 1) return std::printf("%s: A side output written %d times\n", name, w), 1;
-  const int64_t w = (int64_t(A.n) + kSlices - 1) / kSlices;
-  for (int i = 0; i < A.m; ++i) {
-    double s = 0;
-    for (int x = 0; x < kSlices; ++x) s += part[size_t(x) * A.m + i];
-    const int o = p.row_perm[i];
-    if (std::fabs(s - ax[o]) > 1e-12 * (ax_abs[o] + 1e-300)) return std::printf("%s: A x row %d\n", name, o), 1;
-  }
-  // every A-side entry lies in its slice's column range
-  for (int x = 0; x < kSlices; ++x) {
-    for (int t = sp.a.wt_off[x]; t < sp.a.wt_off[x + 1]; ++t) {
-      const int64_t span = sp.a.wt_row[t] >= 0 ? sp.a.wt_len[t] : int64_t(sp.a.wt_len[t]) * kSellChunk;
-      for (int64_t e = sp.a.wt_ptr[t]; e < sp.a.wt_ptr[t] + span; ++e)
-        if (sp.a.col[e] / w != x) return std::printf("%s: entry outside slice %d\n", name, x), 1;
+  for (const int slices : {1, kSlices}) {
+    const SellPair& sa = p.sell(slices);
+    if (sa.a.slices != slices) return std::printf("%s: %d slices asked, %d built\n", name, slices, sa.a.slices), 1;
+    std::vector<double> part = sell_product(sa.a, A.m, vals_of(sa.a), xn, &writes);
+    for (int w : writes)
+      if (w != 1) return std::printf("%s: A side output written %d times (%d slices)\n", name, w, slices), 1;
+    const int64_t w = (int64_t(A.n) + slices - 1) / slices;
+    for (int i = 0; i < A.m; ++i) {
+      double s = 0;
+      for (int x = 0; x < slices; ++x) s += part[size_t(x) * A.m + i];
+      const int o = p.row_perm[i];
+      if (std::fabs(s - ax[o]) > 1e-12 * (ax_abs[o] + 1e-300))
+        return std::printf("%s: A x row %d (%d slices)\n", name, o, slices), 1;
+    }
+    // every A-side entry lies in its slice's column range
+    for (int x = 0; x < slices; ++x) {
+      for (int t = sa.a.wt_off[x]; t < sa.a.wt_off[x + 1]; ++t) {
+        const int64_t span = sa.a.wt_row[t] >= 0 ? sa.a.wt_len[t] : int64_t(sa.a.wt_len[t]) * kSellChunk;
+        for (int64_t e = sa.a.wt_ptr[t]; e < sa.a.wt_ptr[t] + span; ++e)
+          if (sa.a.col[e] / w != x) return std::printf("%s: entry outside slice %d\n", name, x), 1;
+      }
     }
   }
+  const SellPair& sp = p.sell(kSlices);
   // A^T x: input in internal order
   std::vector<double> xm_int(A.m);
   for (int i = 0; i < A.m; ++i) xm_int[i] = xm[p.row_perm[i]];

@@ -37,6 +37,7 @@ def test_settings_defaults_and_layout():
     assert s.eps_kkt == 1e-4 and s.precision == acs.PREC_MIXED and s.projection == acs.PROJ_CG
     assert s.obj_stop == 1
     assert s.cg_reduce == 0.0  # per class: 0.1 for LPs, 0.2 for SOCPs
+    assert s.a_slices == 0  # column slices of A by size
     assert acs.version().startswith("acs")
 
 

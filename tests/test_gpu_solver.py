@@ -52,20 +52,21 @@ def _device():
 @pytest.mark.parametrize("name", list(PROBLEMS))
 @pytest.mark.parametrize("prec", [acs.PREC_FP64, acs.PREC_MIXED])
 @pytest.mark.parametrize("l0", [57, 317])
-def test_one_iteration_parity(name, prec, l0):
+@pytest.mark.parametrize("slices", [1, 8])
+def test_one_iteration_parity(name, prec, l0, slices):
     p = PROBLEMS[name]()
     t, L = default_parameters(p.soc_sizes)
     alg, s_prev, s, O, w = _oracle_run(p, l0, t, L)
     if prec == acs.PREC_MIXED:
         s_prev, s = _f32(s_prev), _f32(s)
     st = acs.State(acs.Problem.from_synth(p), precision=prec, cg_max=2000,
-                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7)
+                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7, a_slices=slices)
     st.set(l0, s_prev, s, O, w)
     st.step(1)
     g = st.get()
     ref = one_iteration(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, 1.0, s, O)
     errs = iterate_errors(g, ref, O)
-    print(f"{name} prec={prec} l0={l0} (normwise/elementwise): {fmt(errs)}")
+    print(f"{name} prec={prec} l0={l0} slices={slices} (normwise/elementwise): {fmt(errs)}")
     assert g["l"] == l0 + 1
     assert np.array_equal(g["s_prev"], s)
     assert_iterate(errs, prec == acs.PREC_FP64, name)
@@ -73,7 +74,8 @@ def test_one_iteration_parity(name, prec, l0):
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
 @pytest.mark.parametrize("prec", [acs.PREC_FP64, acs.PREC_MIXED])
-def test_conditioning_event_parity(name, prec):
+@pytest.mark.parametrize("slices", [1, 8])
+def test_conditioning_event_parity(name, prec, slices):
     p = PROBLEMS[name]()
     t, L = default_parameters(p.soc_sizes)
     l_event = L.first + L.every  # a member of L after the first event
@@ -87,13 +89,13 @@ def test_conditioning_event_parity(name, prec):
     alg.l = l_event - 1
     alg.step()  # conditions (steps 5-14) then iterates
     st = acs.State(acs.Problem.from_synth(p), precision=prec, cg_max=2000,
-                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7)
+                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7, a_slices=slices)
     st.set(l_event - 1, s_prev, s, O, w)
     st.step(1)
     g = st.get()
     ref = {"O": alg.O, "s": alg.s, "x": alg.x, "z": alg.z}
     errs = iterate_errors(g, ref, alg.O, ("O", "s", "x", "z"))
-    print(f"{name} prec={prec}: {fmt(errs)} O range {np.log(alg.O.max() / alg.O.min()):.3f}")
+    print(f"{name} prec={prec} slices={slices}: {fmt(errs)} O range {np.log(alg.O.max() / alg.O.min()):.3f}")
     assert_close({"O": errs.pop("O")}, 1e-9, name)
     assert_iterate(errs, prec == acs.PREC_FP64, name)
 
@@ -125,9 +127,11 @@ def test_solve_config0_fp64():
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
-def test_solve_mixed_to_1e4(name):
+@pytest.mark.parametrize("slices", [1, 8])
+def test_solve_mixed_to_1e4(name, slices):
     p = PROBLEMS[name]()
-    x, y, z, info = acs.solve(acs.Problem.from_synth(p), precision=acs.PREC_MIXED, eps_kkt=1e-4, max_iter=20000)
+    x, y, z, info = acs.solve(acs.Problem.from_synth(p), precision=acs.PREC_MIXED, eps_kkt=1e-4, max_iter=20000,
+                              a_slices=slices)
     rec, obj_err = _verify(p, x, y, z, info, 1.05e-4)
     assert obj_err <= 1e-4
 
@@ -151,12 +155,13 @@ def test_paper_example_fp64():
     assert np.allclose(x, best[2], atol=1e-5)
 
 
-def test_determinism_bitwise():
+@pytest.mark.parametrize("slices", [1, 8])
+def test_determinism_bitwise(slices):
     p = synth.config1(scale=0.002)
     prob = acs.Problem.from_synth(p)
     outs = []
     for _ in range(2):
-        st = acs.State(prob, precision=acs.PREC_MIXED)
+        st = acs.State(prob, precision=acs.PREC_MIXED, a_slices=slices)
         st.step(120)
         outs.append(st.get())
         st.close()
