@@ -59,6 +59,7 @@ constexpr int kMaxSums = kUpdSums;
 // Device control block of one instance (CG scalars, reductions, flags).
 struct Ctl {
   double rho;     // ||r||^2 of the current CG residual
+  double rho_step[2];  // ||r||^2 at the start of CG step j, in slot j & 1 (one-slice CG)
   double rho0;    // ||r_0||^2 of this outer iteration
   double tol2;    // CG stops when rho <= tol2
   double alpha;   // CG step length
@@ -76,7 +77,7 @@ struct Ctl {
 
 // Host-visible status written by kernels into pinned, mapped host memory.
 struct HostStatus {
-  long long launch_seq;  // id of the last finished CG-A launch
+  long long launch_seq;  // id of the last CG step the GPU has finished (8 slices) or reached (1 slice)
   int32_t cg_done_iter;  // last outer iteration whose CG finished
   int32_t check_iter;    // last iteration whose KKT check finished
   double kkt[9];         // copy of Ctl::kkt of check_iter
@@ -225,8 +226,12 @@ template <typename VT> void launch_fin_resid(const Dev<VT>& d, int iter, double 
                                              hipStream_t st);
 // the two CG sweeps (alpha in the first workgroup of the sliced one), the
 // combine with the CG update, and the finalizer (beta, stop test, host progress record)
-template <typename VT> void launch_cg_t(const Dev<VT>& d, hipStream_t st);
-template <typename VT> void launch_cg_a(const Dev<VT>& d, hipStream_t st);
+// CG step j (0-based) of the outer iteration; the one-slice layout finalizes
+// step j-1 inside k_cg_t and posts `launch_id` from k_cg_a_one
+template <typename VT> void launch_cg_t(const Dev<VT>& d, int j, hipStream_t st);
+template <typename VT> void launch_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st);
+// whether the per-step finalize (k_fin_cg_a) is folded into the next step
+template <typename VT> bool cg_fin_folded(const Dev<VT>& d) { return !d.dense && d.sa.slices == 1; }
 template <typename VT> void launch_cg_comb(const Dev<VT>& d, hipStream_t st);
 template <typename VT> void launch_fin_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st);
 template <typename VT> void launch_pres(const Dev<VT>& d, int iter, double bnorm, double cnorm, hipStream_t st);

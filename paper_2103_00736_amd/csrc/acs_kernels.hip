@@ -487,11 +487,42 @@ __global__ __launch_bounds__(kBlock) void k_resid_one(Dev<VT> d) {
 // CG, first half: t = A_s^T q with q = r + beta q_old, kept as the recurrence
 // t = A_s^T r + beta t_old (one gathered operand); alpha = rho / ||t||^2
 // ----------------------------------------------------------------------------
+// j >= 1 with the one-slice layout: every workgroup first finalizes step j-1
+// from the second half's ||r||^2 partials, in the same order (as k_fin_cg_a
+// does in one workgroup), so all agree on beta and on the stop test;
+// workgroup 0 records the result.  It reads rho of step j-1 from the slot of
+// that step and writes step j's into the other slot, so no workgroup of this
+// kernel reads what another writes.  j < 0: k_fin_cg_a ran.
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
-  if (d.ctl->done) return;
+__global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d, int j, int rr_nb) {
+  __shared__ int done_sh;
+  if (threadIdx.x == 0) done_sh = d.ctl->done;
+  __syncthreads();
+  if (done_sh) return;
+  double beta = d.ctl->beta;
+  if (j >= 1) {
+    double t[1];
+    sum_partials<1>(d.partials, rr_nb, t);
+    Ctl* c = d.ctl;
+    const double rn = t[0];
+    const bool bad = !(rn == rn) || isinf(rn);
+    beta = bad ? 0.0 : rn / c->rho_step[(j - 1) & 1];
+    const bool done = bad || rn <= c->tol2 || j >= c->cg_max;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c->rho_step[j & 1] = rn;
+      c->rho = rn;
+      c->beta = beta;
+      c->k = j;
+      c->cg_total += 1;
+      if (done) {
+        c->done = 1;
+        if (bad) host_post(&d.hs->numeric, 1);
+        host_post(&d.hs->cg_done_iter, c->iter);
+      }
+    }
+    if (done) return;
+  }
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const double beta = d.ctl->beta;
   const VT vbeta = VT(beta);
   double acc[1] = {0};
   auto pre = [&](int j) -> VT { return beta != 0.0 ? d.t[j] : VT(0); };
@@ -513,7 +544,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d) {
 // ----------------------------------------------------------------------------
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
-  if (d.ctl->done) return;
+  __shared__ int done_sh;  // workgroup 0 may set done below: one read per workgroup
+  if (threadIdx.x == 0) done_sh = d.ctl->done;
+  __syncthreads();
+  if (done_sh) return;
   if (blockIdx.x == 0) {
     double tt[1];
     sum_partials<1>(d.partials, t_nb, tt);
@@ -570,9 +604,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_comb(Dev<VT> d) {
 // update of each row in one kernel.  Every workgroup turns the first half's
 // partials into alpha in the same order (so all agree); workgroup 0 records it.
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_cg_a_one(Dev<VT> d, int t_nb) {
-  __shared__ int bad_sh;
-  if (d.ctl->done) return;
+__global__ __launch_bounds__(kBlock) void k_cg_a_one(Dev<VT> d, int t_nb, long long launch_id) {
+  __shared__ int bad_sh, done_sh;
+  if (blockIdx.x == 0 && threadIdx.x == 0) host_post(&d.hs->launch_seq, launch_id);  // host's progress
+  if (threadIdx.x == 0) done_sh = d.ctl->done;
+  __syncthreads();
+  if (done_sh) return;
   double tt[1];
   sum_partials<1>(d.partials2, t_nb, tt);
   if (threadIdx.x == 0) bad_sh = !(tt[0] > 0.0) || isinf(tt[0]);
@@ -950,12 +987,13 @@ __global__ void k_ctl_reset(Dev<VT> d, int cg_max) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     Ctl* c = d.ctl;
     c->rho = c->rho0 = c->tol2 = c->alpha = c->beta = 0.0;
+    c->rho_step[0] = c->rho_step[1] = 0.0;
     c->k = 0;
     c->done = 1;
     c->cg_max = cg_max;
     c->iter = 0;
     c->cg_total = 0;
-    for (int i = 0; i < 8; ++i) c->upd[i] = 0.0;
+    for (int i = 0; i < kUpdSums; ++i) c->upd[i] = 0.0;
     for (int i = 0; i < 4; ++i) c->cone[i] = 0.0;
     for (int i = 0; i < 4; ++i) c->cond[i] = 0.0;
     for (int i = 0; i < 9; ++i) c->kkt[i] = 0.0;
@@ -997,6 +1035,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_resid(Dev<VT> d, int nb, int ite
     c->cg_max = cg_max;
     c->rho = rho;
     c->rho0 = rho;
+    c->rho_step[0] = rho;
     c->tol2 = fmax(red2 * rho, abs2);
     c->alpha = 0.0;
     c->beta = 0.0;
@@ -1201,13 +1240,15 @@ __device__ __forceinline__ void dense_rows4(const Dev<VT>& d, int i0, const XT* 
 // y = A_s x from dx32 = O x.
 template <typename VT, int KIND>
 __global__ __launch_bounds__(kBlock) void k_dense_rows(Dev<VT> d, int aux, VT* __restrict__ y) {
-  __shared__ int bad_sh;
+  __shared__ int bad_sh, done_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i0 = (blockIdx.x * (kBlock / 64) + wave) * kDenseRows;
   double acc[3] = {0, 0, 0};
   double alpha = 0, beta = 0;
   if (KIND == DK_CG) {
-    if (d.ctl->done) return;
+    if (threadIdx.x == 0) done_sh = d.ctl->done;  // workgroup 0 may set done below
+    __syncthreads();
+    if (done_sh) return;
     double tt[1];
     sum_partials<1>(d.partials2, aux, tt);
     if (threadIdx.x == 0) bad_sh = !(tt[0] > 0.0) || isinf(tt[0]);
@@ -1463,7 +1504,7 @@ void launch_fin_resid(const Dev<VT>& d, int iter, double red2, double abs2, int 
 }
 
 template <typename VT>
-void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
+void launch_cg_t(const Dev<VT>& d, int j, hipStream_t st) {
   if (d.dense) {
     ACS_LAUNCH((k_dense_cols<VT, DK_CG>), dim3(ceil_div(d.ld, kDenseStrip), d.dnchunk), dim3(kBlock), 0, st, d,
                static_cast<const VT*>(nullptr));
@@ -1471,18 +1512,18 @@ void launch_cg_t(const Dev<VT>& d, hipStream_t st) {
                static_cast<const VT*>(nullptr), static_cast<VT*>(nullptr));
     return;
   }
-  ACS_LAUNCH((k_cg_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d);
+  ACS_LAUNCH((k_cg_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d, cg_fin_folded(d) ? j : -1, rr_blocks(d));
 }
 
 template <typename VT>
-void launch_cg_a(const Dev<VT>& d, hipStream_t st) {
+void launch_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
   if (d.dense) {  // the row product and the CG update of each row in one kernel
     ACS_LAUNCH((k_dense_rows<VT, DK_CG>), dim3(dense_row_blocks(d.m)), dim3(kBlock), 0, st, d, ceil_div(d.n, kBlock),
                static_cast<VT*>(nullptr));
     return;
   }
   if (d.sa.slices == 1) {  // the row product and the CG update of each row in one kernel
-    ACS_LAUNCH((k_cg_a_one<VT>), dim3(d.sa.wg[0]), dim3(kBlock), 0, st, d, d.st.wg[0]);
+    ACS_LAUNCH((k_cg_a_one<VT>), dim3(d.sa.wg[0]), dim3(kBlock), 0, st, d, d.st.wg[0], launch_id);
     return;
   }
   ACS_LAUNCH((k_cg_a_part<VT>), dim3(d.sa.slices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
@@ -1601,8 +1642,8 @@ void launch_ctl_reset(const Dev<VT>& d, int cg_max, hipStream_t st) {
   template void launch_cone<VT>(const Dev<VT>&, const VT*, bool, bool, int, hipStream_t);            \
   template void launch_resid<VT>(const Dev<VT>&, hipStream_t);                                        \
   template void launch_fin_resid<VT>(const Dev<VT>&, int, double, double, int, hipStream_t);               \
-  template void launch_cg_t<VT>(const Dev<VT>&, hipStream_t);                                         \
-  template void launch_cg_a<VT>(const Dev<VT>&, hipStream_t);                                         \
+  template void launch_cg_t<VT>(const Dev<VT>&, int, hipStream_t);                                    \
+  template void launch_cg_a<VT>(const Dev<VT>&, long long, hipStream_t);                              \
   template void launch_cg_comb<VT>(const Dev<VT>&, hipStream_t);                                      \
   template void launch_fin_cg_a<VT>(const Dev<VT>&, long long, hipStream_t);                          \
   template void launch_pres<VT>(const Dev<VT>&, int, double, double, hipStream_t);                    \

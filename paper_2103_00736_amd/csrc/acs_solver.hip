@@ -860,21 +860,29 @@ class Instance final : public InstanceBase {
   int hs_cg_done() { return __atomic_load_n(&hs_->cg_done_iter, __ATOMIC_ACQUIRE); }
   int hs_check() { return __atomic_load_n(&hs_->check_iter, __ATOMIC_ACQUIRE); }
 
-  // CG for outer iteration `it`: chunks of launches, at most one chunk ahead
+  // CG for outer iteration `it`: chunks of launches, at most one chunk ahead.
+  // Each step's id reaches the host's record from k_fin_cg_a, or (one-slice
+  // layout, whose k_cg_t finalizes the step before it) from k_cg_a_one; there
+  // the last step of a capped CG gets a k_fin_cg_a of its own.
   void run_cg(int it, int cg_max) {
     const int chunk = 2;
+    const bool folded = cg_fin_folded(d_);
     int launched = 0;
     while (launched < cg_max) {
       const int c = std::min(chunk, cg_max - launched);
       for (int i = 0; i < c; ++i) {
-        timed(KC_CG_T, [&] { launch_cg_t(d_, st_); });
-        timed(KC_CG_A, [&] { launch_cg_a(d_, st_); });
-        timed(KC_CG_COMB, [&] { launch_cg_comb(d_, st_); });
+        const int j = launched + i;
         const long long id = ++launch_id_;
-        timed(KC_FIN, [&] { launch_fin_cg_a(d_, id, st_); });
+        timed(KC_CG_T, [&] { launch_cg_t(d_, j, st_); });
+        timed(KC_CG_A, [&] { launch_cg_a(d_, id, st_); });
+        timed(KC_CG_COMB, [&] { launch_cg_comb(d_, st_); });
+        if (!folded) timed(KC_FIN, [&] { launch_fin_cg_a(d_, id, st_); });
       }
       launched += c;
-      if (launched >= cg_max) break;
+      if (launched >= cg_max) {
+        if (folded) timed(KC_FIN, [&] { launch_fin_cg_a(d_, launch_id_, st_); });
+        break;
+      }
       const long long target = launch_id_ - c;
       wait_for([&] { return hs_cg_done() >= it || hs_launch_seq() >= target; });
       if (hs_cg_done() >= it) return;
