@@ -370,7 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<VT> d, const VT* __restri
   auto pre = [](int) -> double { return 0.0; };
   auto epi = [&](int j, double u, double) { upd(j, u); };
   sell_rows<double, double>(d.st, d.st_val64, 0, blk, d.w, pre, epi);
-  if (MODE != UPD_PROLOGUE) block_store_partials<kUpdSums>(acc, d.partials, blk);
+  // the sums are read only by the KKT check (k_fin_upd runs on check iterations)
+  if (MODE != UPD_PROLOGUE && CHECK) block_store_partials<kUpdSums>(acc, d.partials, blk);
 }
 
 // ----------------------------------------------------------------------------
@@ -1387,7 +1388,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_fin(Dev<VT> d, const VT* 
   if (KIND == DK_CG) {
     double a1[1] = {acc[0]};
     block_store_partials<1>(a1, d.partials2, blockIdx.x);
-  } else if (KIND == DK_UPDATE && MODE != UPD_PROLOGUE) {
+  } else if (KIND == DK_UPDATE && MODE != UPD_PROLOGUE && CHECK) {
     block_store_partials<kUpdSums>(acc, d.partials, blockIdx.x);
   }
 }
@@ -1435,7 +1436,7 @@ static void launch_dense_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, in
     else
       ACS_LAUNCH((k_dense_cols_fin<VT, DK_UPDATE, UPD_UPDATE_ONLY, false>), gf, b, 0, st, d, s_cur, s_new);
   }
-  ACS_LAUNCH((k_fin_upd<VT>), dim3(1), b, 0, st, d, int(gf.x));
+  if (check) ACS_LAUNCH((k_fin_upd<VT>), dim3(1), b, 0, st, d, int(gf.x));
 }
 
 template <typename VT>
@@ -1460,7 +1461,7 @@ void launch_update(const Dev<VT>& d, const VT* s_cur, VT* s_new, int mode, bool 
     else
       ACS_LAUNCH((k_update<VT, UPD_UPDATE_ONLY, false>), g, b, 0, st, d, s_cur, s_new);
   }
-  ACS_LAUNCH((k_fin_upd<VT>), dim3(1), b, 0, st, d, d.st.wg[0]);
+  if (check) ACS_LAUNCH((k_fin_upd<VT>), dim3(1), b, 0, st, d, d.st.wg[0]);  // sums only the check reads
 }
 
 template <typename VT>

@@ -155,6 +155,32 @@ def test_paper_example_fp64():
     assert np.allclose(x, best[2], atol=1e-5)
 
 
+@pytest.mark.parametrize("cg_max", [1, 2, 3])
+def test_cg_step_cap_both_layouts(cg_max):
+    """A CG stopped by its step cap in every outer iteration (a reduction no
+    step reaches): every iteration counts exactly cg_max steps with either
+    layout (the one-slice CG finalizes its last step in a kernel of its own),
+    and the two layouts' FP64 iterates agree to rounding after 1 and 20
+    iterations."""
+    p = synth.config1(scale=0.002)
+    prob = acs.Problem.from_synth(p)
+    outs = {}
+    for slices in (1, 8):
+        st = acs.State(prob, precision=acs.PREC_FP64, cg_max=cg_max, cg_reduce=1e-30, a_slices=slices)
+        st.step(1)
+        g1, c1 = st.get(), st.info().cg_steps
+        st.step(19)
+        g20, c20 = st.get(), st.info().cg_steps
+        st.close()
+        assert (c1, c20) == (cg_max, 20 * cg_max), (slices, c1, c20)
+        outs[slices] = (g1, g20)
+    for k, (a, b) in enumerate(zip(outs[1], outs[8])):
+        for key in ("s", "w", "x", "z"):
+            err = np.linalg.norm(a[key] - b[key]) / max(np.linalg.norm(b[key]), 1e-300)
+            print(f"cg_max={cg_max} after {(1, 20)[k]}: {key} {err:.1e}")
+            assert err <= 1e-9, (key, err)
+
+
 @pytest.mark.parametrize("slices", [1, 8])
 def test_determinism_bitwise(slices):
     p = synth.config1(scale=0.002)
