@@ -375,10 +375,10 @@ int acs_batch_solve(int32_t count, const acs_problem* const* probs, const acs_se
  * A request whose footprint exceeds the budget fails at submit with
  * ACS_ERR_NOMEM.  Choosing small_nnz: a pool request runs on one workgroup,
  * so its latency grows with its nonzeros (a 200k-nonzero LP took seconds,
- * against about 50 ms on the worker path); measured on a trace of requests
- * with m log-uniform in [1e3, 2e5], small_nnz = 20000 and 3 workers served
- * 1.95x the one-at-a-time rate, small_nnz = 200000 0.3x, and 8 workers less
- * than 3.
+ * against about 50 ms on the worker path).  Measured on a trace of 120
+ * requests with m log-uniform in [1e3, 2e5] and small_nnz = 20000, served
+ * over solved one at a time: 2 workers 2.0x, 3 2.0x, 4 2.1x, 6 2.6x, 8 2.5x;
+ * small_nnz = 200000 served at 0.3x.
  */
 typedef struct acs_server acs_server;
 typedef struct acs_server_counters {

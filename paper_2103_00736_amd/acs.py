@@ -446,7 +446,7 @@ class Batch:
 class Server:
     """Continuous-batching request loop (acs_server)."""
 
-    def __init__(self, hbm_budget: int = 64 << 30, max_slots: int = 256, small_nnz: int = 20_000, workers: int = 3,
+    def __init__(self, hbm_budget: int = 64 << 30, max_slots: int = 256, small_nnz: int = 20_000, workers: int = 6,
                  tick_iters: int = 50):
         h = P()
         _check(lib().acs_server_create(int(hbm_budget), int(max_slots), int(small_nnz), int(workers),

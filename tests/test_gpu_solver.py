@@ -12,6 +12,7 @@ Vectors are compared normwise and element by element (tests/_parity.py).
 """
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from oracle.alg2 import Algorithm2, Schedule, default_parameters, one_iteration
 from oracle.cones import abs_K
@@ -179,6 +180,36 @@ def test_cg_step_cap_both_layouts(cg_max):
             err = np.linalg.norm(a[key] - b[key]) / max(np.linalg.norm(b[key]), 1e-300)
             print(f"cg_max={cg_max} after {(1, 20)[k]}: {key} {err:.1e}")
             assert err <= 1e-9, (key, err)
+
+
+def test_constraint_matrix_without_nonzeros():
+    """A = 0 (m = 3 rows, no nonzeros), b = 0, c >= 0 on the orthant: the
+    optimum is x = 0, z = c, objective 0, which the oracle reaches too.  Every
+    product sweep then runs over empty rows (one-instance path, both layouts
+    and precisions, and the batch kernel)."""
+    m, n = 3, 5
+    c = np.array([1.0, 2.0, 0.5, 0.0, 3.0])
+    rp, ci, v, b = np.zeros(m + 1, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0), np.zeros(m)
+    A = sp.csr_matrix((m, n))
+    t, L = default_parameters([])
+    alg = Algorithm2(A, b, c, n, [], mu=1.0, t=t, schedule=L)
+    alg.run(2000, eps=1e-8, check_every=10)
+    assert np.allclose(alg.x, 0.0) and np.allclose(alg.z, c)
+    h = acs.Problem(m, n, rp, ci, v, b, c, n)
+    for prec in (acs.PREC_FP64, acs.PREC_MIXED):
+        for slices in (1, 8):
+            x, y, z, info = acs.solve(h, precision=prec, eps_kkt=1e-8, max_iter=2000, a_slices=slices)
+            assert info.status == acs.SOLVED, (prec, slices, info.status)
+            tol = 1e-12 if prec == acs.PREC_FP64 else 1e-6
+            assert np.abs(x).max() <= tol and np.abs(z - c).max() <= tol * np.abs(c).max(), (prec, slices)
+            assert abs(info.pobj) <= tol
+    bt = acs.Batch([h, h], eps_kkt=1e-8, max_iter=2000)
+    bt.run(2000)
+    for i in range(2):
+        x, y, z, info = bt.result(i)
+        assert info.status == acs.SOLVED and np.abs(x).max() <= 1e-6 and np.abs(z - c).max() <= 1e-6 * np.abs(c).max()
+    bt.close()
+    h.close()
 
 
 @pytest.mark.parametrize("slices", [1, 8])
