@@ -109,6 +109,19 @@ def cpu_child(args):
             Algorithm2(q.scipy_csr(), q.b, q.c, q.n_orth, q.soc_sizes, mu=1.0, t=t, schedule=L).run(
                 20000, eps=1e-4, check_every=10, obj_stop=1.0)
         out["batch"] = {"solves": len(idx), "seconds": time.perf_counter() - t0}
+        # the serving trace: service times of its four smallest requests (the
+        # oracle takes minutes on the larger ones)
+        trace = synth.config4_trace(args.serve_requests, rate_per_s=200.0)
+        small = sorted(trace, key=lambda r: r.m)[:4]
+        times = []
+        for r in small:
+            q = r.problem()
+            t, L = default_parameters(q.soc_sizes)
+            t0 = time.perf_counter()
+            Algorithm2(q.scipy_csr(), q.b, q.c, q.n_orth, q.soc_sizes, mu=1.0, t=t, schedule=L).run(
+                20000, eps=1e-4, check_every=10, obj_stop=1.0)
+            times.append({"m": r.m, "kind": r.kind, "seconds": time.perf_counter() - t0})
+        out["serve"] = times
     from oracle.subspace import RangeProjector
 
     p = synth.config1(scale=args.scale)
@@ -142,7 +155,8 @@ def cpu_child(args):
 
 def start_cpu_baseline(args):
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--scale", str(args.scale),
-           "--cpu-iters", str(args.cpu_iters), "--workload", args.workload, "--count", str(args.count)]
+           "--cpu-iters", str(args.cpu_iters), "--workload", args.workload, "--count", str(args.count),
+           "--serve-requests", str(args.serve_requests)]
     if args.workload == "lp2m":
         cmd += ["--state-file", args.state_file] + (["--headline-only"] if args.headline_only else [])
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
@@ -173,6 +187,8 @@ def finish_cpu_baseline(proc, timeout_s=600):
         }
         if "lp200" in r:
             base["lp200"] = r["lp200"]
+        if "serve" in r:
+            base["serve_oracle"] = r["serve"]
         if "batch" in r:
             base["batch_solves_per_s"] = r["batch"]["solves"] / r["batch"]["seconds"]
             base["batch_sample"] = (f"{r['batch']['solves']} seeded instances of the batch recipe solved one at a "
@@ -384,6 +400,12 @@ def bench_lp2m(args, cpu_proc):
         if "lp200_fp64" in detail:
             detail["lp200_fp64"]["oracle"] = {"iterations": o["iters"], "solve_s": o["seconds"], "kkt": o["kkt"],
                                               "cores": 1, "what": "the FP64 oracle's whole solve, same rule"}
+    if cpu and "serve_oracle" in cpu:
+        o = cpu.pop("serve_oracle")
+        if "serve" in detail:
+            detail["serve"]["oracle_service_s"] = {
+                "requests": o, "cores": 1,
+                "what": "the FP64 oracle's whole solves of the trace's four smallest requests, one at a time"}
     if cpu and "batch_solves_per_s" in cpu and "batch4096" in detail:
         detail["batch4096"]["oracle_solves_per_s"] = cpu.pop("batch_solves_per_s")
         detail["batch4096"]["oracle_sample"] = cpu.pop("batch_sample") + " (1 core)"
