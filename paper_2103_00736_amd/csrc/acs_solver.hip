@@ -865,7 +865,10 @@ class Instance final : public InstanceBase {
   // layout, whose k_cg_t finalizes the step before it) from k_cg_a_one; there
   // the last step of a capped CG gets a k_fin_cg_a of its own.
   void run_cg(int it, int cg_max) {
-    const int chunk = 2;
+    // steps of n >= 2^20 take longer than the host's turnaround: one step in
+    // flight ahead keeps the GPU busy and launches about one step fewer after
+    // convergence (each a set of exit-at-once dispatches); smaller steps need two
+    const int chunk = d_.n >= (1 << 20) ? 1 : 2;
     const bool folded = cg_fin_folded(d_);
     int launched = 0;
     while (launched < cg_max) {
