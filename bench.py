@@ -391,6 +391,14 @@ def bench_lp2m(args, cpu_proc):
                                 "iterations": i0.iterations, "cg_steps": i0.cg_steps, "solve_s": i0.solve_ms * 1e-3,
                                 "first_solve_s": first.solve_ms * 1e-3, "kkt": i0.kkt,
                                 "objective_rel_error": abs(i0.pobj - q0.p_star) / (1 + abs(q0.p_star))}
+        # the same with ACS_PROJ_AUTO, which takes the direct projection at this m
+        acs.solve(h0, precision=acs.PREC_FP64, eps_kkt=1e-6, max_iter=20000, projection=acs.PROJ_AUTO)
+        i1 = acs.solve(h0, precision=acs.PREC_FP64, eps_kkt=1e-6, max_iter=20000, projection=acs.PROJ_AUTO)[3]
+        detail["lp200_fp64"]["projection_auto"] = {
+            "status": {acs.SOLVED: "solved"}.get(i1.status, f"status {i1.status}"), "iterations": i1.iterations,
+            "solve_s": i1.solve_ms * 1e-3, "kkt": i1.kkt,
+            "objective_rel_error": abs(i1.pobj - q0.p_star) / (1 + abs(q0.p_star)),
+            "what": "ACS_PROJ_AUTO: the direct projection (m <= 2048), second solve"}
         detail["socp1m"] = socp_section(acs, synth, args)
         detail["batch4096"] = batch_section(acs, synth, args.count)
         detail["serve"] = serve_section(acs, synth, args.serve_requests, 200.0, args.workers, args.small_nnz)

@@ -71,6 +71,12 @@ extern "C" {
                               rounding.  Needs m <= 32768 and m * n <= 2^31;
                               extra device memory: acs_problem_factor_bytes.
                               Single-instance paths only (not the batch kernel). */
+#define ACS_PROJ_AUTO 2    /* ACS_PROJ_FACTOR for m <= 2048, else ACS_PROJ_CG; the
+                              batch kernel takes it as ACS_PROJ_CG.  Measured
+                              whole solves on one MI355X: the 200 x 500 LP in
+                              FP64 10 ms against 87 ms by CG; serving-trace LPs
+                              with m = 1000 / 2000 10 / 16 ms against 27 / 34 ms,
+                              with m = 4000 52 ms against 40 ms. */
 
 /*
  * Settings (Alg. 2 Require line and Sec. V).  Call acs_settings_default()
@@ -132,7 +138,7 @@ typedef struct acs_settings {
   double cg_reduce;     /* stop CG once ||r|| <= cg_reduce * ||r_0|| (warm); 0 = per class */
   double cg_abs;        /* ... or once ||r|| <= cg_abs (scaled system)          */
   int32_t verbose;      /* 0 quiet, 1 one line per check on stderr              */
-  int32_t projection;   /* ACS_PROJ_CG (default) or ACS_PROJ_FACTOR              */
+  int32_t projection;   /* ACS_PROJ_CG (default), ACS_PROJ_FACTOR or ACS_PROJ_AUTO */
   int32_t obj_stop;     /* k > 0: a check also needs k * eps_obj <= eps_kkt (default 1); 0: KKT only */
   int32_t equilibrate;  /* 1: Sinkhorn-Knopp column scaling E first (Sec. III, below); 0 (default): none */
   int32_t eq_sweeps;    /* sweeps of that equilibration (default 25)              */

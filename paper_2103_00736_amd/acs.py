@@ -24,7 +24,7 @@ ACS_ERR_STATE = -5
 
 SOLVED, MAX_ITER, NUMERIC, CANCELLED = 0, 1, 2, 3
 PREC_MIXED, PREC_FP64 = 0, 1
-PROJ_CG, PROJ_FACTOR = 0, 1
+PROJ_CG, PROJ_FACTOR, PROJ_AUTO = 0, 1, 2
 
 # timing classes of acs_state_timing
 (KC_UPDATE, KC_RESID, KC_CG_T, KC_CG_A, KC_CONE, KC_CHECK, KC_COND, KC_FIN, KC_CG_COMB, KC_FAC_SYRK, KC_FAC_UPDATE,

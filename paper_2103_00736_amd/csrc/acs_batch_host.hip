@@ -229,7 +229,10 @@ class Batch {
     }
     const int count = int(probs_.size());
     settings_.resize(count);
-    for (int i = 0; i < count; ++i) settings_[i] = resolve_settings(s, *probs_[i]);
+    for (int i = 0; i < count; ++i) {
+      settings_[i] = resolve_settings(s, *probs_[i]);
+      settings_[i].projection = ACS_PROJ_CG;  // the kernel projects by CG (ACS_PROJ_AUTO included)
+    }
     layout_and_upload();
     // default schedules: LDS-staged row blocks of 1024 nonzeros
     g_.resize(count);
@@ -577,7 +580,8 @@ int acs_batch_create(int32_t count, const acs_problem* const* probs, const acs_s
   if (out) *out = nullptr;
   return guarded([&] {
     if (count < 1 || !probs || !s || !out) throw AcsError(ACS_ERR_ARG, "bad argument");
-    if (s->projection != ACS_PROJ_CG) throw AcsError(ACS_ERR_ARG, "the batch kernel projects by CG only");
+    if (s->projection != ACS_PROJ_CG && s->projection != ACS_PROJ_AUTO)
+      throw AcsError(ACS_ERR_ARG, "the batch kernel projects by CG only");
     if (s->equilibrate) throw AcsError(ACS_ERR_ARG, "the batch kernel does not equilibrate (acs_solve does)");
     std::vector<std::shared_ptr<const Problem>> v;
     v.reserve(count);
@@ -639,7 +643,8 @@ int acs_batch_solve(int32_t count, const acs_problem* const* probs, const acs_se
                     double* const* y, double* const* z, acs_info* infos, void* stream) {
   return guarded([&] {
     if (count < 1 || !probs || !s) throw AcsError(ACS_ERR_ARG, "bad argument");
-    if (s->projection != ACS_PROJ_CG) throw AcsError(ACS_ERR_ARG, "the batch kernel projects by CG only");
+    if (s->projection != ACS_PROJ_CG && s->projection != ACS_PROJ_AUTO)
+      throw AcsError(ACS_ERR_ARG, "the batch kernel projects by CG only");
     if (s->equilibrate) throw AcsError(ACS_ERR_ARG, "the batch kernel does not equilibrate (acs_solve does)");
     std::vector<std::shared_ptr<const Problem>> v;
     for (int i = 0; i < count; ++i) {

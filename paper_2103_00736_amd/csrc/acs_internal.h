@@ -24,6 +24,7 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kStageNnz = 2048;   // products staged in LDS per multi-row block
 constexpr int kSlices = 8;        // column slices of A, one per XCD
 constexpr int32_t kOneSliceMaxN = 262144;  // settings.a_slices = 0: one slice up to this n
+constexpr int32_t kAutoFactorMaxM = 2048;  // ACS_PROJ_AUTO: the direct projection up to this m
 // The iteration whose x, z feed a conditioning event (Alg. 2 steps 5-10 read
 // the x, z of the previous iteration) projects accurately: its CG runs to a
 // relative residual reduction of kEventCgReduce, with up to kEventCgMaxFactor

@@ -80,6 +80,7 @@ acs_settings resolve_settings(const acs_settings& in, const Problem& p) {
   if (s.max_iter < 0 || s.check_every < 1 || s.cg_max < 0 || s.obj_stop < 0)
     throw AcsError(ACS_ERR_ARG, "settings: bad counts");
   if (s.precision != ACS_PREC_MIXED && s.precision != ACS_PREC_FP64) throw AcsError(ACS_ERR_ARG, "settings: precision");
+  if (s.projection == ACS_PROJ_AUTO) s.projection = p.m <= kAutoFactorMaxM ? ACS_PROJ_FACTOR : ACS_PROJ_CG;
   if (s.projection != ACS_PROJ_CG && s.projection != ACS_PROJ_FACTOR) throw AcsError(ACS_ERR_ARG, "settings: projection");
   if ((s.equilibrate != 0 && s.equilibrate != 1) || s.eq_sweeps < 0)
     throw AcsError(ACS_ERR_ARG, "settings: equilibrate must be 0 or 1 and eq_sweeps >= 0");

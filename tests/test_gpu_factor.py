@@ -412,3 +412,31 @@ def test_factor_full_size_normal_equations(full_size_lp, prec):
           f"bars {bars[0]:.1e} {bars[1]:.1e}")
     assert res[0] <= bars[0] + 1e-8
     assert res[1] <= bars[1] + 1e-12
+
+
+def test_projection_auto_picks_by_m():
+    """ACS_PROJ_AUTO takes the direct projection for m <= 2048 and the CG
+    above: bitwise the explicit choice in each case; the batch kernel takes it
+    as CG."""
+    small = synth.config0()  # m = 200
+    large = synth.config1(scale=0.005)  # m = 2500
+    assert small.m <= 2048 < large.m
+    for p, explicit in ((small, acs.PROJ_FACTOR), (large, acs.PROJ_CG)):
+        h = acs.Problem.from_synth(p)
+        a = acs.solve(h, eps_kkt=1e-4, max_iter=20000, projection=acs.PROJ_AUTO)
+        b = acs.solve(h, eps_kkt=1e-4, max_iter=20000, projection=explicit)
+        assert a[3].status == acs.SOLVED and a[3].iterations == b[3].iterations, p.name
+        for u, v in zip(a[:3], b[:3]):
+            assert np.array_equal(u, v), p.name
+    probs = [synth.config3(i) for i in range(3)]
+    hs = [acs.Problem.from_synth(q) for q in probs]
+    res = []
+    for proj in (acs.PROJ_AUTO, acs.PROJ_CG):
+        bt = acs.Batch(hs, eps_kkt=1e-4, max_iter=20000, projection=proj)
+        bt.run(20000)
+        res.append([bt.result(i) for i in range(len(hs))])
+        bt.close()
+    for ra, rb in zip(*res):
+        assert ra[3].status == acs.SOLVED and ra[3].iterations == rb[3].iterations
+        for u, v in zip(ra[:3], rb[:3]):
+            assert np.array_equal(u, v)
