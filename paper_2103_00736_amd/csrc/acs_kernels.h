@@ -125,6 +125,12 @@ struct Dev {
   VT* st_val;
   double* sa_val64;
   double* st_val64;
+  // the CG's layouts, with the columns of A renumbered within each slice in
+  // the order sa first reads them, so its vector t is stored in that order:
+  // sa_cg is sa with the renumbered column array (values sa_val), st_cg the
+  // A_s^T layout with its rows in the new order and its own VT values
+  SellDev sa_cg, st_cg;
+  VT* st_cg_val;
   VT* part;                // kSlices x m partial row sums of A_s t
   double* part64;          // kSlices x m partial row sums of the FP64 residual
   const int32_t* row_perm; // internal row -> caller's row

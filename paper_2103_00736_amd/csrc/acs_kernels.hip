@@ -532,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_t(Dev<VT> d, int j, int rr_nb) {
     d.t[j] = tj;
     acc[0] += double(tj) * double(tj);
   };
-  sell_rows<VT, VT>(d.st, d.st_val, 0, blk, d.r, pre, epi);
+  sell_rows<VT, VT>(d.st_cg, d.st_cg_val, 0, blk, d.r, pre, epi);
   // one slice: the fused second half reads them while it writes d.partials
   block_store_partials<1>(acc, d.sa.slices == 1 ? d.partials2 : d.partials, blk);
 }
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_part(Dev<VT> d, int t_nb) {
   VT* __restrict__ part = d.part + size_t(x) * d.m;
   auto pre = [](int) -> VT { return VT(0); };
   auto epi = [&](int i, VT sum, VT) { part[i] = sum; };
-  sell_rows<VT, VT>(d.sa, d.sa_val, x, lb, d.t, pre, epi);
+  sell_rows<VT, VT>(d.sa_cg, d.sa_val, x, lb, d.t, pre, epi);
 }
 
 // CG update of row i given (M q)_i: q = r + beta q; w += alpha q; r -= alpha M q
@@ -632,12 +632,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_a_one(Dev<VT> d, int t_nb, long l
   double acc[1] = {0};
   auto pre = [](int) -> VT { return VT(0); };
   auto epi = [&](int i, VT mq, VT) { cg_row_update(d, i, mq, alpha, beta, valpha, vbeta, acc[0]); };
-  sell_rows<VT, VT>(d.sa, d.sa_val, 0, blk, d.t, pre, epi);
+  sell_rows<VT, VT>(d.sa_cg, d.sa_val, 0, blk, d.t, pre, epi);
   block_store_partials<1>(acc, d.partials, blk);
 }
 
 // values of a SELL layout from the FP64 A_s (padding entries hold 0), in VT
-// for the CG and in FP64 for the refinement sweeps (one array when VT = double)
+// for the CG and in FP64 for the refinement sweeps (one array when VT = double;
+// val64 == nullptr: VT values only)
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_sell_vals(const int32_t* __restrict__ src, int64_t count,
                                                       const double* __restrict__ a64, VT* __restrict__ val,
@@ -649,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_vals(const int32_t* __restrict_
       val64[e] = a;
     } else {
       val[e] = VT(a);
-      val64[e] = a;
+      if (val64) val64[e] = a;
     }
   }
 }
@@ -1513,7 +1514,7 @@ void launch_cg_t(const Dev<VT>& d, int j, hipStream_t st) {
                static_cast<const VT*>(nullptr), static_cast<VT*>(nullptr));
     return;
   }
-  ACS_LAUNCH((k_cg_t<VT>), dim3(d.st.wg[0]), dim3(kBlock), 0, st, d, cg_fin_folded(d) ? j : -1, rr_blocks(d));
+  ACS_LAUNCH((k_cg_t<VT>), dim3(d.st_cg.wg[0]), dim3(kBlock), 0, st, d, cg_fin_folded(d) ? j : -1, rr_blocks(d));
 }
 
 template <typename VT>
@@ -1524,10 +1525,10 @@ void launch_cg_a(const Dev<VT>& d, long long launch_id, hipStream_t st) {
     return;
   }
   if (d.sa.slices == 1) {  // the row product and the CG update of each row in one kernel
-    ACS_LAUNCH((k_cg_a_one<VT>), dim3(d.sa.wg[0]), dim3(kBlock), 0, st, d, d.st.wg[0], launch_id);
+    ACS_LAUNCH((k_cg_a_one<VT>), dim3(d.sa.wg[0]), dim3(kBlock), 0, st, d, d.st_cg.wg[0], launch_id);
     return;
   }
-  ACS_LAUNCH((k_cg_a_part<VT>), dim3(d.sa.slices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st.wg[0]);
+  ACS_LAUNCH((k_cg_a_part<VT>), dim3(d.sa.slices * d.sa.wg_max), dim3(kBlock), 0, st, d, d.st_cg.wg[0]);
 }
 
 template <typename VT>
@@ -1587,6 +1588,12 @@ void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
     const bool a = S == &d.sa;
     ACS_LAUNCH((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, S->src, S->entries, d.a_val64,
                        a ? d.sa_val : d.st_val, a ? d.sa_val64 : d.st_val64);
+  }
+  {  // the CG's A_s^T values (sa_cg shares sa's)
+    const int nb = int(std::max<int64_t>(1, std::min<int64_t>((d.st_cg.entries + kBlock - 1) / kBlock, 8192)));
+    double* v64 = sizeof(VT) == sizeof(double) ? reinterpret_cast<double*>(d.st_cg_val) : nullptr;
+    ACS_LAUNCH((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, d.st_cg.src, d.st_cg.entries, d.a_val64,
+               d.st_cg_val, v64);
   }
   ACS_LAUNCH((k_chat<VT>), dim3(ceil_div(d.n, kBlock)), dim3(kBlock), 0, st, d);
 }

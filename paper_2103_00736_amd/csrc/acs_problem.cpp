@@ -195,8 +195,35 @@ const SellPair& Problem::sell(int slices) const {
     }
     build_sell(rps, m, scol.data(), ssrc.data(), pads, &sp->a);
     build_sell({t_row_ptr.data()}, n, t_col.data(), t_perm.data(), {0}, &sp->t);
+    // the CG's column order: within each slice, columns in the order the A
+    // layout first reads them (padding entries aside), then the columns no
+    // entry reads; slice x keeps its columns and its index range [x*w, ...)
+    std::vector<int32_t> cinv(size_t(n), -1);
+    std::vector<int64_t> cursor(static_cast<size_t>(slices));
+    for (int x = 0; x < slices; ++x) cursor[size_t(x)] = int64_t(x) * w;
+    const Sell& A = sp->a;
+    for (size_t e = 0; e < A.col.size(); ++e) {
+      const int32_t c = A.col[e];
+      if (A.src[e] >= 0 && cinv[size_t(c)] < 0) cinv[size_t(c)] = int32_t(cursor[size_t(c / w)]++);
+    }
+    for (int32_t c = 0; c < n; ++c)
+      if (cinv[size_t(c)] < 0) cinv[size_t(c)] = int32_t(cursor[size_t(c / w)]++);
+    sp->cg_col.assign(size_t(n), 0);
+    for (int32_t c = 0; c < n; ++c) sp->cg_col[size_t(cinv[size_t(c)])] = c;
+    sp->a_cg_col.resize(A.col.size());
+    for (size_t e = 0; e < A.col.size(); ++e) sp->a_cg_col[e] = cinv[size_t(A.col[e])];
+    // A^T with its rows in the new order
+    std::vector<int32_t> nrp(size_t(n) + 1, 0), ncol(static_cast<size_t>(nnz)), nsrc(static_cast<size_t>(nnz));
+    for (int32_t j = 0; j < n; ++j) {
+      const int32_t c = sp->cg_col[size_t(j)];
+      const int32_t b = t_row_ptr[size_t(c)], len = t_row_ptr[size_t(c) + 1] - b;
+      nrp[size_t(j) + 1] = nrp[size_t(j)] + len;
+      std::copy(t_col.begin() + b, t_col.begin() + b + len, ncol.begin() + nrp[size_t(j)]);
+      std::copy(t_perm.begin() + b, t_perm.begin() + b + len, nsrc.begin() + nrp[size_t(j)]);
+    }
+    build_sell({nrp.data()}, n, ncol.data(), nsrc.data(), {0}, &sp->t_cg);
     std::string err;
-    if (!check_sell(sp->a, m, nnz, &err) || !check_sell(sp->t, n, nnz, &err))
+    if (!check_sell(sp->a, m, nnz, &err) || !check_sell(sp->t, n, nnz, &err) || !check_sell(sp->t_cg, n, nnz, &err))
       throw AcsError(ACS_ERR_DEVICE, "internal error in the SELL layout: " + err);
     sell_[which] = std::move(sp);
   });

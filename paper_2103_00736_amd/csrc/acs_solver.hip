@@ -288,16 +288,20 @@ static int64_t estimate_bytes(const Problem& p, int precision, int a_slices) {
   int64_t b = 0;
   b += 4 * (m + 1) + 4 * nnz + 8 * nnz + 8 * nnz;        // A pattern, original and FP64 scaled values
   const int64_t v64 = vt == 8 ? 0 : 8;                   // FP64 SELL values beside the VT ones
-  for (const Sell* S : {&sp.a, &sp.t})                   // SELL layouts: entries, tasks, chunk rows
-    b += (8 + vt + v64) * int64_t(S->col.size()) + 12 * int64_t(S->wt_ptr.size() + S->long_row.size()) +
+  for (const Sell* S : {&sp.a, &sp.t, &sp.t_cg}) {       // SELL layouts: entries, tasks, chunk rows
+    const int64_t per = S == &sp.t_cg ? 8 + vt : 8 + vt + v64;  // the CG's A^T: VT values only
+    b += per * int64_t(S->col.size()) + 12 * int64_t(S->wt_ptr.size() + S->long_row.size()) +
          4 * int64_t(S->chunk_row.size());
+  }
+  b += 4 * int64_t(sp.a_cg_col.size());                  // the CG's column numbers of the A layout
   b += (vt + 8) * slices * m + (4 + vt) * m;             // slice partials, row permutation, scratch
-  b += 8 * int64_t(sp.t.wg_max) + 256;                   // ||t||^2 partials of the one-slice CG
+  b += 8 * int64_t(sp.t_cg.wg_max) + 256;                // ||t||^2 partials of the one-slice CG
   b += 8 * int64_t(p.a_blocks.size());
   b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
-  const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max), size_t(sp.a.wg_max),
+  const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max),
+                                         size_t(sp.t_cg.wg_max), size_t(sp.a.wg_max),
                                          size_t(n / kBlock + 2)});
-  b += 8 * kMaxSums * int64_t(parts) + 8 * kBlock + 64 * 256;  // partials, per-array alignment
+  b += 8 * kMaxSums * int64_t(parts) + 8 * kBlock + 96 * 256;  // partials, per-array alignment
   return b;
 }
 
@@ -442,6 +446,14 @@ class Instance final : public InstanceBase {
       };
       sell_dev(sp.a, &d.sa);
       sell_dev(sp.t, &d.st);
+      sell_dev(sp.t_cg, &d.st_cg);
+      d.sa_cg = d.sa;
+      {
+        int32_t* c = arena_.alloc<int32_t>(std::max<size_t>(sp.a_cg_col.size(), 1));
+        if (!sp.a_cg_col.empty()) up(c, sp.a_cg_col);
+        d.sa_cg.col = c;
+      }
+      d.st_cg_val = arena_.alloc<VT>(std::max<size_t>(sp.t_cg.col.size(), 1));
       d.sa_val = arena_.alloc<VT>(std::max<size_t>(sp.a.col.size(), 1));
       d.st_val = arena_.alloc<VT>(std::max<size_t>(sp.t.col.size(), 1));
       if (sizeof(VT) == sizeof(double)) {
@@ -454,7 +466,7 @@ class Instance final : public InstanceBase {
       d.part = arena_.alloc<VT>(size_t(S.a_slices) * p.m);
       d.part64 = arena_.alloc<double>(size_t(S.a_slices) * p.m);
       // ||t||^2 partials of k_cg_t, read by the one-slice second half
-      d.partials2 = arena_.alloc<double>(std::max<size_t>(size_t(sp.t.wg_max), 1));
+      d.partials2 = arena_.alloc<double>(std::max<size_t>(size_t(sp.t_cg.wg_max), 1));
     }
   }
 
@@ -618,7 +630,7 @@ class Instance final : public InstanceBase {
     d.ounit = arena_.alloc<double>(size_t(p.n_orth) + p.soc_size.size());
     d.ctl = arena_.alloc<Ctl>(1);
     const size_t units = size_t(p.n_orth) + p.soc_size.size();
-    nparts_ = std::max<size_t>({p.a_blocks.size(), size_t(d.st.wg_max), size_t(d.sa.wg_max), units / kBlock + 1,
+    nparts_ = std::max<size_t>({p.a_blocks.size(), size_t(d.st.wg_max), size_t(d.st_cg.wg_max), size_t(d.sa.wg_max), units / kBlock + 1,
                                  p.soc_size.size() / 4 + 1, size_t(p.m) / kBlock + 1, size_t(p.n) / kBlock + 1,
                                  size_t(p.m) / 16 + 1, 1});
     d.partials = arena_.alloc<double>(nparts_ * kMaxSums);

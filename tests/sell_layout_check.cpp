@@ -140,6 +140,50 @@ static int check_case(const char* name, const Csr& A) {
           if (sa.a.col[e] / w != x) return std::printf("%s: entry outside slice %d\n", name, x), 1;
       }
     }
+    // the CG's column numbering: a permutation that keeps every column in its
+    // slice, numbered in the order of first reading by the A layout
+    if (int(sa.cg_col.size()) != A.n || sa.a_cg_col.size() != sa.a.col.size())
+      return std::printf("%s: CG numbering sizes (%d slices)\n", name, slices), 1;
+    std::vector<int> cinv(A.n, -1);
+    for (int j = 0; j < A.n; ++j) {
+      const int c = sa.cg_col[j];
+      if (c < 0 || c >= A.n || cinv[c] >= 0) return std::printf("%s: cg_col not a permutation\n", name), 1;
+      if (c / w != j / w) return std::printf("%s: cg_col leaves its slice\n", name), 1;
+      cinv[c] = j;
+    }
+    std::vector<int64_t> next(slices);
+    for (int x = 0; x < slices; ++x) next[x] = int64_t(x) * w;
+    std::vector<char> met(A.n, 0);
+    for (size_t e = 0; e < sa.a.col.size(); ++e) {
+      if (sa.a_cg_col[e] != cinv[sa.a.col[e]]) return std::printf("%s: a_cg_col entry %zu\n", name, e), 1;
+      const int c = sa.a.col[e];
+      if (sa.a.src[e] < 0 || met[c]) continue;
+      met[c] = 1;
+      if (cinv[c] != next[c / w]++) return std::printf("%s: column %d out of first-reading order\n", name, c), 1;
+    }
+    // the CG's products: A t with t in the new order, A^T r into the new order
+    Sell acg = sa.a;
+    acg.col = sa.a_cg_col;
+    std::vector<double> xn_cg(A.n);
+    for (int j = 0; j < A.n; ++j) xn_cg[j] = xn[sa.cg_col[j]];
+    part = sell_product(acg, A.m, vals_of(sa.a), xn_cg, &writes);
+    for (int i = 0; i < A.m; ++i) {
+      double s = 0;
+      for (int x = 0; x < slices; ++x) s += part[size_t(x) * A.m + i];
+      const int o = p.row_perm[i];
+      if (std::fabs(s - ax[o]) > 1e-12 * (ax_abs[o] + 1e-300))
+        return std::printf("%s: CG A t row %d (%d slices)\n", name, o, slices), 1;
+    }
+    std::vector<double> xm_i(A.m);
+    for (int i = 0; i < A.m; ++i) xm_i[i] = xm[p.row_perm[i]];
+    std::vector<double> tc = sell_product(sa.t_cg, A.n, vals_of(sa.t_cg), xm_i, &writes);
+    for (int wv : writes)
+      if (wv != 1) return std::printf("%s: CG A^T side output written %d times\n", name, wv), 1;
+    for (int j = 0; j < A.n; ++j) {
+      const int c = sa.cg_col[j];
+      if (std::fabs(tc[j] - atx[c]) > 1e-12 * (atx_abs[c] + 1e-300))
+        return std::printf("%s: CG A^T r col %d (%d slices)\n", name, c, slices), 1;
+    }
   }
   const SellPair& sp = p.sell(kSlices);
   // A^T x: input in internal order
