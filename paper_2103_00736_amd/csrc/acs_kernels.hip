@@ -1051,26 +1051,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_resid(Dev<VT> d, int nb, int ite
   }
 }
 
-// alpha = rho / ||t||^2 (||t||^2 = q^T A_s A_s^T q)
-template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_fin_cg_t(Dev<VT> d, int nb) {
-  if (d.ctl->done) return;
-  double t[1];
-  sum_partials<1>(d.partials, nb, t);
-  if (threadIdx.x == 0) {
-    Ctl* c = d.ctl;
-    const double tt = t[0];
-    if (tt > 0.0 && !isinf(tt)) {
-      c->alpha = c->rho / tt;
-    } else {
-      c->alpha = 0.0;
-      c->done = 1;
-      if (!(tt == tt)) host_post(&d.hs->numeric, 1);
-      host_post(&d.hs->cg_done_iter, c->iter);
-    }
-  }
-}
-
 // beta = ||r_new||^2 / rho, stop test, progress record for the host
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_fin_cg_a(Dev<VT> d, int nb, long long launch_id) {
