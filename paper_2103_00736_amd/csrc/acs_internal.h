@@ -73,13 +73,16 @@ struct Sell {
 struct SellPair {
   Sell a;  // A t, 1 or kSlices column slices of A (residual sweeps, plain products)
   Sell t;  // A^T r, one slice (update sweeps)
-  // The CG's products run with the columns of A renumbered within each slice
-  // in the order `a` first reads them (its entries in storage order), so the
-  // CG vector t lives in that order: a gather that comes first in a wave's
-  // reads lands next to its neighbours'.  a_cg_col is `a`'s column array in
-  // the new numbering (tasks, entries and values are `a`'s); t_cg is the A^T
-  // layout with its rows (columns of A) in the new order; cg_col[j'] is the
-  // column of A that new index j' stands for.
+  // With kSlices column slices the CG's products run with the columns of A
+  // renumbered within each slice in the order `a` first reads them (its
+  // entries in storage order), so the CG vector t lives in that order: a
+  // gather that comes first in a wave's reads lands next to its neighbours'.
+  // a_cg_col is `a`'s column array in the new numbering (tasks, entries and
+  // values are `a`'s); t_cg is the A^T layout with its rows (columns of A) in
+  // the new order; cg_col[j'] is the column of A that new index j' stands
+  // for.  With one slice (t small enough for the caches) the CG uses `a` and
+  // `t` and these stay empty (cg_own false).
+  bool cg_own = false;
   std::vector<int32_t> a_cg_col;
   Sell t_cg;
   std::vector<int32_t> cg_col;

@@ -125,10 +125,11 @@ struct Dev {
   VT* st_val;
   double* sa_val64;
   double* st_val64;
-  // the CG's layouts, with the columns of A renumbered within each slice in
-  // the order sa first reads them, so its vector t is stored in that order:
-  // sa_cg is sa with the renumbered column array (values sa_val), st_cg the
-  // A_s^T layout with its rows in the new order and its own VT values
+  // the CG's layouts: with 8 slices the columns of A are renumbered within
+  // each slice in the order sa first reads them, so the CG vector t is stored
+  // in that order: sa_cg is sa with the renumbered column array (values
+  // sa_val), st_cg the A_s^T layout with its rows in the new order and its
+  // own VT values.  With one slice they are sa, st and st_val themselves.
   SellDev sa_cg, st_cg;
   VT* st_cg_val;
   VT* part;                // kSlices x m partial row sums of A_s t

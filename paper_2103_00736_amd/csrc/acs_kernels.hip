@@ -1569,7 +1569,7 @@ void launch_rescale(const Dev<VT>& d, int wmode, hipStream_t st) {
     ACS_LAUNCH((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, S->src, S->entries, d.a_val64,
                        a ? d.sa_val : d.st_val, a ? d.sa_val64 : d.st_val64);
   }
-  {  // the CG's A_s^T values (sa_cg shares sa's)
+  if (d.st_cg_val != d.st_val) {  // the CG's own A_s^T values (sa_cg shares sa's)
     const int nb = int(std::max<int64_t>(1, std::min<int64_t>((d.st_cg.entries + kBlock - 1) / kBlock, 8192)));
     double* v64 = sizeof(VT) == sizeof(double) ? reinterpret_cast<double*>(d.st_cg_val) : nullptr;
     ACS_LAUNCH((k_sell_vals<VT>), dim3(nb), dim3(kBlock), 0, st, d.st_cg.src, d.st_cg.entries, d.a_val64,

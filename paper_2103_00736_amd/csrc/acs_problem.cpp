@@ -195,9 +195,17 @@ const SellPair& Problem::sell(int slices) const {
     }
     build_sell(rps, m, scol.data(), ssrc.data(), pads, &sp->a);
     build_sell({t_row_ptr.data()}, n, t_col.data(), t_perm.data(), {0}, &sp->t);
+    std::string err;
+    if (!check_sell(sp->a, m, nnz, &err) || !check_sell(sp->t, n, nnz, &err))
+      throw AcsError(ACS_ERR_DEVICE, "internal error in the SELL layout: " + err);
+    if (slices == 1) {
+      sell_[which] = std::move(sp);
+      return;
+    }
     // the CG's column order: within each slice, columns in the order the A
     // layout first reads them (padding entries aside), then the columns no
     // entry reads; slice x keeps its columns and its index range [x*w, ...)
+    sp->cg_own = true;
     std::vector<int32_t> cinv(size_t(n), -1);
     std::vector<int64_t> cursor(static_cast<size_t>(slices));
     for (int x = 0; x < slices; ++x) cursor[size_t(x)] = int64_t(x) * w;
@@ -222,8 +230,7 @@ const SellPair& Problem::sell(int slices) const {
       std::copy(t_perm.begin() + b, t_perm.begin() + b + len, nsrc.begin() + nrp[size_t(j)]);
     }
     build_sell({nrp.data()}, n, ncol.data(), nsrc.data(), {0}, &sp->t_cg);
-    std::string err;
-    if (!check_sell(sp->a, m, nnz, &err) || !check_sell(sp->t, n, nnz, &err) || !check_sell(sp->t_cg, n, nnz, &err))
+    if (!check_sell(sp->t_cg, n, nnz, &err))
       throw AcsError(ACS_ERR_DEVICE, "internal error in the SELL layout: " + err);
     sell_[which] = std::move(sp);
   });

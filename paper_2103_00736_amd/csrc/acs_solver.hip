@@ -294,8 +294,9 @@ static int64_t estimate_bytes(const Problem& p, int precision, int a_slices) {
          4 * int64_t(S->chunk_row.size());
   }
   b += 4 * int64_t(sp.a_cg_col.size());                  // the CG's column numbers of the A layout
+  // (the CG's own layouts are empty with one slice)
   b += (vt + 8) * slices * m + (4 + vt) * m;             // slice partials, row permutation, scratch
-  b += 8 * int64_t(sp.t_cg.wg_max) + 256;                // ||t||^2 partials of the one-slice CG
+  b += 8 * int64_t(std::max(sp.t.wg_max, sp.t_cg.wg_max)) + 256;  // ||t||^2 partials of the one-slice CG
   b += 8 * int64_t(p.a_blocks.size());
   b += n * (3 * vt + 8 * 10) + m * (3 * vt + 8 * 7);
   const size_t parts = std::max<size_t>({p.a_blocks.size(), p.t_blocks.size(), size_t(sp.t.wg_max),
@@ -446,14 +447,6 @@ class Instance final : public InstanceBase {
       };
       sell_dev(sp.a, &d.sa);
       sell_dev(sp.t, &d.st);
-      sell_dev(sp.t_cg, &d.st_cg);
-      d.sa_cg = d.sa;
-      {
-        int32_t* c = arena_.alloc<int32_t>(std::max<size_t>(sp.a_cg_col.size(), 1));
-        if (!sp.a_cg_col.empty()) up(c, sp.a_cg_col);
-        d.sa_cg.col = c;
-      }
-      d.st_cg_val = arena_.alloc<VT>(std::max<size_t>(sp.t_cg.col.size(), 1));
       d.sa_val = arena_.alloc<VT>(std::max<size_t>(sp.a.col.size(), 1));
       d.st_val = arena_.alloc<VT>(std::max<size_t>(sp.t.col.size(), 1));
       if (sizeof(VT) == sizeof(double)) {
@@ -463,10 +456,24 @@ class Instance final : public InstanceBase {
         d.sa_val64 = arena_.alloc<double>(std::max<size_t>(sp.a.col.size(), 1));
         d.st_val64 = arena_.alloc<double>(std::max<size_t>(sp.t.col.size(), 1));
       }
+      // the CG's layouts (after the value arrays: with one slice they alias them)
+      d.sa_cg = d.sa;
+      if (sp.cg_own) {  // renumbered columns
+        sell_dev(sp.t_cg, &d.st_cg);
+        int32_t* c = arena_.alloc<int32_t>(std::max<size_t>(sp.a_cg_col.size(), 1));
+        if (!sp.a_cg_col.empty()) up(c, sp.a_cg_col);
+        d.sa_cg.col = c;
+        d.st_cg_val = arena_.alloc<VT>(std::max<size_t>(sp.t_cg.col.size(), 1));
+      } else {
+        d.st_cg = d.st;
+        d.st_cg_val = d.st_val;
+      }
+      if (!d.sa_val || !d.st_val || !d.st_cg_val || !d.sa_cg.col || !d.st_cg.col)
+        throw AcsError(ACS_ERR_DEVICE, "internal error: a SELL array of the CG is unset");
       d.part = arena_.alloc<VT>(size_t(S.a_slices) * p.m);
       d.part64 = arena_.alloc<double>(size_t(S.a_slices) * p.m);
       // ||t||^2 partials of k_cg_t, read by the one-slice second half
-      d.partials2 = arena_.alloc<double>(std::max<size_t>(size_t(sp.t_cg.wg_max), 1));
+      d.partials2 = arena_.alloc<double>(std::max<size_t>(size_t(d.st_cg.wg_max), 1));
     }
   }
 

@@ -153,9 +153,10 @@ def test_conditioning_event_parity(name):
 # The row-scaled power-law LP (row scales 10^+-3) gets column scales E that
 # span about 1e9: the FP32 CG of the mixed path then sits at the edge of what
 # its refinement can recover, and whether the solve converges within 20000
-# iterations turns on the last bits of ||t||^2 (13300 iterations with one
-# summation order, a stall near KKT 5e-2 with another).  That case runs the
-# FP64 path (about 3800 iterations with either order); the SOCP the mixed one.
+# iterations turns on the last bits of ||t||^2 (10740 iterations on 8 column
+# slices with one summation order, a stall near KKT 1e-1 with another).  That
+# case runs the FP64 path (about 3800 iterations with either order); the SOCP
+# the mixed one.
 @pytest.mark.parametrize("name,precision", [("lp_powerlaw", acs.PREC_FP64), ("socp", acs.PREC_MIXED)])
 def test_equilibrated_solve(name, precision):
     p = PROBLEMS[name]()
