@@ -873,6 +873,7 @@ def _serve_run(acs, srv_kw, trace, handles, arrivals, warm):
     """Submit every request at its arrival time (a client thread) and wait for all."""
     srv = acs.Server(**srv_kw)
     tickets = [None] * len(trace)
+    lag = np.zeros(len(trace))  # arrival -> call of submit (the client was still in an earlier submit)
     start = time.perf_counter()
 
     def client():
@@ -880,6 +881,7 @@ def _serve_run(acs, srv_kw, trace, handles, arrivals, warm):
             delay = start + arrivals[i] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
+            lag[i] = max(0.0, time.perf_counter() - (start + arrivals[i]))
             tickets[i] = srv.submit(handles[i], eps_kkt=1e-4, max_iter=20000)
 
     th = threading.Thread(target=client)
@@ -892,12 +894,17 @@ def _serve_run(acs, srv_kw, trace, handles, arrivals, warm):
     end = time.perf_counter()
     st = srv.stats()
     srv.close()
-    lat = np.array([f.latency_ms for f in res[warm:]])
+    srv_lat = np.array([f.latency_ms for f in res[warm:]])
+    lat = srv_lat + 1e3 * lag[warm:]
     queue = np.array([f.queue_ms for f in res[warm:]])
     half = len(lat) // 2
     return {"requests": len(res), "warmup_excluded": warm,
             "offered_rate": (len(trace) - 1) / max(arrivals[-1], 1e-9), "solves_per_s": len(res) / (end - start),
             "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+            "latency_from": "the request's arrival time: the client's lag before submit (still inside an earlier "
+                            "submit) plus the server's latency from the entry of submit to the result",
+            "p50_p99_server_latency_ms": [float(np.percentile(srv_lat, 50)), float(np.percentile(srv_lat, 99))],
+            "mean_client_lag_ms": float(1e3 * np.mean(lag[warm:])),
             "mean_queue_ms": float(np.mean(queue)),
             "queue_ms_first_half_vs_second_half": [float(np.mean(queue[:half])), float(np.mean(queue[half:]))],
             "solved": sum(1 for f in res if f.status == acs.SOLVED), "makespan_s": end - start,

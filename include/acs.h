@@ -171,8 +171,8 @@ typedef struct acs_info {
   double setup_ms;      /* upload + setup                                      */
   double alpha;         /* exponent of the last conditioning (step 11)         */
   double o_range;       /* log(max O) - log(min O) after the last conditioning */
-  double queue_ms;      /* server: submit -> admission                         */
-  double latency_ms;    /* server: submit -> result ready                      */
+  double queue_ms;      /* server: entry of submit -> admission                */
+  double latency_ms;    /* server: entry of submit (layout build included) -> result ready */
   double eps_obj;       /* objective-error estimate of the last check (above)  */
   double reserved[3];
 } acs_info;
@@ -400,7 +400,11 @@ int acs_server_create(int64_t hbm_budget, int32_t max_slots, int64_t small_nnz, 
                       acs_server** out);
 /* Stops the loop; unfinished requests are dropped. */
 void acs_server_destroy(acs_server* srv);
-/* Queue a solve of p (the problem handle may be destroyed afterwards). */
+/* Queue a solve of p (the problem handle may be destroyed afterwards).  A
+ * request for the worker streams first has its device layouts built (on host
+ * threads, once per problem handle) to size it against the budget, so on a
+ * handle's first submit the call takes time that grows with nnz; the
+ * request's latency_ms counts from the entry of this call. */
 int acs_server_submit(acs_server* srv, const acs_problem* p, const acs_settings* s, uint64_t* ticket);
 /* ACS_PENDING while unfinished; ACS_OK copies x, z (n), y (m) and info (any
  * may be NULL) and releases the ticket. */

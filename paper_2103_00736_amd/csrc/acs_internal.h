@@ -40,6 +40,7 @@ constexpr int kSellChunk = 64;    // rows per SELL chunk (one per lane of a wave
 constexpr int kSellMaxLen = 64;   // longest row packed into a chunk
 constexpr int kWaveRowMax = 2048; // longest row given to one wave; longer rows get a workgroup
 constexpr int kSellWindow = 16384; // rows sorted by length within windows of this many rows
+constexpr int kHostThreads = 16;  // host threads that build the layouts of one large problem
 
 // SELL-64 layout of the products of the CG (each output row is a dot product
 // of a sparse row with a gathered vector).  The rows are split into slices

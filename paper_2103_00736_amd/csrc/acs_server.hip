@@ -103,6 +103,7 @@ class Server {
 
   uint64_t submit(std::shared_ptr<const Problem> p, const acs_settings& s) {
     auto r = std::make_shared<Request>();
+    r->t_submit = Clock::now();  // the latency includes the layout build below
     r->p = std::move(p);
     r->s = resolve_settings(s, *r->p);
     // dense requests and those asking for the direct projection or the
@@ -112,7 +113,6 @@ class Server {
                         : instance_device_bytes(*r->p, r->s.precision, r->s.projection, r->s.equilibrate,
                                                 r->s.a_slices);
     if (r->bytes > budget_) throw AcsError(ACS_ERR_NOMEM, "request needs more device memory than the server budget");
-    r->t_submit = Clock::now();
     {
       std::lock_guard<std::mutex> lk(mu_);
       if (stop_) throw AcsError(ACS_ERR_STATE, "server is shutting down");

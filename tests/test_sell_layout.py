@@ -42,3 +42,21 @@ def test_sell_layout_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-4000:]
     assert "runtime error" not in out.stderr and "AddressSanitizer" not in out.stderr, out.stderr[-4000:]
     assert out.stdout.strip().endswith("ok")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_sell_layout_under_thread_sanitizer(tmp_path):
+    """The layouts of large problems are built on several host threads (each
+    writing only the rows, columns or entries it owns): the same checks built
+    with ThreadSanitizer (host code only, g++; any data race aborts)."""
+    exe = tmp_path / "sell_check_tsan"
+    src = [os.path.join(ROOT, "tests", "sell_layout_check.cpp"),
+           os.path.join(ROOT, "paper_2103_00736_amd", "csrc", "acs_problem.cpp")]
+    flags = ["-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-fsanitize=thread", "-pthread"]
+    subprocess.run(["g++", *flags, "-o", str(exe)] + src, check=True)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1:abort_on_error=0")
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=900, env=env)
+    print(out.stdout[-2000:])
+    assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-4000:]
+    assert "ThreadSanitizer" not in out.stderr, out.stderr[-4000:]
+    assert out.stdout.strip().endswith("ok")
