@@ -194,6 +194,10 @@ void acs_settings_default(acs_settings* s);
  * row_ptr[m] = nnz; 0 <= col < n, strictly ascending in a row; finite val,
  * b, c; n_orth >= 0, soc sizes >= 1, n_orth + sum(soc) = n.  Failure:
  * ACS_ERR_ARG and *out = NULL.  Pure host code: valid without a GPU.
+ * A problem with m + nnz >= 2^18 is built, and later its device layouts, on
+ * up to 16 host threads (fewer on smaller machines; the environment variable
+ * ACS_HOST_THREADS, read once, caps them further).  The result does not
+ * depend on the number of threads.
  */
 int acs_problem_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                        const double* val, const double* b, const double* c, int32_t n_orth, int32_t n_soc,

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <exception>
 #include <mutex>
 #include <sstream>
@@ -12,13 +13,24 @@
 
 namespace acs {
 
-// fn(i) for i in [0, count), on up to kHostThreads threads when `big` (else
-// inline); each i must write only what it owns.  Fewer threads when the
+// fn(i) for i in [0, count), on up to host_threads() threads when `big`
+// (else inline); each i must write only what it owns.  Fewer threads when the
 // system refuses more; the first exception is rethrown after the join.
+static int64_t host_threads() {  // kHostThreads, the machine's, or ACS_HOST_THREADS if smaller
+  static const int64_t n = [] {
+    int64_t t = std::min<int64_t>(kHostThreads, std::max<int64_t>(1, int64_t(std::thread::hardware_concurrency())));
+    if (const char* e = std::getenv("ACS_HOST_THREADS")) {
+      const long v = std::strtol(e, nullptr, 10);
+      if (v >= 1) t = std::min<int64_t>(t, v);
+    }
+    return t;
+  }();
+  return n;
+}
+
 template <class F>
 static void parallel_for(int64_t count, bool big, F&& fn) {
-  const int64_t hw = std::max<int64_t>(1, int64_t(std::thread::hardware_concurrency()));
-  const int64_t want = big ? std::min<int64_t>({hw, int64_t(kHostThreads), count}) : 1;
+  const int64_t want = big ? std::min<int64_t>(host_threads(), count) : 1;
   if (want <= 1) {
     for (int64_t i = 0; i < count; ++i) fn(i);
     return;
@@ -192,8 +204,7 @@ bool build_problem(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, co
   // transpose pattern by counting sort over columns (columns ascending in A^T rows = rows of A);
   // each host thread owns a range of columns and scans every entry, so each A^T row is filled
   // by one thread in row order
-  const int64_t hw = std::max<int64_t>(1, int64_t(std::thread::hardware_concurrency()));
-  const int64_t ranges = big ? std::min<int64_t>({hw, int64_t(kHostThreads), int64_t(n)}) : 1;
+  const int64_t ranges = big ? std::min<int64_t>(host_threads(), int64_t(n)) : 1;
   const int64_t cw = (int64_t(n) + ranges - 1) / ranges;
   p.t_row_ptr.assign(size_t(n) + 1, 0);
   parallel_for(ranges, big, [&](int64_t r) {

@@ -4,7 +4,9 @@
 // (long rows by workgroup, wave rows, 64-row chunks, every slice and task
 // index the kernels visit) and compares the two products with plain CSR sums
 // of the caller's matrix.  Prints one line per case and "ok" at the end;
-// exits non-zero on the first mismatch.
+// exits non-zero on the first mismatch.  A "hash" line per case digests
+// every array the build produced (to compare builds on different numbers of
+// host threads).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -205,6 +207,37 @@ static int check_case(const char* name, const Csr& A) {
   std::printf("%s: m=%d n=%d nnz=%zu stored A %.3fx A^T %.3fx long %zu/%zu wave tasks %zu/%zu\n", name, A.m, A.n,
               A.col.size(), pad_a, pad_t, sp.a.long_row.size(), sp.t.long_row.size(), sp.a.wt_ptr.size(),
               sp.t.wt_ptr.size());
+  // FNV-1a over everything the problem build and both layouts produced, so
+  // that builds on different numbers of host threads can be compared
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const std::vector<int32_t>& v) {
+    for (int32_t x : v) {
+      h ^= uint32_t(x);
+      h *= 1099511628211ull;
+    }
+    h ^= v.size();
+    h *= 1099511628211ull;
+  };
+  auto mix_sell = [&](const Sell& S) {
+    for (const auto* v : {&S.long_off, &S.long_row, &S.long_beg, &S.long_end, &S.wt_off, &S.wt_ptr, &S.wt_len,
+                          &S.wt_row, &S.chunk_row, &S.col, &S.src, &S.wg})
+      mix(*v);
+  };
+  mix(p.row_perm);
+  mix(p.row_ptr);
+  mix(p.col);
+  mix(p.t_row_ptr);
+  mix(p.t_col);
+  mix(p.t_perm);
+  for (const int slices : {1, kSlices}) {
+    const SellPair& q = p.sell(slices);
+    mix_sell(q.a);
+    mix_sell(q.t);
+    mix_sell(q.t_cg);
+    mix(q.a_cg_col);
+    mix(q.cg_col);
+  }
+  std::printf("hash %s %016llx\n", name, (unsigned long long)h);
   return 0;
 }
 

@@ -60,3 +60,22 @@ def test_sell_layout_under_thread_sanitizer(tmp_path):
     assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-4000:]
     assert "ThreadSanitizer" not in out.stderr, out.stderr[-4000:]
     assert out.stdout.strip().endswith("ok")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_layouts_do_not_depend_on_the_number_of_host_threads(tmp_path):
+    """Problem creation and the layouts of large problems are split over host
+    threads (at most ACS_HOST_THREADS): one thread and several must build the
+    same arrays, bit for bit."""
+    exe = tmp_path / "sell_check_threads"
+    src = [os.path.join(ROOT, "tests", "sell_layout_check.cpp"),
+           os.path.join(ROOT, "paper_2103_00736_amd", "csrc", "acs_problem.cpp")]
+    subprocess.run(["g++", "-O2", "-std=c++17", "-pthread", "-o", str(exe)] + src, check=True)
+    hashes = {}
+    for threads in ("1", "3", "8"):
+        out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300,
+                             env=dict(os.environ, ACS_HOST_THREADS=threads))
+        assert out.returncode == 0, out.stdout + out.stderr
+        hashes[threads] = [l for l in out.stdout.splitlines() if l.startswith("hash ")]
+        assert len(hashes[threads]) == 5, out.stdout
+    assert hashes["1"] == hashes["3"] == hashes["8"], hashes
