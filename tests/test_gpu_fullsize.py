@@ -180,7 +180,10 @@ def _edge_problem(seed=3):
 
 
 @pytest.mark.parametrize("prec", [acs.PREC_FP64, acs.PREC_MIXED])
-def test_edge_case_iteration_parity(prec):
+@pytest.mark.parametrize("slices", [1, 8])
+def test_edge_case_iteration_parity(prec, slices):
+    """One iteration on the edge problem against the oracle, on both layouts
+    (with 8 column slices the CG runs on its renumbered columns)."""
     p = _edge_problem()
     t, L = default_parameters(p.soc_sizes)
     alg = Algorithm2(p.scipy_csr(), p.b, p.c, p.n_orth, p.soc_sizes, mu=1.0, t=t, schedule=L)
@@ -192,7 +195,7 @@ def test_edge_case_iteration_parity(prec):
         s_prev = s_prev.astype(np.float32).astype(np.float64)
         s = s.astype(np.float32).astype(np.float64)
     st = acs.State(acs.Problem.from_synth(p), precision=prec, cg_max=3000,
-                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7)
+                   cg_reduce=1e-13 if prec == acs.PREC_FP64 else 1e-7, a_slices=slices)
     st.set(alg.l, s_prev, s, alg.O, -alg.dual_multiplier())
     st.step(1)
     g = st.get()
@@ -200,8 +203,8 @@ def test_edge_case_iteration_parity(prec):
     tol = 1e-9 if prec == acs.PREC_FP64 else 1e-5
     for k in ("s", "x", "z"):
         err = np.linalg.norm(g[k] - ref[k]) / np.linalg.norm(ref[k])
-        print(k, f"{err:.2e}")
-        assert err <= tol, k
+        print(k, slices, f"{err:.2e}")
+        assert err <= tol, (k, slices)
 
 
 def test_edge_case_solve():
