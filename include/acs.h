@@ -118,8 +118,8 @@ extern "C" {
  * vector of one slice stays in that XCD's L2, and a second launch adds the
  * 8 partial sums of every row (and applies the CG update); the CG's own
  * vector is stored with each slice's columns in the order the layout first
- * reads them, on two more layouts (about 16 bytes per nonzero in device
- * memory, counted by acs_problem_device_bytes).  With 1 slice a
+ * reads them, on two more layouts (16 bytes per nonzero of device memory in
+ * mixed precision, 20 in FP64; acs_problem_device_bytes counts them).  With 1 slice a
  * workgroup sums whole rows and applies the CG update itself: one launch
  * fewer per CG step and per outer iteration, for problems whose gathered
  * vector fits every L2.  0 picks 1 slice for n <= 262144, else 8.  The two
