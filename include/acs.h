@@ -110,7 +110,10 @@ extern "C" {
  * preconditioned problem with its own O on top; in the original variables
  * that is the column scaling E O_hat, with the ratio of steps 5-10 taken from
  * x_hat, z_hat.  D drops out (neither range((D A E)^T) nor the affine set
- * depends on it), and results are returned in the original variables.
+ * depends on it), and results are returned in the original variables.  On
+ * badly row-scaled problems E can span many decades (about 1e9 on a power-law
+ * LP with row scales 1e+-3), where the FP32 CG of ACS_PREC_MIXED may stall
+ * short of the tolerance; use ACS_PREC_FP64 with equilibration there.
  */
 /*
  * Layout of the sparse products with A_s (a_slices).  With 8 slices each of
